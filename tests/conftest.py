@@ -1,0 +1,25 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _built_helpers():
+    """The fixture and oracle libraries are plain gcc builds; make sure they
+    exist (the GPU library is built by __graft_entry__.build())."""
+    import oracle
+    import workloads
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+        oracle.build(force=True)
+    if not os.path.exists(os.path.join(ROOT, "workloads", "libgbuf.so")):
+        workloads.build(force=True)
+    yield
