@@ -1,0 +1,220 @@
+/*
+ * ocr.h -- C-ABI of the MI355X (gfx950) occlusion-point-reuse library.
+ *
+ * The library computes, per pixel of a G-buffer, radius-limited ambient
+ * occlusion (Sec. 3.2, Eq. ao-hemisphere) or normalised rectangular-light
+ * shadow visibility (Sec. 3.3, Eq. shadow-area) with one traced ray per
+ * pixel and sample, and reuses neighbouring pixels' first-hit occluders
+ * through the occluder-domain MIS estimators of Sec. 4 (Eqs.
+ * ao-unbiased-estimator, ao-biased-estimator, shadow-estimator,
+ * shadow-biased-estimator).
+ *
+ * Conventions common to every entry point:
+ *   - Pointers marked "device" must be HIP device memory (hipMalloc or a
+ *     torch CUDA tensor's data_ptr) on the current device; "host" pointers
+ *     are ordinary host memory.  The caller owns every buffer it passes.
+ *   - Per-frame calls only enqueue work on `stream` (a hipStream_t, NULL =
+ *     the null stream).  They allocate nothing and never synchronise; the
+ *     caller keeps buffers alive until the stream has passed the call.
+ *   - Every call returns an ocr_status; on error the outputs are undefined
+ *     and ocr_last_error() returns a thread-local description.  Nothing is
+ *     thrown across the ABI.
+ *   - Pixel arrays are row-major [height][width]; 3-vectors are interleaved
+ *     float[height][width][3].  Row 0 is the top row.
+ *   - Given the same inputs and seed every call produces bitwise identical
+ *     outputs.
+ */
+#ifndef OCR_H
+#define OCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ocr_status;
+enum {
+    OCR_OK = 0,
+    OCR_ERR_INVALID_ARG = -1, /* a pointer, size or parameter is out of range */
+    OCR_ERR_OOM = -2,         /* a library-owned allocation failed */
+    OCR_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+    OCR_ERR_UNSUPPORTED = -4, /* a valid request this build does not implement */
+    OCR_ERR_BUDGET = -5,      /* a server request can never fit its memory budget */
+    OCR_ERR_BUSY = -6         /* a server queue is full; retry later */
+};
+
+/* effect */
+enum { OCR_AO = 0, OCR_SHADOW = 1 };
+/* estimator: no reuse (Eqs. ao-mc-estimator / shadow-mc-estimator), biased
+ * reuse (local first-hit consistency), unbiased reuse (first-hit validation) */
+enum { OCR_NOREUSE = 0, OCR_BIASED = 1, OCR_UNBIASED = 2 };
+/* reuse set S(i) of a target pixel i (Sec. 4.2, Eq. reuse-group):
+ * OCR_WINDOW = the (2r+1)^2 pixels within Chebyshev distance r, clipped to
+ * the image; OCR_GROUP = the fixed image-aligned group of N pixels holding i
+ * (N = 1, 2, 4, 8 as 1x1, 2x1, 2x2, 4x2 tiles).  Background pixels are never
+ * members. */
+enum { OCR_WINDOW = 0, OCR_GROUP = 1 };
+
+/* hit codes of an occluder record */
+#define OCR_HIT_MISS 0xFFFFFFFFu /* no occluder within the support (or background pixel) */
+#define OCR_HIT_SELF 0xFFFFFFFEu /* shadow sample behind the receiver's tangent plane, or
+                                    receiver behind the light's emitting face: not traced */
+
+/* Shading points (Sec. 3.1 notation: x and n_x per pixel).
+ * pos, nrm: device float[h][w][3]; prim: device uint32[h][w], the triangle
+ * index the pixel lies on, or 0xFFFFFFFF for background.  nrm is the unit
+ * geometric normal facing the camera. */
+typedef struct {
+    const float *pos;
+    const float *nrm;
+    const uint32_t *prim;
+    int32_t width, height;
+} ocr_gbuffer;
+
+/* One-sided rectangular emitter (uniform area sampling, Eq.
+ * shadow-light-pdf): the rectangle c + a e_u + b e_v, |a|,|b| <= 1/2, emitting
+ * towards normalize(e_u x e_v).  e_u and e_v must be orthogonal. */
+typedef struct {
+    float center[3];
+    float edge_u[3];
+    float edge_v[3];
+} ocr_rect_light;
+
+/* First-hit occluder records (App. D / App. H, step 1), device buffers the
+ * caller allocates:
+ *   dz:  float[h][w][3]  hit point minus the ray origin o (o = x + eps n with
+ *        eps = 2^-16 (1 + max_c |x_c|)), so z = o + dz;
+ *   nz:  float[h][w][3]  unit geometric normal of the hit triangle, oriented
+ *        towards the ray origin;
+ *   hit: uint32[h][w]    index of the hit triangle in the scene's triangle
+ *        array, or OCR_HIT_MISS / OCR_HIT_SELF.
+ * dz and nz are written only where hit is a triangle index. */
+typedef struct {
+    float *dz;
+    float *nz;
+    uint32_t *hit;
+} ocr_occluders;
+
+/* Reuse configuration.
+ *   pattern:    OCR_WINDOW or OCR_GROUP
+ *   radius:     window radius r, 0..8 (OCR_WINDOW)
+ *   group_n:    1, 2, 4 or 8 (OCR_GROUP)
+ *   estimator:  OCR_NOREUSE, OCR_BIASED or OCR_UNBIASED
+ *   dark_guard: biased shadows only: a target whose reuse set holds no
+ *               unblocked sample gets 0 (Sec. 4.4)
+ *   accumulate: 0 = write the estimate, 1 = add it to the output (sample
+ *               accumulation; see ocr_scale) */
+typedef struct {
+    int32_t pattern;
+    int32_t radius;
+    int32_t group_n;
+    int32_t estimator;
+    int32_t dark_guard;
+    int32_t accumulate;
+} ocr_reuse_params;
+
+/* Library-owned acceleration structure over a triangle scene. */
+typedef struct ocr_bvh ocr_bvh;
+
+typedef struct {
+    int64_t ntris;      /* triangles in the scene */
+    int64_t nnodes;     /* 4-wide interior nodes */
+    int32_t depth;      /* levels of 4-wide nodes */
+    int32_t max_leaf;   /* largest leaf (triangles) */
+    int64_t device_bytes;
+    double build_ms;    /* host build time */
+} ocr_bvh_info;
+
+/* Build a 4-wide SAH bounding-volume hierarchy over a triangle scene and
+ * upload it to the current device.  (The paper relies on a hardware
+ * acceleration structure, Sec. 5; CDNA4 has no ray-tracing units, so the
+ * library builds its own.)
+ *   verts: host float[nverts][3]; tris: host uint32[ntris][3] vertex
+ *   indices, each < nverts.  Triangle index t is its row in `tris`.
+ *   stream: the upload is ordered on it and waited for before returning.
+ * Synchronous.  Errors: OCR_ERR_INVALID_ARG (null pointers, nverts < 1,
+ * ntris < 1 or >= 2^27, index out of range), OCR_ERR_OOM, OCR_ERR_HIP. */
+ocr_status ocr_build_bvh(const float *verts, int64_t nverts, const uint32_t *tris, int64_t ntris,
+                         void *stream, ocr_bvh **out);
+ocr_status ocr_bvh_free(ocr_bvh *bvh);
+ocr_status ocr_bvh_get_info(const ocr_bvh *bvh, ocr_bvh_info *info);
+
+/* Step 1 of App. D (AO) / App. H (shadow): one sample per valid pixel with
+ * the counter-based hash pcg4d(px, py, sample, seed32 + a*0x9E3779B9)
+ * (Jarzynski and Olano, JCGT 2020; seed32 = low ^ high word of seed), then a
+ * closest-hit trace:
+ *   AO (mode OCR_AO): cosine-weighted direction (Eq. ao-direction-pdf, by
+ *     Malley's method in the basis of Duff et al., JCGT 2017), ray
+ *     t in (0, ao_radius];
+ *   shadow (OCR_SHADOW): uniform light point y (Eq. shadow-light-pdf),
+ *     segment o -> y, t in (0, 1); not traced (OCR_HIT_SELF) when y is
+ *     behind the receiver's tangent plane or the receiver is behind the
+ *     light's emitting face.
+ * The receiver's own triangle (prim) is never hit.  light is NULL for AO.
+ * Errors: OCR_ERR_INVALID_ARG (null pointers, width or height < 1,
+ * ao_radius not finite and > 0 for AO, degenerate or non-orthogonal light
+ * edges for shadows), OCR_ERR_HIP. */
+ocr_status ocr_trace_occluders(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int32_t mode, float ao_radius,
+                               const ocr_rect_light *light, uint64_t seed, uint32_t sample,
+                               ocr_occluders *out, void *stream);
+
+/* The sample step alone (row A1 of the trace): for every pixel, the offset
+ * receiver point o, the ray direction (AO: the cosine-weighted direction;
+ * shadow: y - o for the uniform light point y) and its kind (0 traced,
+ * 1 not traced -- shadow sample behind the tangent plane or receiver behind
+ * the light, 2 background).  Bit-identical to what ocr_trace_occluders
+ * traces.  origin, dir: device float[h][w][3]; kind: device uint8[h][w].
+ * Errors as ocr_trace_occluders. */
+ocr_status ocr_sample_rays(const ocr_gbuffer *gbuf, int32_t mode, const ocr_rect_light *light, uint64_t seed,
+                           uint32_t sample, float *origin, float *dir, uint8_t *kind, void *stream);
+
+/* Device workspace (bytes) ocr_reuse_ao / ocr_reuse_shadow need for a
+ * w x h frame: the first-hit validation bits of the unbiased estimator
+ * (one bit per receiver/candidate pair of a reuse set); 0 for the other
+ * estimators.  Returns 0 for invalid parameters. */
+size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params *params);
+
+/* AO reuse (Sec. 4.3): out[i] = 1 - B_i with
+ *   B_i = sum_{j in S(i), hit_j} [p(z_j|x_i) > 0 and P_i(j) > 0] p(z_j|x_i) / P_i(j),
+ *   P_i(j) = sum_{k in S(i)} p(z_j|x_k),
+ * p = p_AO of Eq. ao-pdf (biased: without the first-hit factor, Eq.
+ * ao-biased-estimator; unbiased: with it, Eq. ao-unbiased-estimator, each
+ * pair validated by an any-hit segment from x_k to z_j stopping 1e-4 short
+ * of z_j).  OCR_NOREUSE gives out[i] = 1 - [hit_i].  Background pixels get 1.
+ *   bvh: needed for OCR_UNBIASED (NULL allowed otherwise)
+ *   occ: the records of ocr_trace_occluders(OCR_AO) for this G-buffer
+ *   workspace: device, >= ocr_workspace_bytes() bytes (NULL if that is 0)
+ *   out: device float[h][w]; raw, unclamped (Sec. 6).
+ * Errors: OCR_ERR_INVALID_ARG, OCR_ERR_HIP. */
+ocr_status ocr_reuse_ao(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ, float ao_radius,
+                        const ocr_reuse_params *params, void *workspace, size_t workspace_bytes, float *out,
+                        void *stream);
+
+/* Shadow reuse (Sec. 4.4): out[i] = F_i - B_i with B_i as above for p_Sh of
+ * Eq. shadow-pdf (Jacobian of Eq. shadow-jacobian at the light
+ * re-intersection y'(x,z); support: y' on the rectangle beyond z, on the
+ * emitting side, z in front of the receiver's tangent plane) and F_i the
+ * exact fraction of the light in front of the receiver's tangent plane
+ * (F_i = 1 for a receiver facing the whole light).  Biased with dark_guard:
+ * 0 when no sample of S(i) is unblocked.  OCR_NOREUSE gives [hit_i is a
+ * miss].  Background pixels get 0.  Errors as ocr_reuse_ao. */
+ocr_status ocr_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                            const ocr_rect_light *light, const ocr_reuse_params *params, void *workspace,
+                            size_t workspace_bytes, float *out, void *stream);
+
+/* out[i] *= s for n floats (device); turns accumulated sums over M samples
+ * into their mean (the final line of App. D / App. H). */
+ocr_status ocr_scale(float *out, int64_t n, float s, void *stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *ocr_last_error(void);
+
+/* Library version string. */
+const char *ocr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OCR_H */

@@ -1,0 +1,322 @@
+"""Python binding of the MI355X occlusion-point-reuse library (``libocr.so``).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch provides device memory (CUDA tensors on ROCm) and the
+current stream; the C-ABI takes raw pointers.  The names mirror ``ocr.h``.
+There is no fallback: if the library is missing or the device is not a
+gfx950 GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libocr.so")
+
+OCR_AO, OCR_SHADOW = 0, 1
+OCR_NOREUSE, OCR_BIASED, OCR_UNBIASED = 0, 1, 2
+OCR_WINDOW, OCR_GROUP = 0, 1
+HIT_MISS = 0xFFFFFFFF
+HIT_SELF = 0xFFFFFFFE
+
+MODES = {"ao": OCR_AO, "shadow": OCR_SHADOW}
+ESTIMATORS = {"none": OCR_NOREUSE, "biased": OCR_BIASED, "unbiased": OCR_UNBIASED}
+PATTERNS = {"window": OCR_WINDOW, "group": OCR_GROUP}
+
+
+class OcrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ocr status {status}: {msg}")
+        self.status = status
+
+
+class _GBuffer(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("nrm", ctypes.c_void_p), ("prim", ctypes.c_void_p),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class _Light(ctypes.Structure):
+    _fields_ = [("center", ctypes.c_float * 3), ("edge_u", ctypes.c_float * 3), ("edge_v", ctypes.c_float * 3)]
+
+
+class _Occ(ctypes.Structure):
+    _fields_ = [("dz", ctypes.c_void_p), ("nz", ctypes.c_void_p), ("hit", ctypes.c_void_p)]
+
+
+class ReuseParams(ctypes.Structure):
+    _fields_ = [("pattern", ctypes.c_int32), ("radius", ctypes.c_int32), ("group_n", ctypes.c_int32),
+                ("estimator", ctypes.c_int32), ("dark_guard", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
+
+
+class BvhInfo(ctypes.Structure):
+    _fields_ = [("ntris", ctypes.c_int64), ("nnodes", ctypes.c_int64), ("depth", ctypes.c_int32),
+                ("max_leaf", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
+
+
+EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders", "ocr_sample_rays",
+           "ocr_workspace_bytes",
+           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_scale", "ocr_last_error", "ocr_version"]
+
+_lib = None
+
+
+def lib():
+    """Load libocr.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OcrError(-4, f"{LIB_PATH} is missing: build it first (python -m paper_2607_23122_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.ocr_build_bvh.restype = i32
+    L.ocr_build_bvh.argtypes = [vp, i64, vp, i64, vp, ctypes.POINTER(vp)]
+    L.ocr_bvh_free.restype = i32
+    L.ocr_bvh_free.argtypes = [vp]
+    L.ocr_bvh_get_info.restype = i32
+    L.ocr_bvh_get_info.argtypes = [vp, ctypes.POINTER(BvhInfo)]
+    L.ocr_trace_occluders.restype = i32
+    L.ocr_trace_occluders.argtypes = [vp, ctypes.POINTER(_GBuffer), i32, ctypes.c_float, ctypes.POINTER(_Light),
+                                      ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(_Occ), vp]
+    L.ocr_sample_rays.restype = i32
+    L.ocr_sample_rays.argtypes = [ctypes.POINTER(_GBuffer), i32, ctypes.POINTER(_Light), ctypes.c_uint64,
+                                  ctypes.c_uint32, vp, vp, vp, vp]
+    L.ocr_workspace_bytes.restype = ctypes.c_size_t
+    L.ocr_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(ReuseParams)]
+    L.ocr_reuse_ao.restype = i32
+    L.ocr_reuse_ao.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), ctypes.c_float,
+                               ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
+    L.ocr_reuse_shadow.restype = i32
+    L.ocr_reuse_shadow.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), ctypes.POINTER(_Light),
+                                   ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
+    L.ocr_scale.restype = i32
+    L.ocr_scale.argtypes = [vp, i64, ctypes.c_float, vp]
+    L.ocr_last_error.restype = ctypes.c_char_p
+    L.ocr_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise OcrError(status, lib().ocr_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise OcrError(-1, "expected a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise OcrError(-1, "expected a contiguous tensor")
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# Device-side inputs
+# ---------------------------------------------------------------------------
+@dataclass
+class DeviceGBuffer:
+    pos: object   # torch.float32 [H,W,3]
+    nrm: object   # torch.float32 [H,W,3]
+    prim: object  # torch.int32 [H,W] holding uint32 bit patterns
+
+    @property
+    def height(self) -> int:
+        return int(self.prim.shape[0])
+
+    @property
+    def width(self) -> int:
+        return int(self.prim.shape[1])
+
+    @classmethod
+    def from_host(cls, gb, device="cuda"):
+        import torch
+        pos = torch.from_numpy(np.ascontiguousarray(gb.pos, np.float32)).to(device)
+        nrm = torch.from_numpy(np.ascontiguousarray(gb.nrm, np.float32)).to(device)
+        prim = torch.from_numpy(np.ascontiguousarray(gb.prim, np.uint32).view(np.int32)).to(device)
+        return cls(pos, nrm, prim)
+
+    def c(self) -> _GBuffer:
+        return _GBuffer(_dptr(self.pos), _dptr(self.nrm), _dptr(self.prim), self.width, self.height)
+
+
+def light_struct(light) -> _Light:
+    la = light.as_array() if hasattr(light, "as_array") else np.asarray(light, np.float32)
+    s = _Light()
+    for i in range(3):
+        s.center[i] = float(la[i])
+        s.edge_u[i] = float(la[3 + i])
+        s.edge_v[i] = float(la[6 + i])
+    return s
+
+
+@dataclass
+class Occluders:
+    dz: object   # torch.float32 [H,W,3]
+    nz: object   # torch.float32 [H,W,3]
+    hit: object  # torch.int32 [H,W] (uint32 bit patterns)
+
+    @classmethod
+    def empty(cls, H, W, device="cuda"):
+        import torch
+        return cls(torch.zeros((H, W, 3), dtype=torch.float32, device=device),
+                   torch.zeros((H, W, 3), dtype=torch.float32, device=device),
+                   torch.zeros((H, W), dtype=torch.int32, device=device))
+
+    def c(self) -> _Occ:
+        return _Occ(_dptr(self.dz), _dptr(self.nz), _dptr(self.hit))
+
+    def hit_u32(self) -> np.ndarray:
+        return self.hit.cpu().numpy().view(np.uint32)
+
+
+class BVH:
+    """Library-owned acceleration structure (ocr_build_bvh / ocr_bvh_free)."""
+
+    def __init__(self, V, F, stream=None):
+        V = np.ascontiguousarray(V, np.float32)
+        F = np.ascontiguousarray(F, np.uint32)
+        h = ctypes.c_void_p()
+        _check(lib().ocr_build_bvh(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], _stream(stream),
+                                   ctypes.byref(h)))
+        self.h = h
+        self.ntris = int(F.shape[0])
+
+    def info(self) -> BvhInfo:
+        out = BvhInfo()
+        _check(lib().ocr_bvh_get_info(self.h, ctypes.byref(out)))
+        return out
+
+    def free(self):
+        if getattr(self, "h", None) and self.h.value:
+            _check(lib().ocr_bvh_free(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_bvh(V, F, stream=None) -> BVH:
+    return BVH(V, F, stream)
+
+
+def reuse_params(pattern="window", radius=2, group_n=8, estimator="biased", dark_guard=True,
+                 accumulate=False) -> ReuseParams:
+    return ReuseParams(PATTERNS[pattern] if isinstance(pattern, str) else int(pattern), int(radius), int(group_n),
+                       ESTIMATORS[estimator] if isinstance(estimator, str) else int(estimator),
+                       1 if dark_guard else 0, 1 if accumulate else 0)
+
+
+def trace_occluders(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, light=None, seed=1, sample=0,
+                    out: Occluders | None = None, stream=None) -> Occluders:
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    out = out or Occluders.empty(gbuf.height, gbuf.width, gbuf.prim.device)
+    g = gbuf.c()
+    o = out.c()
+    lp = ctypes.byref(light_struct(light)) if light is not None else None
+    _check(lib().ocr_trace_occluders(bvh.h, ctypes.byref(g), m, float(ao_radius), lp, int(seed), int(sample),
+                                     ctypes.byref(o), _stream(stream)))
+    return out
+
+
+def sample_rays(gbuf: DeviceGBuffer, mode="ao", light=None, seed=1, sample=0, stream=None):
+    """(origin, dir, kind) device tensors of the sample step."""
+    import torch
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    dev = gbuf.prim.device
+    o = torch.empty((gbuf.height, gbuf.width, 3), dtype=torch.float32, device=dev)
+    d = torch.empty((gbuf.height, gbuf.width, 3), dtype=torch.float32, device=dev)
+    k = torch.empty((gbuf.height, gbuf.width), dtype=torch.uint8, device=dev)
+    g = gbuf.c()
+    lp = ctypes.byref(light_struct(light)) if light is not None else None
+    _check(lib().ocr_sample_rays(ctypes.byref(g), m, lp, int(seed), int(sample), _dptr(o), _dptr(d), _dptr(k),
+                                 _stream(stream)))
+    return o, d, k
+
+
+def workspace_bytes(width, height, params: ReuseParams) -> int:
+    return int(lib().ocr_workspace_bytes(int(width), int(height), ctypes.byref(params)))
+
+
+def _workspace(gbuf, params, workspace):
+    import torch
+    need = workspace_bytes(gbuf.width, gbuf.height, params)
+    if need == 0:
+        return None, 0
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=gbuf.prim.device)
+    return workspace, int(workspace.numel() * workspace.element_size())
+
+
+def reuse_ao(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluders, ao_radius: float, params: ReuseParams,
+             out=None, workspace=None, stream=None):
+    import torch
+    out = out if out is not None else torch.empty((gbuf.height, gbuf.width), dtype=torch.float32,
+                                                  device=gbuf.prim.device)
+    ws, nbytes = _workspace(gbuf, params, workspace)
+    g, o = gbuf.c(), occ.c()
+    _check(lib().ocr_reuse_ao(bvh.h if bvh is not None else None, ctypes.byref(g), ctypes.byref(o), float(ao_radius),
+                              ctypes.byref(params), _dptr(ws) if ws is not None else None, nbytes, _dptr(out),
+                              _stream(stream)))
+    return out
+
+
+def reuse_shadow(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluders, light, params: ReuseParams, out=None,
+                 workspace=None, stream=None):
+    import torch
+    out = out if out is not None else torch.empty((gbuf.height, gbuf.width), dtype=torch.float32,
+                                                  device=gbuf.prim.device)
+    ws, nbytes = _workspace(gbuf, params, workspace)
+    g, o = gbuf.c(), occ.c()
+    ls = light_struct(light)
+    _check(lib().ocr_reuse_shadow(bvh.h if bvh is not None else None, ctypes.byref(g), ctypes.byref(o),
+                                  ctypes.byref(ls), ctypes.byref(params), _dptr(ws) if ws is not None else None,
+                                  nbytes, _dptr(out), _stream(stream)))
+    return out
+
+
+def scale(out, s: float, stream=None):
+    _check(lib().ocr_scale(_dptr(out), int(out.numel()), float(s), _stream(stream)))
+    return out
+
+
+def render(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, light=None, seed=1, nsamples=1,
+           first_sample=0, params: ReuseParams | None = None, stream=None):
+    """Mean over `nsamples` samples of the per-sample estimate (trace, then
+    reuse accumulating into one buffer, then one scale)."""
+    import torch
+    params = params or reuse_params()
+    occ = Occluders.empty(gbuf.height, gbuf.width, gbuf.prim.device)
+    out = None
+    ws = None
+    need = workspace_bytes(gbuf.width, gbuf.height, params)
+    if need:
+        ws = torch.empty(need, dtype=torch.uint8, device=gbuf.prim.device)
+    for s in range(nsamples):
+        trace_occluders(bvh, gbuf, mode, ao_radius, light, seed, first_sample + s, occ, stream)
+        p = ReuseParams(params.pattern, params.radius, params.group_n, params.estimator, params.dark_guard,
+                        0 if s == 0 else 1)
+        if mode in ("ao", OCR_AO):
+            out = reuse_ao(bvh, gbuf, occ, ao_radius, p, out, ws, stream)
+        else:
+            out = reuse_shadow(bvh, gbuf, occ, light, p, out, ws, stream)
+    if nsamples > 1:
+        scale(out, 1.0 / nsamples, stream)
+    return out
+
+
+def version() -> str:
+    return lib().ocr_version().decode()

@@ -1,0 +1,208 @@
+// Software ray traversal of the 4-wide BVH on gfx950 (no ray-tracing units).
+//
+// One lane per ray.  The traversal stack lives in LDS, one column per lane
+// (entry k of lane t at [k * blockDim + t], so lanes at equal depth hit
+// distinct banks), with a private spill area for the rare deep paths.
+// Child boxes are tested with a conservative slab test (far distances
+// widened by a few ulps so no box that the ray touches is skipped), and
+// triangles with the watertight test of Woop, Benthin and Wald (JCGT 2013):
+// the edge functions are 2x2 determinants of sheared vertex coordinates,
+// evaluated without contraction and recomputed in FP64 when one is exactly
+// zero, so rays through shared edges and vertices never slip between
+// triangles.
+#pragma once
+
+#include "ocr_common.hpp"
+
+namespace ocr {
+
+struct TRay {
+    float o[3];
+    float inv[3];   // 1 / d with zero components replaced by +-1e-20
+    float m0[3], m1[3], m2[3];  // shear rows: x' = m0.(p-o), y' = m1.(p-o), z' = m2.(p-o)
+    uint32_t ign0, ign1;
+};
+
+__device__ inline void make_ray(const float o[3], const float d[3], uint32_t ign0, uint32_t ign1, TRay &r) {
+    for (int c = 0; c < 3; ++c) {
+        r.o[c] = o[c];
+        float dc = fabsf(d[c]) < 1e-20f ? copysignf(1e-20f, d[c]) : d[c];
+        r.inv[c] = 1.0f / dc;
+    }
+    float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
+    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    if (d[kz] < 0.0f) {
+        int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    float dkz = d[kz];
+    float Sx = d[kx] / dkz, Sy = d[ky] / dkz, Sz = 1.0f / dkz;
+    for (int c = 0; c < 3; ++c) {
+        r.m0[c] = (c == kx ? 1.0f : 0.0f) - (c == kz ? Sx : 0.0f);
+        r.m1[c] = (c == ky ? 1.0f : 0.0f) - (c == kz ? Sy : 0.0f);
+        r.m2[c] = c == kz ? Sz : 0.0f;
+    }
+    r.ign0 = ign0;
+    r.ign1 = ign1;
+}
+
+// Watertight triangle test.  Returns the ray parameter t (> 0) or -1.
+__device__ inline float tri_hit(const TRay &r, const float4 &v0, const float4 &v1, const float4 &v2) {
+#pragma clang fp contract(off)
+    float A[3] = {v0.x - r.o[0], v0.y - r.o[1], v0.z - r.o[2]};
+    float B[3] = {v1.x - r.o[0], v1.y - r.o[1], v1.z - r.o[2]};
+    float C[3] = {v2.x - r.o[0], v2.y - r.o[1], v2.z - r.o[2]};
+    float Ax = __fmaf_rn(r.m0[2], A[2], __fmaf_rn(r.m0[1], A[1], r.m0[0] * A[0]));
+    float Ay = __fmaf_rn(r.m1[2], A[2], __fmaf_rn(r.m1[1], A[1], r.m1[0] * A[0]));
+    float Bx = __fmaf_rn(r.m0[2], B[2], __fmaf_rn(r.m0[1], B[1], r.m0[0] * B[0]));
+    float By = __fmaf_rn(r.m1[2], B[2], __fmaf_rn(r.m1[1], B[1], r.m1[0] * B[0]));
+    float Cx = __fmaf_rn(r.m0[2], C[2], __fmaf_rn(r.m0[1], C[1], r.m0[0] * C[0]));
+    float Cy = __fmaf_rn(r.m1[2], C[2], __fmaf_rn(r.m1[1], C[1], r.m1[0] * C[0]));
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        double u = (double)Cx * (double)By - (double)Cy * (double)Bx;
+        double v = (double)Ax * (double)Cy - (double)Ay * (double)Cx;
+        double w = (double)Bx * (double)Ay - (double)By * (double)Ax;
+        U = (float)u;
+        V = (float)v;
+        W = (float)w;
+        if ((u < 0.0 || v < 0.0 || w < 0.0) && (u > 0.0 || v > 0.0 || w > 0.0)) return -1.0f;
+    } else if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) {
+        return -1.0f;
+    }
+    float det = U + V + W;
+    if (det == 0.0f) return -1.0f;
+    float Az = __fmaf_rn(r.m2[2], A[2], __fmaf_rn(r.m2[1], A[1], r.m2[0] * A[0]));
+    float Bz = __fmaf_rn(r.m2[2], B[2], __fmaf_rn(r.m2[1], B[1], r.m2[0] * B[0]));
+    float Cz = __fmaf_rn(r.m2[2], C[2], __fmaf_rn(r.m2[1], C[1], r.m2[0] * C[0]));
+    float T = __fmaf_rn(W, Cz, __fmaf_rn(V, Bz, U * Az));
+    float t = T / det;
+    return t > 0.0f ? t : -1.0f;
+}
+
+// Result of a closest-hit query: `tri` is the scene triangle index or
+// OCR_HIT_MISS, `leaf_tri` its position in the leaf-ordered array.
+struct Hit {
+    float t;
+    uint32_t tri;
+    uint32_t leaf_tri;
+};
+
+// Closest hit over t in (0, tmax] (INCLUSIVE) or (0, tmax); with ANY, the
+// first hit found over (0, tmax) ends the query.  Equal distances resolve
+// to the smaller scene triangle index.
+template <bool ANY, bool INCLUSIVE>
+__device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, uint32_t *lds_stack, int stride) {
+    Hit h;
+    h.t = tmax;
+    h.tri = OCR_HIT_MISS;
+    h.leaf_tri = 0;
+    uint32_t spill[kStackTotal - kStackLds];
+    int sp = 0;
+    uint32_t node = 0;  // root
+    const float grow = 1.0f + 0x1p-20f;
+    for (;;) {
+        if (!(node & kLeafBit)) {
+            const float4 *np = reinterpret_cast<const float4 *>(bvh.nodes + node);
+            float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+            uint4 ch = reinterpret_cast<const uint4 *>(np)[6];
+            float lxs[4] = {lx.x, lx.y, lx.z, lx.w}, hxs[4] = {hx.x, hx.y, hx.z, hx.w};
+            float lys[4] = {ly.x, ly.y, ly.z, ly.w}, hys[4] = {hy.x, hy.y, hy.z, hy.w};
+            float lzs[4] = {lz.x, lz.y, lz.z, lz.w}, hzs[4] = {hz.x, hz.y, hz.z, hz.w};
+            uint32_t chs[4] = {ch.x, ch.y, ch.z, ch.w};
+            float tn[4];
+            uint32_t cand[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float t0x = (lxs[i] - r.o[0]) * r.inv[0], t1x = (hxs[i] - r.o[0]) * r.inv[0];
+                float t0y = (lys[i] - r.o[1]) * r.inv[1], t1y = (hys[i] - r.o[1]) * r.inv[1];
+                float t0z = (lzs[i] - r.o[2]) * r.inv[2], t1z = (hzs[i] - r.o[2]) * r.inv[2];
+                float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+                float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
+                tfar = fminf(tfar, h.t * grow);
+                bool hit = tnear <= tfar && chs[i] != kEmpty;
+                tn[i] = hit ? tnear : INFINITY;
+                cand[i] = chs[i];
+            }
+            // sort the four (distance, child) pairs, nearest first (5 compare-exchanges)
+#define OCR_CSWAP(a, b)                                      \
+    if (tn[b] < tn[a]) {                                     \
+        float tt = tn[a]; tn[a] = tn[b]; tn[b] = tt;         \
+        uint32_t cc = cand[a]; cand[a] = cand[b]; cand[b] = cc; \
+    }
+            OCR_CSWAP(0, 1)
+            OCR_CSWAP(2, 3)
+            OCR_CSWAP(0, 2)
+            OCR_CSWAP(1, 3)
+            OCR_CSWAP(1, 2)
+#undef OCR_CSWAP
+            if (tn[0] < INFINITY) {
+                // push the farther ones (farthest first), continue with the nearest
+#pragma unroll
+                for (int k = 3; k >= 1; --k) {
+                    if (tn[k] < INFINITY) {
+                        if (sp < kStackLds) lds_stack[sp * stride] = cand[k];
+                        else spill[sp - kStackLds] = cand[k];
+                        ++sp;
+                    }
+                }
+                node = cand[0];
+                continue;
+            }
+        } else {
+            uint32_t first = node & 0x07FFFFFFu;
+            uint32_t count = ((node >> 27) & 0xFu) + 1u;
+            for (uint32_t q = 0; q < count; ++q) {
+                const float4 *tp = bvh.tris + 3 * (size_t)(first + q);
+                float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
+                uint32_t id = __float_as_uint(v0.w);
+                if (id == r.ign0 || id == r.ign1) continue;
+                float t = tri_hit(r, v0, v1, v2);
+                if (!(t > 0.0f)) continue;
+                bool take;
+                if (ANY) {
+                    take = t < tmax;
+                } else if (t < h.t) {
+                    take = true;
+                } else if (t == h.t) {
+                    take = h.tri == OCR_HIT_MISS ? INCLUSIVE : id < h.tri;
+                } else {
+                    take = false;
+                }
+                if (take) {
+                    h.t = t;
+                    h.tri = id;
+                    h.leaf_tri = first + q;
+                    if (ANY) return h;
+                }
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        node = sp < kStackLds ? lds_stack[sp * stride] : spill[sp - kStackLds];
+    }
+    return h;
+}
+
+// Unit geometric normal of a leaf-ordered triangle, facing against d.
+__device__ inline void oriented_normal(const DeviceBVH &bvh, uint32_t leaf_tri, const float d[3], float n[3]) {
+    const float4 *tp = bvh.tris + 3 * (size_t)leaf_tri;
+    float4 a = tp[0], b = tp[1], c = tp[2];
+    float e1[3] = {b.x - a.x, b.y - a.y, b.z - a.z};
+    float e2[3] = {c.x - a.x, c.y - a.y, c.z - a.z};
+    float x = e1[1] * e2[2] - e1[2] * e2[1];
+    float y = e1[2] * e2[0] - e1[0] * e2[2];
+    float z = e1[0] * e2[1] - e1[1] * e2[0];
+    float inv = rsqrtf(x * x + y * y + z * z);
+    float s = (x * d[0] + y * d[1] + z * d[2]) > 0.0f ? -inv : inv;
+    n[0] = x * s;
+    n[1] = y * s;
+    n[2] = z * s;
+}
+
+}  // namespace ocr
