@@ -876,7 +876,11 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
     *nvar = 0;
     *value = 0.0;
     if (c->prim[i] == ORC_MISS) {
+        /* background pixel: no estimate is defined; the output convention is
+         * 1 for AO (nothing occludes) and 0 for shadows (no lit surface) */
         *value = p->mode == 0 ? 1.0 : 0.0;
+        var[0] = *value;
+        *nvar = 1;
         return;
     }
     if (p->estimator == 0) {
