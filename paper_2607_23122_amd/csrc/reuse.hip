@@ -414,28 +414,31 @@ hipError_t launch_reuse(const GBufView &g, const OccView &occ, int mode, float R
     const float R2 = R * R;
     const int words = pair_words(p);
     const bool unb = p.estimator == OCR_UNBIASED;
+    // the dark-region guard belongs to the biased shadow estimator only
+    ocr_reuse_params q = p;
+    q.dark_guard = (p.estimator == OCR_BIASED && p.dark_guard) ? 1 : 0;
     if (p.estimator == OCR_NOREUSE) {
         int64_t n = (int64_t)g.w * g.h;
         dim3 grid((unsigned)((n + kRBlock - 1) / kRBlock)), block(kRBlock);
-        if (mode == OCR_AO) hipLaunchKernelGGL(noreuse_kernel<OCR_AO>, grid, block, 0, st, g, occ, p.accumulate, out);
-        else hipLaunchKernelGGL(noreuse_kernel<OCR_SHADOW>, grid, block, 0, st, g, occ, p.accumulate, out);
+        if (mode == OCR_AO) hipLaunchKernelGGL(noreuse_kernel<OCR_AO>, grid, block, 0, st, g, occ, q.accumulate, out);
+        else hipLaunchKernelGGL(noreuse_kernel<OCR_SHADOW>, grid, block, 0, st, g, occ, q.accumulate, out);
     } else if (p.pattern == OCR_WINDOW) {
         if (mode == OCR_AO) {
-            hipError_t e = unb ? launch_win<OCR_AO, true>(g, occ, R2, L, bits, words, p, out, st)
-                               : launch_win<OCR_AO, false>(g, occ, R2, L, bits, words, p, out, st);
+            hipError_t e = unb ? launch_win<OCR_AO, true>(g, occ, R2, L, bits, words, q, out, st)
+                               : launch_win<OCR_AO, false>(g, occ, R2, L, bits, words, q, out, st);
             if (e != hipSuccess) return e;
         } else {
-            hipError_t e = unb ? launch_win<OCR_SHADOW, true>(g, occ, R2, L, bits, words, p, out, st)
-                               : launch_win<OCR_SHADOW, false>(g, occ, R2, L, bits, words, p, out, st);
+            hipError_t e = unb ? launch_win<OCR_SHADOW, true>(g, occ, R2, L, bits, words, q, out, st)
+                               : launch_win<OCR_SHADOW, false>(g, occ, R2, L, bits, words, q, out, st);
             if (e != hipSuccess) return e;
         }
     } else {
         if (mode == OCR_AO) {
-            if (unb) launch_grp<OCR_AO, true>(g, occ, R2, L, bits, words, p, out, st);
-            else launch_grp<OCR_AO, false>(g, occ, R2, L, bits, words, p, out, st);
+            if (unb) launch_grp<OCR_AO, true>(g, occ, R2, L, bits, words, q, out, st);
+            else launch_grp<OCR_AO, false>(g, occ, R2, L, bits, words, q, out, st);
         } else {
-            if (unb) launch_grp<OCR_SHADOW, true>(g, occ, R2, L, bits, words, p, out, st);
-            else launch_grp<OCR_SHADOW, false>(g, occ, R2, L, bits, words, p, out, st);
+            if (unb) launch_grp<OCR_SHADOW, true>(g, occ, R2, L, bits, words, q, out, st);
+            else launch_grp<OCR_SHADOW, false>(g, occ, R2, L, bits, words, q, out, st);
         }
     }
     return hipGetLastError();

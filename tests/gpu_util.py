@@ -33,9 +33,13 @@ def compare_records(gpu_dz, gpu_nz, gpu_hit, rec, o):
     """Where the hits agree: dz = z - o and the oriented normal."""
     same = (gpu_hit == rec.hit) & (rec.hit < oracle.SELF)
     ref_dz = rec.z[same] - o[same].astype(np.float64)
-    err = np.abs(gpu_dz[same].astype(np.float64) - ref_dz)
-    scale = np.linalg.norm(ref_dz, axis=1, keepdims=True)
-    assert (err <= 4e-6 * scale + 1e-6).all(), float((err / (scale + 1e-30)).max())
+    err = np.linalg.norm(gpu_dz[same].astype(np.float64) - ref_dz, axis=1)
+    scale = np.linalg.norm(ref_dz, axis=1)
+    # the distance along a ray is ill-conditioned at grazing incidence: allow
+    # FP32 error of a few ulps of |dz| divided by |cos| of the hit angle
+    cos = np.abs(np.einsum("ij,ij->i", rec.nz[same], ref_dz)) / np.maximum(scale, 1e-30)
+    allow = 8e-7 * scale / np.maximum(cos, 1e-3) + 1e-6
+    assert (err <= allow).all(), float((err / allow).max())
     nerr = np.abs(gpu_nz[same].astype(np.float64) - rec.nz[same]).max() if same.any() else 0.0
     assert nerr < 1e-5, nerr
     return int(same.sum())
