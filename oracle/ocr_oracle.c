@@ -37,7 +37,9 @@
  * range's tolerance, and a pair density is "ambiguous" when one of its
  * support tests sits within a narrow band of its threshold.  Ambiguous
  * densities are enumerated (both outcomes) so that the comparison accepts
- * either; grazing traces exclude the targets that use them.
+ * either.  Grazing traces are only flagged: a comparison that finds a
+ * different hit on a flagged ray leaves out the targets whose reuse set
+ * holds it.
  */
 #include "ocr_oracle.h"
 
@@ -888,15 +890,13 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
          * V = 1 when the ray or segment is free. */
         *value = c->hit[i] == ORC_MISS ? 1.0 : 0.0;
         var[0] = *value;
-        *nvar = c->graze[i] ? 0 : 1;
+        *nvar = 1;
         return;
     }
     t->m = reuse_set(p, c->W, c->H, c->prim, ix, iy, t->S);
     int m = t->m, excluded = 0, ia = -1;
-    for (int a = 0; a < m; ++a) {
+    for (int a = 0; a < m; ++a)
         if (t->S[a] == i) ia = a;
-        if (c->graze[t->S[a]]) excluded = 1;
-    }
     int amb_idx[MAX_AMBIG + 1], namb = 0;
     for (int a = 0; a < m; ++a)
         for (int b = 0; b < m; ++b) {

@@ -57,9 +57,9 @@ void orc_records(const orc_scene *s, int32_t W, int32_t H, const float *pos, con
                  uint32_t *hit, double *z, double *nz, uint8_t *graze);
 
 /* Reuse estimate for the targets of a region.  Records must cover every
- * pixel of the targets' reuse sets.  nvar: 0 = excluded (grazing trace or
- * too many ambiguous threshold decisions), else the number of admissible
- * values written to var[8*i]. */
+ * pixel of the targets' reuse sets.  nvar: 0 = not comparable (more than
+ * three ambiguous threshold decisions, or a density on a grazing light
+ * direction), else the number of admissible values written to var[8*i]. */
 void orc_reuse(const orc_scene *s, int32_t W, int32_t H, const float *pos, const float *nrm,
                const uint32_t *prim, const orc_params *p, const uint32_t *hit, const double *z,
                const double *nz, const uint8_t *graze, int32_t x0, int32_t y0, int32_t x1, int32_t y1,

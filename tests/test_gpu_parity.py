@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as w
-from gpu_util import compare_hits, compare_records, compare_values, log, tiles, to_np
+from gpu_util import compare_hits, compare_records, compare_values, log, mismatch_reach, tiles, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -107,7 +107,7 @@ def test_trace_matches_oracle(ocr, request, which, mode):
     gh = occ.hit_u32()
     st = compare_hits(gh, rec, case.gb.valid)
     o, _, _ = oracle.samples(case.gb, p)
-    n = compare_records(to_np(occ.dz), to_np(occ.nz), gh, rec, o)
+    n = compare_records(to_np(occ.dz), to_np(occ.nz), gh, rec, o, case.scene)
     log(f"    {st}, records compared {n}")
     assert st["rays"] > 0.5 * case.gb.valid.sum()
 
@@ -125,8 +125,9 @@ def test_reuse_ao_boxes(ocr, boxes, pattern, size, est):
     log(f"[reuse ao boxes] {pattern} {size} {est}")
     occ = _trace(ocr, boxes, "ao", seed=1)
     gpu = _reuse(ocr, boxes, "ao", occ, ocr.reuse_params(pattern, size, size, est))
-    _, res = oracle.frame(boxes.osc, boxes.gb, _oparams(boxes, "ao", est, pattern, size))
-    st = compare_values(gpu, res)
+    p = _oparams(boxes, "ao", est, pattern, size)
+    rec, res = oracle.frame(boxes.osc, boxes.gb, p)
+    st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
     log(f"    {st}")
     assert st["excluded"] <= 1e-3 * st["targets"]
 
@@ -139,8 +140,9 @@ def test_reuse_shadow_terrain_small(ocr, terrain_small, pattern, size, est, guar
     log(f"[reuse shadow 480x270] {pattern} {size} {est} guard={guard}")
     occ = _trace(ocr, case, "shadow", seed=3)
     gpu = _reuse(ocr, case, "shadow", occ, ocr.reuse_params(pattern, size, size, est, dark_guard=guard))
-    _, res = oracle.frame(case.osc, case.gb, _oparams(case, "shadow", est, pattern, size, seed=3, guard=guard))
-    st = compare_values(gpu, res)
+    p = _oparams(case, "shadow", est, pattern, size, seed=3, guard=guard)
+    rec, res = oracle.frame(case.osc, case.gb, p)
+    st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
     log(f"    {st}")
     assert st["excluded"] <= 2e-3 * st["targets"]
 
@@ -150,8 +152,9 @@ def test_reuse_ao_terrain_small_unbiased_r3(ocr, terrain_small):
     log("[reuse ao 480x270] window 3 unbiased")
     occ = _trace(ocr, case, "ao", seed=5)
     gpu = _reuse(ocr, case, "ao", occ, ocr.reuse_params("window", 3, 0, "unbiased"))
-    _, res = oracle.frame(case.osc, case.gb, _oparams(case, "ao", "unbiased", "window", 3, seed=5))
-    st = compare_values(gpu, res)
+    p = _oparams(case, "ao", "unbiased", "window", 3, seed=5)
+    rec, res = oracle.frame(case.osc, case.gb, p)
+    st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
     log(f"    {st}")
 
 
@@ -166,10 +169,14 @@ def test_reuse_1080p_tiles(ocr, terrain_1080, mode, est, ntiles):
     occ = _trace(ocr, case, mode, seed=1)
     gpu = _reuse(ocr, case, mode, occ, ocr.reuse_params("window", 3, 0, est))
     p = _oparams(case, mode, est, "window", 3, seed=1)
+    gh = occ.hit_u32()
     for t in tiles(case.gb.width, case.gb.height, ntiles, 32, seed=11 if mode == "ao" else 12):
-        rec = oracle.records(case.osc, case.gb, p, oracle.halo_region(p, case.gb.width, case.gb.height, t))
+        hr = oracle.halo_region(p, case.gb.width, case.gb.height, t)
+        rec = oracle.records(case.osc, case.gb, p, hr)
         res = oracle.reuse(case.osc, case.gb, p, rec, t)
-        st = compare_values(gpu, res, region=t)
+        inside = np.zeros_like(case.gb.valid)
+        inside[hr[1]:hr[3], hr[0]:hr[2]] = True
+        st = compare_values(gpu, res, region=t, exclude=mismatch_reach(np.where(inside, gh, rec.hit), rec, p))
         log(f"    tile {t}: {st}")
     # every estimate is finite; background pixels carry the conventions
     assert np.isfinite(gpu).all()
@@ -219,8 +226,9 @@ def test_small_and_ragged_frames(ocr, W, H):
         log(f"[ragged {W}x{H}] {pattern} {size} {est}")
         occ = _trace(ocr, case, "ao", seed=4)
         gpu = _reuse(ocr, case, "ao", occ, ocr.reuse_params(pattern, size, size, est))
-        _, res = oracle.frame(case.osc, gb, _oparams(case, "ao", est, pattern, size, seed=4))
-        compare_values(gpu, res)
+        p = _oparams(case, "ao", est, pattern, size, seed=4)
+        rec, res = oracle.frame(case.osc, gb, p)
+        compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
 
 
 def test_all_background(ocr):
