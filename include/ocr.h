@@ -105,7 +105,10 @@ typedef struct {
  *   dark_guard: biased shadows only: a target whose reuse set holds no
  *               unblocked sample gets 0 (Sec. 4.4)
  *   accumulate: 0 = write the estimate, 1 = add it to the output (sample
- *               accumulation; see ocr_scale) */
+ *               accumulation; see ocr_scale)
+ *   validated:  OCR_UNBIASED only: 1 = the workspace already holds this
+ *               frame's validation bits (ocr_validate_pairs), 0 = the reuse
+ *               call computes them first */
 typedef struct {
     int32_t pattern;
     int32_t radius;
@@ -113,6 +116,7 @@ typedef struct {
     int32_t estimator;
     int32_t dark_guard;
     int32_t accumulate;
+    int32_t validated;
 } ocr_reuse_params;
 
 /* Library-owned acceleration structure over a triangle scene. */
@@ -175,6 +179,17 @@ ocr_status ocr_sample_rays(const ocr_gbuffer *gbuf, int32_t mode, const ocr_rect
  * (one bit per receiver/candidate pair of a reuse set); 0 for the other
  * estimators.  Returns 0 for invalid parameters. */
 size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params *params);
+
+/* First half of the unbiased estimators (Eq. occ-first-hit): for every
+ * receiver k and candidate j of a common reuse set whose density at k is
+ * positive, an any-hit segment from o_k towards z_j over t in (0, 1 - 1e-4),
+ * ignoring z_j's triangle and k's own, decides whether z_j is the first hit
+ * from x_k.  Writes one bit per pair into workspace (layout internal; size
+ * from ocr_workspace_bytes with estimator OCR_UNBIASED).  mode, ao_radius and
+ * light as for the trace.  Errors as ocr_reuse_ao. */
+ocr_status ocr_validate_pairs(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ, int32_t mode,
+                              float ao_radius, const ocr_rect_light *light, const ocr_reuse_params *params,
+                              void *workspace, size_t workspace_bytes, void *stream);
 
 /* AO reuse (Sec. 4.3): out[i] = 1 - B_i with
  *   B_i = sum_{j in S(i), hit_j} [p(z_j|x_i) > 0 and P_i(j) > 0] p(z_j|x_i) / P_i(j),

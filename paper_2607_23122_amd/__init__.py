@@ -49,7 +49,8 @@ class _Occ(ctypes.Structure):
 
 class ReuseParams(ctypes.Structure):
     _fields_ = [("pattern", ctypes.c_int32), ("radius", ctypes.c_int32), ("group_n", ctypes.c_int32),
-                ("estimator", ctypes.c_int32), ("dark_guard", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
+                ("estimator", ctypes.c_int32), ("dark_guard", ctypes.c_int32), ("accumulate", ctypes.c_int32),
+                ("validated", ctypes.c_int32)]
 
 
 class BvhInfo(ctypes.Structure):
@@ -58,7 +59,7 @@ class BvhInfo(ctypes.Structure):
 
 
 EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders", "ocr_sample_rays",
-           "ocr_workspace_bytes",
+           "ocr_workspace_bytes", "ocr_validate_pairs",
            "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_scale", "ocr_last_error", "ocr_version"]
 
 _lib = None
@@ -87,6 +88,9 @@ def lib():
                                   ctypes.c_uint32, vp, vp, vp, vp]
     L.ocr_workspace_bytes.restype = ctypes.c_size_t
     L.ocr_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(ReuseParams)]
+    L.ocr_validate_pairs.restype = i32
+    L.ocr_validate_pairs.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), i32, ctypes.c_float,
+                                     ctypes.POINTER(_Light), ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp]
     L.ocr_reuse_ao.restype = i32
     L.ocr_reuse_ao.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), ctypes.c_float,
                                ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
@@ -214,10 +218,10 @@ def build_bvh(V, F, stream=None) -> BVH:
 
 
 def reuse_params(pattern="window", radius=2, group_n=8, estimator="biased", dark_guard=True,
-                 accumulate=False) -> ReuseParams:
+                 accumulate=False, validated=False) -> ReuseParams:
     return ReuseParams(PATTERNS[pattern] if isinstance(pattern, str) else int(pattern), int(radius), int(group_n),
                        ESTIMATORS[estimator] if isinstance(estimator, str) else int(estimator),
-                       1 if dark_guard else 0, 1 if accumulate else 0)
+                       1 if dark_guard else 0, 1 if accumulate else 0, 1 if validated else 0)
 
 
 def trace_occluders(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, light=None, seed=1, sample=0,
@@ -259,6 +263,19 @@ def _workspace(gbuf, params, workspace):
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=gbuf.prim.device)
     return workspace, int(workspace.numel() * workspace.element_size())
+
+
+def validate_pairs(bvh: BVH, gbuf: DeviceGBuffer, occ: Occluders, mode="ao", ao_radius=1.0, light=None,
+                   params: ReuseParams | None = None, workspace=None, stream=None):
+    """First-hit validation bits of the unbiased estimator into `workspace`."""
+    params = params or reuse_params(estimator="unbiased")
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    ws, nbytes = _workspace(gbuf, params, workspace)
+    g, o = gbuf.c(), occ.c()
+    lp = ctypes.byref(light_struct(light)) if light is not None else None
+    _check(lib().ocr_validate_pairs(bvh.h, ctypes.byref(g), ctypes.byref(o), m, float(ao_radius), lp,
+                                    ctypes.byref(params), _dptr(ws), nbytes, _stream(stream)))
+    return ws
 
 
 def reuse_ao(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluders, ao_radius: float, params: ReuseParams,
@@ -308,7 +325,7 @@ def render(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, light=None, 
     for s in range(nsamples):
         trace_occluders(bvh, gbuf, mode, ao_radius, light, seed, first_sample + s, occ, stream)
         p = ReuseParams(params.pattern, params.radius, params.group_n, params.estimator, params.dark_guard,
-                        0 if s == 0 else 1)
+                        0 if s == 0 else 1, 0)
         if mode in ("ao", OCR_AO):
             out = reuse_ao(bvh, gbuf, occ, ao_radius, p, out, ws, stream)
         else:

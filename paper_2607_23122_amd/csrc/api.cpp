@@ -111,12 +111,13 @@ ocr_status reuse_common(const ocr_bvh *bvh, const ocr_gbuffer *g, const ocr_occl
     size_t need = ocr_workspace_bytes(g->width, g->height, p);
     if (need > 0 && (!ws || ws_bytes < need))
         return fail(OCR_ERR_INVALID_ARG, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
-    if (p->estimator == OCR_UNBIASED && !bvh) return fail(OCR_ERR_INVALID_ARG, "unbiased reuse needs the BVH");
+    if (p->estimator == OCR_UNBIASED && !p->validated && !bvh)
+        return fail(OCR_ERR_INVALID_ARG, "unbiased reuse needs the BVH");
     hipStream_t s = (hipStream_t)stream;
     OccView ov{occ->dz, occ->nz, occ->hit};
     GBufView gv = view(g);
     hipError_t e;
-    if (p->estimator == OCR_UNBIASED) {
+    if (p->estimator == OCR_UNBIASED && !p->validated) {
         e = launch_validate(bvh->dev, gv, ov, mode, R, L, *p, (uint32_t *)ws, s);
         if (e != hipSuccess) return hip_fail(e, "validation launch");
     }
@@ -249,6 +250,34 @@ size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params
         return 0;
     if (params->pattern != OCR_WINDOW && params->pattern != OCR_GROUP) return 0;
     return (size_t)width * (size_t)height * (size_t)pair_words(*params) * sizeof(uint32_t);
+}
+
+ocr_status ocr_validate_pairs(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ, int32_t mode,
+                              float ao_radius, const ocr_rect_light *light, const ocr_reuse_params *params,
+                              void *workspace, size_t workspace_bytes, void *stream) {
+    if (!bvh) return fail(OCR_ERR_INVALID_ARG, "bvh is NULL");
+    ocr_status st = check_gbuf(gbuf);
+    if (st) return st;
+    if ((st = check_params(params))) return st;
+    if (params->estimator != OCR_UNBIASED) return fail(OCR_ERR_INVALID_ARG, "validation is for OCR_UNBIASED");
+    if (!occ || !occ->dz || !occ->nz || !occ->hit) return fail(OCR_ERR_INVALID_ARG, "occluder records incomplete");
+    LightF L;
+    std::memset(&L, 0, sizeof L);
+    if (mode == OCR_AO) {
+        if (!(std::isfinite(ao_radius) && ao_radius > 0.0f))
+            return fail(OCR_ERR_INVALID_ARG, "AO radius %g must be finite and > 0", (double)ao_radius);
+    } else if (mode == OCR_SHADOW) {
+        if ((st = make_light(light, L))) return st;
+        ao_radius = 1.0f;
+    } else {
+        return fail(OCR_ERR_INVALID_ARG, "mode %d out of range", mode);
+    }
+    size_t need = ocr_workspace_bytes(gbuf->width, gbuf->height, params);
+    if (!workspace || workspace_bytes < need)
+        return fail(OCR_ERR_INVALID_ARG, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    hipError_t e = launch_validate(bvh->dev, view(gbuf), OccView{occ->dz, occ->nz, occ->hit}, mode, ao_radius, L,
+                                   *params, (uint32_t *)workspace, (hipStream_t)stream);
+    return e == hipSuccess ? OCR_OK : hip_fail(e, "validation launch");
 }
 
 ocr_status ocr_reuse_ao(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ, float ao_radius,
