@@ -52,8 +52,14 @@
 
 #define PI 3.14159265358979323846
 #define GRAZE_REL 0x1p-19     /* edge / end-point band for traces, relative to L */
-#define SUPPORT_BAND 0x1p-14  /* band around the radius / light-rectangle / s=1 / front tests */
-#define COS_BAND 0x1p-18      /* band around a clamped cosine reaching zero */
+/* Bands around FP32-decided thresholds, each a generous multiple of the
+ * FP32 rounding error of the quantity the GPU compares (a few ulps):      */
+#define RADIUS_BAND 0x1p-17   /* |x - z| against R, relative to R           */
+#define FRONT_BAND 0x1p-17    /* cosine of x->z with n_x against 0          */
+#define LIGHT_BAND 0x1p-14    /* y' against the rectangle's edges (units of the
+                                 edge length) and s against 1; y' carries the
+                                 rounding of o - c, up to ~1e-6 of the edge  */
+#define COS_BAND 0x1p-18      /* a clamped cosine reaching zero             */
 #define VALID_ETA 1e-4        /* validation segments stop at t = 1 - eta */
 #define MAX_AMBIG 3
 
@@ -568,7 +574,7 @@ static dens_t density_ao(const double o[3], const double n[3], const double z[3]
     double cos_x = dot3(n, w) / d;   /* <n_x, w_{x->z}> */
     double cos_z = -dot3(nz, w) / d; /* <n_z, w_{z->x}> */
     int fail = 0, amb = 0;
-    if (fabs(d - R) <= SUPPORT_BAND * R) amb = 1;
+    if (fabs(d - R) <= RADIUS_BAND * R) amb = 1;
     else if (!(d <= R)) fail = 1;
     if (fabs(cos_x) <= COS_BAND) amb = 1;
     else if (!(cos_x > 0.0)) fail = 1;
@@ -609,11 +615,10 @@ static dens_t density_shadow(const double o[3], const double n[3], const double 
     double d = sqrt(d2);
     int fail = 0, amb = 0;
     double front = dot3(n, w) / d;
-    if (fabs(front) <= SUPPORT_BAND) amb = 1;
+    if (fabs(front) <= FRONT_BAND) amb = 1;
     else if (!(front > 0.0)) fail = 1;
     double cos_y = -dot3(nl, w) / d; /* <n_y, w_{y'->x}> */
-    if (fabs(cos_y) <= COS_BAND) { r.excl = !fail; return r; }
-    if (!(cos_y > 0.0)) return r;
+    if (!(cos_y > 0.0) && fabs(cos_y) > COS_BAND) return r;
     double co[3];
     sub3(c, o, co);
     double s = dot3(nl, co) / dot3(nl, w); /* y' = o + s w */
@@ -621,12 +626,18 @@ static dens_t density_shadow(const double o[3], const double n[3], const double 
     double yc[3];
     sub3(yp, c, yc);
     double a = dot3(yc, eu) / dot3(eu, eu), b = dot3(yc, ev) / dot3(ev, ev);
-    if (fabs(s - 1.0) <= SUPPORT_BAND * fabs(s)) amb = 1;
+    if (fabs(s - 1.0) <= LIGHT_BAND * fabs(s)) amb = 1;
     else if (!(s > 1.0)) fail = 1;
-    if (fabs(fabs(a) - 0.5) <= SUPPORT_BAND) amb = 1;
+    if (fabs(fabs(a) - 0.5) <= LIGHT_BAND) amb = 1;
     else if (!(fabs(a) <= 0.5)) fail = 1;
-    if (fabs(fabs(b) - 0.5) <= SUPPORT_BAND) amb = 1;
+    if (fabs(fabs(b) - 0.5) <= LIGHT_BAND) amb = 1;
     else if (!(fabs(b) <= 0.5)) fail = 1;
+    /* a ray nearly parallel to the light's plane meets it far outside the
+     * rectangle; only if it still lands on the light is the value unstable */
+    if (!fail && fabs(cos_y) <= COS_BAND) {
+        r.excl = 1;
+        return r;
+    }
     double cos_z = -dot3(nz, w) / d; /* <n_z, w_{z->x}> */
     if (fabs(cos_z) <= COS_BAND) amb = 1;
     else if (!(cos_z > 0.0)) fail = 1;
@@ -659,7 +670,7 @@ static double front_fraction(const double o[3], const double n[3], const double 
     double oc[3];
     sub3(o, c, oc);
     double side = dot3(nl, oc);
-    if (near_edge) *near_edge = fabs(side) <= SUPPORT_BAND * len3(oc);
+    if (near_edge) *near_edge = fabs(side) <= LIGHT_BAND * len3(oc);
     if (!(side > 0.0)) return 0.0;
     double P[4][3], Q[8][3];
     const double su[4] = {-0.5, 0.5, 0.5, -0.5}, sv[4] = {-0.5, -0.5, 0.5, 0.5};
