@@ -51,8 +51,7 @@ __device__ inline float finish(int mode, bool valid, float B, float F, bool dark
 // LDS layout of the window kernel for radius R (dynamic shared memory).
 struct WinLayout {
     int RW, cells, side, dens, hsum, words;
-    bool bits_in_lds;
-    size_t o_off, n_off, sh_off, bits_off, valid_off, miss_off, list_off, B_off, wave_off, total;
+    size_t o_off, n_off, sh_off, valid_off, miss_off, list_off, B_off, wave_off, total;
 };
 
 __host__ __device__ inline size_t lds_take(size_t &off, size_t bytes) {
@@ -69,13 +68,11 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     l.dens = l.side * l.side;
     l.hsum = l.side * (2 * R + 1);
     l.words = words;
-    l.bits_in_lds = unb && words <= 10;
     size_t off = 0;
     l.B_off = lds_take(off, sizeof(unsigned long long) * kWT * kWT);
     l.o_off = lds_take(off, sizeof(float) * 3 * l.cells);
     l.n_off = lds_take(off, sizeof(float) * 3 * l.cells);
     l.sh_off = lds_take(off, mode == OCR_SHADOW ? sizeof(float) * 3 * l.cells : 0);
-    l.bits_off = lds_take(off, l.bits_in_lds ? sizeof(uint32_t) * l.cells * words : 0);
     l.valid_off = lds_take(off, l.cells);
     l.miss_off = lds_take(off, l.cells);
     l.list_off = lds_take(off, 4 * sizeof(int) + sizeof(uint16_t) * l.cells);
@@ -103,7 +100,6 @@ __global__ __launch_bounds__(kRBlock) void reuse_window_kernel(GBufView g, OccVi
     float *s_o = reinterpret_cast<float *>(smem + lay.o_off);    // [3][cells]
     float *s_n = reinterpret_cast<float *>(smem + lay.n_off);    // [3][cells]
     float *s_sh = reinterpret_cast<float *>(smem + lay.sh_off);  // [3][cells]
-    uint32_t *s_bits = reinterpret_cast<uint32_t *>(smem + lay.bits_off);
     uint8_t *s_valid = smem + lay.valid_off;
     uint8_t *s_miss = smem + lay.miss_off;
     int *s_count = reinterpret_cast<int *>(smem + lay.list_off);
@@ -148,9 +144,6 @@ __global__ __launch_bounds__(kRBlock) void reuse_window_kernel(GBufView g, OccVi
             s_sh[CELLS + c] = rk.ak;
             s_sh[2 * CELLS + c] = rk.bk;
         }
-        if (UNB && lay.bits_in_lds) {
-            for (int q = 0; q < words; ++q) s_bits[c * words + q] = valid ? bits[gi * words + q] : 0u;
-        }
         s_valid[c] = valid;
         s_miss[c] = valid && hit == OCR_HIT_MISS;
         if (valid && hit < OCR_HIT_SELF) s_list[atomicAdd(s_count, 1)] = (uint16_t)c;
@@ -185,16 +178,9 @@ __global__ __launch_bounds__(kRBlock) void reuse_window_kernel(GBufView g, OccVi
                     p = dens_shadow(w, nk, rk, nzj, L);
                 }
                 if (UNB && p > 0.0f) {
-                    // receiver k's bit for the candidate at offset j - k = (-dx, -dy)
-                    const int bidx = (-dy + D) * SIDE + (-dx + D);
-                    uint32_t wv;
-                    if (lay.bits_in_lds) {
-                        wv = s_bits[kc * words + (bidx >> 5)];
-                    } else {
-                        const int64_t gk = (int64_t)(y0 + ky) * g.w + (x0 + kx);
-                        wv = bits[gk * words + (bidx >> 5)];
-                    }
-                    if (!((wv >> (bidx & 31)) & 1u)) p = 0.0f;
+                    // candidate j's validation bit for the receiver at offset k - j = (dx, dy): bit q
+                    const uint32_t wv = bits[gj * words + (q >> 5)];
+                    if (!((wv >> (q & 31)) & 1u)) p = 0.0f;
                 }
             }
             w_dens[q] = p;
@@ -325,8 +311,8 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
             rel_vec(oj, o, dzj, w);
             p = MODE == OCR_AO ? dens_ao(w, n, nzj, R2) : dens_shadow(w, n, rk, nzj, L);
             if (UNB && p > 0.0f) {
-                const int bidx = (my - ly + D) * SIDE + (mx - lx + D);
-                if (!((s_bits[tid][bidx >> 5] >> (bidx & 31)) & 1u)) p = 0.0f;
+                const int bidx = (ly - my + D) * SIDE + (lx - mx + D);
+                if (!((s_bits[jt][bidx >> 5] >> (bidx & 31)) & 1u)) p = 0.0f;
             }
         }
         s_p[tid][m] = p;

@@ -83,74 +83,156 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g
     }
 }
 
-// Receiver-centric first-hit validation.  Lane = receiver k; for every
-// candidate j of the pair neighbourhood (offsets j - k in [-D, D]^2, same
-// group for the group pattern) whose density at k is positive, an any-hit
-// segment o_k -> z_j over t in (0, 1 - 1e-4), ignoring z_j's triangle and
-// k's own, decides Occ(x_k, z_j).  Bit (dy+D)(2D+1) + (dx+D) of k's words
-// is set when z_j is the first hit from o_k.
+// First-hit validation (Eq. occ-first-hit) for the sliding window, one
+// wavefront per candidate j: lane q takes the receiver k = j + (q % side - D,
+// q / side - D), side = 2D + 1, D = 2r; when the density of z_j at k is
+// positive, an any-hit segment o_k -> z_j over t in (0, 1 - 1e-4), ignoring
+// z_j's triangle and k's own, decides Occ(x_k, z_j).  All segments of a wave
+// end at the same point, so their traversals stay coherent.  Bit q of j's
+// words is set when z_j is the first hit from o_k (k == j: always).
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void validate_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
-                                                          LightF L, int D, int pattern, int gw, int gh, int words,
-                                                          uint32_t *bits, int tiles_x, int ntiles) {
+__global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
+                                                                 LightF L, int D, int words, uint32_t *bits,
+                                                                 int tiles_x, int ntiles) {
     __shared__ uint32_t stack[kStackLds * kBlock];
+    __shared__ uint32_t s_list[kBlock];
+    __shared__ int s_count;
     int tx, ty;
     tile_of_block(tiles_x, ntiles, tx, ty);
     if (ty * tiles_x + tx >= ntiles) return;
-    int px, py;
-    pixel_of_thread(tx, ty, px, py);
-    if (px >= g.w || py >= g.h) return;
-    int64_t k = (int64_t)py * g.w + px;
-    uint32_t *mine = bits + k * words;
-    uint32_t primk = g.prim[k];
-    if (primk == OCR_HIT_MISS) {
-        for (int q = 0; q < words; ++q) mine[q] = 0u;
-        return;
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
+    {
+        int px, py;
+        pixel_of_thread(tx, ty, px, py);
+        if (px < g.w && py < g.h) {
+            int64_t j = (int64_t)py * g.w + px;
+            if (occ.hit[j] < OCR_HIT_SELF) s_list[atomicAdd(&s_count, 1)] = (uint32_t)j;
+            else
+                for (int q = 0; q < words; ++q) bits[j * words + q] = 0u;
+        }
     }
-    float xk[3], nk[3], ok[3];
-    load3(g.pos, k, xk);
-    load3(g.nrm, k, nk);
-    offset_point(xk, nk, ok);
-    RecvShadow rk = {0.f, 0.f, 0.f};
-    if (MODE == OCR_SHADOW) rk = recv_shadow(ok, L);
-    int side = 2 * D + 1;
-    uint32_t word = 0u;
-    int widx = 0;
-    for (int idx = 0; idx < side * side; ++idx) {
-        int dy = idx / side - D, dx = idx % side - D;
-        int jx = px + dx, jy = py + dy;
-        bool bit = false;
-        bool inside = jx >= 0 && jx < g.w && jy >= 0 && jy < g.h;
-        if (inside && pattern == OCR_GROUP) inside = (jx / gw == px / gw) && (jy / gh == py / gh);
-        if (inside) {
-            int64_t j = (int64_t)jy * g.w + jx;
-            uint32_t hj = occ.hit[j];
-            if (j == k) {
-                bit = true;
-            } else if (hj < OCR_HIT_SELF) {
-                float xj[3], nj[3], oj[3], dzj[3], nzj[3], w[3];
-                load3(g.pos, j, xj);
-                load3(g.nrm, j, nj);
-                offset_point(xj, nj, oj);
-                load3(occ.dz, j, dzj);
-                load3(occ.nz, j, nzj);
-                rel_vec(oj, ok, dzj, w);
-                float p = MODE == OCR_AO ? dens_ao(w, nk, nzj, R2) : dens_shadow(w, nk, rk, nzj, L);
-                if (p > 0.0f) {
-                    TRay r;
-                    make_ray(ok, w, hj, primk, r);
-                    Hit h = traverse<true, false>(bvh, r, 1.0f - 1e-4f, stack + threadIdx.x, kBlock);
-                    bit = h.tri == OCR_HIT_MISS;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int side = 2 * D + 1, npairs = side * side;
+    const int ncand = s_count;
+    for (int li = wave; li < ncand; li += kBlock / 64) {
+        const int64_t j = __builtin_amdgcn_readfirstlane((int)s_list[li]);
+        const int jx = (int)(j % g.w), jy = (int)(j / g.w);
+        const uint32_t hj = occ.hit[j];
+        float xj[3], nj[3], oj[3], dzj[3], nzj[3];
+        load3(g.pos, j, xj);
+        load3(g.nrm, j, nj);
+        offset_point(xj, nj, oj);
+        load3(occ.dz, j, dzj);
+        load3(occ.nz, j, nzj);
+        for (int base = 0; base < npairs; base += 64) {
+            const int q = base + lane;
+            bool bit = false;
+            if (q < npairs) {
+                const int kx = jx + q % side - D, ky = jy + q / side - D;
+                if (kx >= 0 && kx < g.w && ky >= 0 && ky < g.h) {
+                    const int64_t k = (int64_t)ky * g.w + kx;
+                    const uint32_t primk = g.prim[k];
+                    if (k == j) {
+                        bit = true;
+                    } else if (primk != OCR_HIT_MISS) {
+                        float xk[3], nk[3], ok[3], w[3];
+                        load3(g.pos, k, xk);
+                        load3(g.nrm, k, nk);
+                        offset_point(xk, nk, ok);
+                        rel_vec(oj, ok, dzj, w);
+                        float p;
+                        if (MODE == OCR_AO) {
+                            p = dens_ao(w, nk, nzj, R2);
+                        } else {
+                            RecvShadow rk = recv_shadow(ok, L);
+                            p = dens_shadow(w, nk, rk, nzj, L);
+                        }
+                        if (p > 0.0f) {
+                            TRay r;
+                            make_ray(ok, w, hj, primk, r);
+                            Hit h = traverse<true, false>(bvh, r, 1.0f - 1e-4f, stack + threadIdx.x, kBlock);
+                            bit = h.tri == OCR_HIT_MISS;
+                        }
+                    }
                 }
             }
-        }
-        if (bit) word |= 1u << (idx & 31);
-        if ((idx & 31) == 31 || idx == side * side - 1) {
-            mine[widx++] = word;
-            word = 0u;
+            const unsigned long long m = __ballot(bit);
+            const int w0 = base >> 5;
+            if (lane == 0 && w0 < words) bits[j * words + w0] = (uint32_t)m;
+            if (lane == 1 && w0 + 1 < words) bits[j * words + w0 + 1] = (uint32_t)(m >> 32);
         }
     }
-    for (; widx < words; ++widx) mine[widx] = 0u;
+}
+
+// First-hit validation for fixed groups: one lane per (candidate m, receiver
+// k) pair of a group; block = 32 x 8 pixels, which the group shapes tile.
+// Bit (ky - my + D)(2D+1) + (kx - mx + D) of m's words, D = the group extent.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void validate_group_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
+                                                                LightF L, int N, int gw, int gh, int D, int words,
+                                                                uint32_t *bits, int tiles_x, int ntiles) {
+    __shared__ uint32_t stack[kStackLds * kBlock];
+    __shared__ uint32_t s_words[kBlock * 2];
+    int tx, ty;
+    tile_of_block(tiles_x, ntiles, tx, ty);
+    if (ty * tiles_x + tx >= ntiles) return;
+    const int tid = threadIdx.x;
+    s_words[2 * tid] = 0u;
+    s_words[2 * tid + 1] = 0u;
+    __syncthreads();
+    const int side = 2 * D + 1;
+    const int ngroups = (32 / gw) * (8 / gh);
+    const int npairs = ngroups * N * N;
+    for (int P = tid; P < npairs; P += kBlock) {
+        const int grp = P / (N * N), pr = P % (N * N), m = pr / N, kk = pr % N;
+        const int gx0 = (grp % (32 / gw)) * gw, gy0 = (grp / (32 / gw)) * gh;
+        const int mlx = gx0 + m % gw, mly = gy0 + m / gw, klx = gx0 + kk % gw, kly = gy0 + kk / gw;
+        const int mx = tx * 32 + mlx, my = ty * 8 + mly, kx = tx * 32 + klx, ky = ty * 8 + kly;
+        if (mx >= g.w || my >= g.h || kx >= g.w || ky >= g.h) continue;
+        const int64_t j = (int64_t)my * g.w + mx, k = (int64_t)ky * g.w + kx;
+        const uint32_t hj = occ.hit[j], primk = g.prim[k];
+        if (hj >= OCR_HIT_SELF || primk == OCR_HIT_MISS) continue;
+        bool bit = false;
+        if (j == k) {
+            bit = true;
+        } else {
+            float xj[3], nj[3], oj[3], dzj[3], nzj[3], xk[3], nk[3], ok[3], w[3];
+            load3(g.pos, j, xj);
+            load3(g.nrm, j, nj);
+            offset_point(xj, nj, oj);
+            load3(occ.dz, j, dzj);
+            load3(occ.nz, j, nzj);
+            load3(g.pos, k, xk);
+            load3(g.nrm, k, nk);
+            offset_point(xk, nk, ok);
+            rel_vec(oj, ok, dzj, w);
+            float p;
+            if (MODE == OCR_AO) {
+                p = dens_ao(w, nk, nzj, R2);
+            } else {
+                RecvShadow rk = recv_shadow(ok, L);
+                p = dens_shadow(w, nk, rk, nzj, L);
+            }
+            if (p > 0.0f) {
+                TRay r;
+                make_ray(ok, w, hj, primk, r);
+                Hit h = traverse<true, false>(bvh, r, 1.0f - 1e-4f, stack + threadIdx.x, kBlock);
+                bit = h.tri == OCR_HIT_MISS;
+            }
+        }
+        if (bit) {
+            const int bidx = (kly - mly + D) * side + (klx - mlx + D);
+            atomicOr(&s_words[2 * (mly * 32 + mlx) + (bidx >> 5)], 1u << (bidx & 31));
+        }
+    }
+    __syncthreads();
+    const int px = tx * 32 + (tid & 31), py = ty * 8 + (tid >> 5);
+    if (px < g.w && py < g.h) {
+        const int64_t i = (int64_t)py * g.w + px;
+        for (int q = 0; q < words; ++q) bits[i * words + q] = s_words[2 * tid + q];
+    }
 }
 
 template <int MODE>
@@ -218,17 +300,29 @@ hipError_t launch_trace(const DeviceBVH &bvh, const GBufView &g, int mode, float
 
 hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, int mode, float R,
                            const LightF &L, const ocr_reuse_params &p, uint32_t *bits, hipStream_t st) {
-    int tiles_x;
-    int nt = ntiles_for(g, tiles_x);
-    dim3 grid(grid_for(nt)), block(kBlock);
-    int D = pair_extent(p), words = pair_words(p), gw = 1, gh = 1;
-    if (p.pattern == OCR_GROUP) group_dims(p.group_n, gw, gh);
-    if (mode == OCR_AO)
-        hipLaunchKernelGGL(validate_kernel<OCR_AO>, grid, block, 0, st, bvh, g, occ, R * R, L, D, p.pattern, gw, gh,
-                           words, bits, tiles_x, nt);
-    else
-        hipLaunchKernelGGL(validate_kernel<OCR_SHADOW>, grid, block, 0, st, bvh, g, occ, R * R, L, D, p.pattern, gw,
-                           gh, words, bits, tiles_x, nt);
+    const int D = pair_extent(p), words = pair_words(p);
+    if (p.pattern == OCR_WINDOW) {
+        int tiles_x;
+        int nt = ntiles_for(g, tiles_x);
+        dim3 grid(grid_for(nt)), block(kBlock);
+        if (mode == OCR_AO)
+            hipLaunchKernelGGL(validate_window_kernel<OCR_AO>, grid, block, 0, st, bvh, g, occ, R * R, L, D, words,
+                               bits, tiles_x, nt);
+        else
+            hipLaunchKernelGGL(validate_window_kernel<OCR_SHADOW>, grid, block, 0, st, bvh, g, occ, R * R, L, D,
+                               words, bits, tiles_x, nt);
+    } else {
+        int gw, gh;
+        group_dims(p.group_n, gw, gh);
+        int tiles_x = (g.w + 31) / 32, tiles_y = (g.h + 7) / 8, nt = tiles_x * tiles_y;
+        dim3 grid(grid_for(nt)), block(kBlock);
+        if (mode == OCR_AO)
+            hipLaunchKernelGGL(validate_group_kernel<OCR_AO>, grid, block, 0, st, bvh, g, occ, R * R, L, p.group_n,
+                               gw, gh, D, words, bits, tiles_x, nt);
+        else
+            hipLaunchKernelGGL(validate_group_kernel<OCR_SHADOW>, grid, block, 0, st, bvh, g, occ, R * R, L,
+                               p.group_n, gw, gh, D, words, bits, tiles_x, nt);
+    }
     return hipGetLastError();
 }
 
