@@ -94,7 +94,7 @@ template <int MODE>
 __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
                                                                  LightF L, int D, int words, uint32_t *bits,
                                                                  int tiles_x, int ntiles) {
-    __shared__ uint32_t stack[kStackLds * kBlock];
+    __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
     __shared__ uint32_t s_list[kBlock];
     __shared__ int s_count;
     int tx, ty;
@@ -128,14 +128,16 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
         load3(occ.nz, j, nzj);
         for (int base = 0; base < npairs; base += 64) {
             const int q = base + lane;
-            bool bit = false;
+            bool self = false, want = false;
+            TRay r;
+            r.ign0 = r.ign1 = OCR_HIT_MISS;
             if (q < npairs) {
                 const int kx = jx + q % side - D, ky = jy + q / side - D;
                 if (kx >= 0 && kx < g.w && ky >= 0 && ky < g.h) {
                     const int64_t k = (int64_t)ky * g.w + kx;
                     const uint32_t primk = g.prim[k];
                     if (k == j) {
-                        bit = true;
+                        self = true;
                     } else if (primk != OCR_HIT_MISS) {
                         float xk[3], nk[3], ok[3], w[3];
                         load3(g.pos, k, xk);
@@ -150,14 +152,14 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
                             p = dens_shadow(w, nk, rk, nzj, L);
                         }
                         if (p > 0.0f) {
-                            TRay r;
                             make_ray(ok, w, hj, primk, r);
-                            Hit h = traverse<true, false>(bvh, r, 1.0f - 1e-4f, stack + threadIdx.x, kBlock);
-                            bit = h.tri == OCR_HIT_MISS;
+                            want = true;
                         }
                     }
                 }
             }
+            const bool blocked = traverse_wave_any(bvh, r, 1.0f - 1e-4f, want, wstack[wave]);
+            const bool bit = self || (want && !blocked);
             const unsigned long long m = __ballot(bit);
             const int w0 = base >> 5;
             if (lane == 0 && w0 < words) bits[j * words + w0] = (uint32_t)m;

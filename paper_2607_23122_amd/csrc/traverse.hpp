@@ -206,3 +206,96 @@ __device__ inline void oriented_normal(const DeviceBVH &bvh, uint32_t leaf_tri, 
 }
 
 }  // namespace ocr
+
+namespace ocr {
+
+// Read-only view of the BVH in the constant address space: with a
+// wave-uniform index, node and triangle fetches become scalar loads.
+typedef __attribute__((address_space(4))) const float cfloat;
+typedef __attribute__((address_space(4))) const uint32_t cuint;
+
+// Wave-coherent any-hit traversal.  Every lane of the wave must call it
+// (wave-uniform control flow); lanes with want == false only ride along.
+// The wave walks one node order -- the union of its active rays' paths --
+// from a wave-uniform stack in LDS (`wstack`, kStackTotal entries for this
+// wave); each lane tests its own ray against the shared node's four boxes
+// and the leaf's triangles, and drops out as soon as its segment is blocked.
+// Returns whether this lane's segment (t in (0, tmax)) is blocked.
+__device__ inline bool traverse_wave_any(const DeviceBVH &bvh, const TRay &r, float tmax, bool want,
+                                         uint32_t *wstack) {
+    bool active = want;
+    bool blocked = false;
+    if (__ballot(active) == 0ull) return false;
+    const float grow = 1.0f + 0x1p-20f;
+    int sp = 0;
+    uint32_t node = 0;
+    for (;;) {
+        if (!(node & kLeafBit)) {
+            const cfloat *np = (const cfloat *)(bvh.nodes + node);
+            const cuint *cp = (const cuint *)(bvh.nodes + node);
+            float lxs[4], hxs[4], lys[4], hys[4], lzs[4], hzs[4];
+            uint32_t chs[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                lxs[i] = np[i];
+                hxs[i] = np[4 + i];
+                lys[i] = np[8 + i];
+                hys[i] = np[12 + i];
+                lzs[i] = np[16 + i];
+                hzs[i] = np[20 + i];
+                chs[i] = cp[24 + i];
+            }
+            uint32_t next = kEmpty;
+#pragma unroll
+            for (int i = 3; i >= 0; --i) {
+                bool hit = false;
+                if (active) {
+                    float t0x = (lxs[i] - r.o[0]) * r.inv[0], t1x = (hxs[i] - r.o[0]) * r.inv[0];
+                    float t0y = (lys[i] - r.o[1]) * r.inv[1], t1y = (hys[i] - r.o[1]) * r.inv[1];
+                    float t0z = (lzs[i] - r.o[2]) * r.inv[2], t1z = (hzs[i] - r.o[2]) * r.inv[2];
+                    float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+                    float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
+                    tfar = fminf(tfar, tmax * grow);
+                    hit = tnear <= tfar;
+                }
+                if (chs[i] != kEmpty && __ballot(hit) != 0ull) {
+                    // children pushed in reverse so that child 0 is visited first
+                    if (next != kEmpty) {
+                        wstack[sp] = next;
+                        ++sp;
+                    }
+                    next = chs[i];
+                }
+            }
+            if (next != kEmpty) {
+                node = __builtin_amdgcn_readfirstlane(next);
+                continue;
+            }
+        } else {
+            const uint32_t first = node & 0x07FFFFFFu;
+            const uint32_t count = ((node >> 27) & 0xFu) + 1u;
+            for (uint32_t q = 0; q < count; ++q) {
+                const cfloat *tp = (const cfloat *)(bvh.tris + 3 * (size_t)(first + q));
+                float4 v0, v1, v2;
+                v0.x = tp[0]; v0.y = tp[1]; v0.z = tp[2]; v0.w = tp[3];
+                v1.x = tp[4]; v1.y = tp[5]; v1.z = tp[6]; v1.w = tp[7];
+                v2.x = tp[8]; v2.y = tp[9]; v2.z = tp[10]; v2.w = tp[11];
+                const uint32_t id = __float_as_uint(v0.w);
+                if (active && id != r.ign0 && id != r.ign1) {
+                    const float t = tri_hit(r, v0, v1, v2);
+                    if (t > 0.0f && t < tmax) {
+                        blocked = true;
+                        active = false;
+                    }
+                }
+            }
+            if (__ballot(active) == 0ull) return blocked;
+        }
+        if (sp == 0) break;
+        --sp;
+        node = __builtin_amdgcn_readfirstlane(wstack[sp]);
+    }
+    return blocked;
+}
+
+}  // namespace ocr
