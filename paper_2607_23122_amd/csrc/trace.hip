@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g
 // z_j's triangle and k's own, decides Occ(x_k, z_j).  All segments of a wave
 // end at the same point, so their traversals stay coherent.  Bit q of j's
 // words is set when z_j is the first hit from o_k (k == j: always).
-template <int MODE>
+template <int MODE, int NR>
 __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
                                                                  LightF L, int D, int words, uint32_t *bits,
                                                                  int tiles_x, int ntiles) {
@@ -126,44 +126,53 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
         offset_point(xj, nj, oj);
         load3(occ.dz, j, dzj);
         load3(occ.nz, j, nzj);
-        for (int base = 0; base < npairs; base += 64) {
-            const int q = base + lane;
-            bool self = false, want = false;
-            TRay r;
-            r.ign0 = r.ign1 = OCR_HIT_MISS;
-            if (q < npairs) {
-                const int kx = jx + q % side - D, ky = jy + q / side - D;
-                if (kx >= 0 && kx < g.w && ky >= 0 && ky < g.h) {
-                    const int64_t k = (int64_t)ky * g.w + kx;
-                    const uint32_t primk = g.prim[k];
-                    if (k == j) {
-                        self = true;
-                    } else if (primk != OCR_HIT_MISS) {
-                        float xk[3], nk[3], ok[3], w[3];
-                        load3(g.pos, k, xk);
-                        load3(g.nrm, k, nk);
-                        offset_point(xk, nk, ok);
-                        rel_vec(oj, ok, dzj, w);
-                        float p;
-                        if (MODE == OCR_AO) {
-                            p = dens_ao(w, nk, nzj, R2);
-                        } else {
-                            RecvShadow rk = recv_shadow(ok, L);
-                            p = dens_shadow(w, nk, rk, nzj, L);
-                        }
-                        if (p > 0.0f) {
-                            make_ray(ok, w, hj, primk, r);
-                            want = true;
+        // pairs base .. base + 64*NR - 1 in one coherent walk; lane takes pair base + 64*s + lane
+        for (int base = 0; base < npairs; base += 64 * NR) {
+            TRay r[NR];
+            bool want[NR], self[NR], blocked[NR];
+#pragma unroll
+            for (int sl = 0; sl < NR; ++sl) {
+                const int q = base + 64 * sl + lane;
+                want[sl] = false;
+                self[sl] = false;
+                r[sl].ign0 = r[sl].ign1 = OCR_HIT_MISS;
+                if (q < npairs) {
+                    const int kx = jx + q % side - D, ky = jy + q / side - D;
+                    if (kx >= 0 && kx < g.w && ky >= 0 && ky < g.h) {
+                        const int64_t k = (int64_t)ky * g.w + kx;
+                        const uint32_t primk = g.prim[k];
+                        if (k == j) {
+                            self[sl] = true;
+                        } else if (primk != OCR_HIT_MISS) {
+                            float xk[3], nk[3], ok[3], w[3];
+                            load3(g.pos, k, xk);
+                            load3(g.nrm, k, nk);
+                            offset_point(xk, nk, ok);
+                            rel_vec(oj, ok, dzj, w);
+                            float p;
+                            if (MODE == OCR_AO) {
+                                p = dens_ao(w, nk, nzj, R2);
+                            } else {
+                                RecvShadow rk = recv_shadow(ok, L);
+                                p = dens_shadow(w, nk, rk, nzj, L);
+                            }
+                            if (p > 0.0f) {
+                                make_ray(ok, w, hj, primk, r[sl]);
+                                want[sl] = true;
+                            }
                         }
                     }
                 }
             }
-            const bool blocked = traverse_wave_any(bvh, r, 1.0f - 1e-4f, want, wstack[wave]);
-            const bool bit = self || (want && !blocked);
-            const unsigned long long m = __ballot(bit);
-            const int w0 = base >> 5;
-            if (lane == 0 && w0 < words) bits[j * words + w0] = (uint32_t)m;
-            if (lane == 1 && w0 + 1 < words) bits[j * words + w0 + 1] = (uint32_t)(m >> 32);
+            traverse_wave_any<NR>(bvh, r, 1.0f - 1e-4f, want, blocked, wstack[wave]);
+#pragma unroll
+            for (int sl = 0; sl < NR; ++sl) {
+                const bool bit = self[sl] || (want[sl] && !blocked[sl]);
+                const unsigned long long m = __ballot(bit);
+                const int w0 = (base + 64 * sl) >> 5;
+                if (lane == 0 && w0 < words) bits[j * words + w0] = (uint32_t)m;
+                if (lane == 1 && w0 + 1 < words) bits[j * words + w0 + 1] = (uint32_t)(m >> 32);
+            }
         }
     }
 }
@@ -307,12 +316,24 @@ hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccVie
         int tiles_x;
         int nt = ntiles_for(g, tiles_x);
         dim3 grid(grid_for(nt)), block(kBlock);
-        if (mode == OCR_AO)
-            hipLaunchKernelGGL(validate_window_kernel<OCR_AO>, grid, block, 0, st, bvh, g, occ, R * R, L, D, words,
-                               bits, tiles_x, nt);
-        else
-            hipLaunchKernelGGL(validate_window_kernel<OCR_SHADOW>, grid, block, 0, st, bvh, g, occ, R * R, L, D,
-                               words, bits, tiles_x, nt);
+        // all (4r+1)^2 segments of a candidate in one walk: ceil(side^2 / 64) per lane (up to 5; larger
+        // windows walk in several passes)
+        const int side = 2 * D + 1, nr = (side * side + 63) / 64;
+#define OCR_VAL(M, N)                                                                                               \
+    hipLaunchKernelGGL((validate_window_kernel<M, N>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, \
+                       tiles_x, nt)
+        if (mode == OCR_AO) {
+            if (nr <= 1) OCR_VAL(OCR_AO, 1);
+            else if (nr == 2) OCR_VAL(OCR_AO, 2);
+            else if (nr == 3) OCR_VAL(OCR_AO, 3);
+            else OCR_VAL(OCR_AO, 5);
+        } else {
+            if (nr <= 1) OCR_VAL(OCR_SHADOW, 1);
+            else if (nr == 2) OCR_VAL(OCR_SHADOW, 2);
+            else if (nr == 3) OCR_VAL(OCR_SHADOW, 3);
+            else OCR_VAL(OCR_SHADOW, 5);
+        }
+#undef OCR_VAL
     } else {
         int gw, gh;
         group_dims(p.group_n, gw, gh);

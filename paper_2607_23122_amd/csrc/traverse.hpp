@@ -214,18 +214,27 @@ namespace ocr {
 typedef __attribute__((address_space(4))) const float cfloat;
 typedef __attribute__((address_space(4))) const uint32_t cuint;
 
-// Wave-coherent any-hit traversal.  Every lane of the wave must call it
-// (wave-uniform control flow); lanes with want == false only ride along.
-// The wave walks one node order -- the union of its active rays' paths --
-// from a wave-uniform stack in LDS (`wstack`, kStackTotal entries for this
-// wave); each lane tests its own ray against the shared node's four boxes
-// and the leaf's triangles, and drops out as soon as its segment is blocked.
-// Returns whether this lane's segment (t in (0, tmax)) is blocked.
-__device__ inline bool traverse_wave_any(const DeviceBVH &bvh, const TRay &r, float tmax, bool want,
-                                         uint32_t *wstack) {
-    bool active = want;
-    bool blocked = false;
-    if (__ballot(active) == 0ull) return false;
+// Wave-coherent any-hit traversal of up to NR segments per lane.  Every lane
+// of the wave must call it (wave-uniform control flow); slots with
+// want[q] == false only ride along.  The wave walks one node order -- the
+// union of its active segments' paths -- from a wave-uniform stack in LDS
+// (`wstack`, kStackTotal entries for this wave); node and triangle fetches
+// use a wave-uniform index (scalar loads); each lane tests its own segments
+// against the shared node's four boxes and the leaf's triangles and drops a
+// segment as soon as it is blocked.  blocked[q] reports segment q (t in
+// (0, tmax)).
+template <int NR>
+__device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[NR], float tmax,
+                                         const bool (&want)[NR], bool (&blocked)[NR], uint32_t *wstack) {
+    bool active[NR];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        active[q] = want[q];
+        blocked[q] = false;
+        any |= active[q];
+    }
+    if (__ballot(any) == 0ull) return;
     const float grow = 1.0f + 0x1p-20f;
     int sp = 0;
     uint32_t node = 0;
@@ -249,14 +258,19 @@ __device__ inline bool traverse_wave_any(const DeviceBVH &bvh, const TRay &r, fl
 #pragma unroll
             for (int i = 3; i >= 0; --i) {
                 bool hit = false;
-                if (active) {
-                    float t0x = (lxs[i] - r.o[0]) * r.inv[0], t1x = (hxs[i] - r.o[0]) * r.inv[0];
-                    float t0y = (lys[i] - r.o[1]) * r.inv[1], t1y = (hys[i] - r.o[1]) * r.inv[1];
-                    float t0z = (lzs[i] - r.o[2]) * r.inv[2], t1z = (hzs[i] - r.o[2]) * r.inv[2];
-                    float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-                    float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
-                    tfar = fminf(tfar, tmax * grow);
-                    hit = tnear <= tfar;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    if (active[q]) {
+                        const TRay &rq = r[q];
+                        float t0x = (lxs[i] - rq.o[0]) * rq.inv[0], t1x = (hxs[i] - rq.o[0]) * rq.inv[0];
+                        float t0y = (lys[i] - rq.o[1]) * rq.inv[1], t1y = (hys[i] - rq.o[1]) * rq.inv[1];
+                        float t0z = (lzs[i] - rq.o[2]) * rq.inv[2], t1z = (hzs[i] - rq.o[2]) * rq.inv[2];
+                        float tnear =
+                            fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+                        float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
+                        tfar = fminf(tfar, tmax * grow);
+                        hit |= tnear <= tfar;
+                    }
                 }
                 if (chs[i] != kEmpty && __ballot(hit) != 0ull) {
                     // children pushed in reverse so that child 0 is visited first
@@ -274,28 +288,33 @@ __device__ inline bool traverse_wave_any(const DeviceBVH &bvh, const TRay &r, fl
         } else {
             const uint32_t first = node & 0x07FFFFFFu;
             const uint32_t count = ((node >> 27) & 0xFu) + 1u;
-            for (uint32_t q = 0; q < count; ++q) {
-                const cfloat *tp = (const cfloat *)(bvh.tris + 3 * (size_t)(first + q));
+            for (uint32_t t3 = 0; t3 < count; ++t3) {
+                const cfloat *tp = (const cfloat *)(bvh.tris + 3 * (size_t)(first + t3));
                 float4 v0, v1, v2;
                 v0.x = tp[0]; v0.y = tp[1]; v0.z = tp[2]; v0.w = tp[3];
                 v1.x = tp[4]; v1.y = tp[5]; v1.z = tp[6]; v1.w = tp[7];
                 v2.x = tp[8]; v2.y = tp[9]; v2.z = tp[10]; v2.w = tp[11];
                 const uint32_t id = __float_as_uint(v0.w);
-                if (active && id != r.ign0 && id != r.ign1) {
-                    const float t = tri_hit(r, v0, v1, v2);
-                    if (t > 0.0f && t < tmax) {
-                        blocked = true;
-                        active = false;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    if (active[q] && id != r[q].ign0 && id != r[q].ign1) {
+                        const float t = tri_hit(r[q], v0, v1, v2);
+                        if (t > 0.0f && t < tmax) {
+                            blocked[q] = true;
+                            active[q] = false;
+                        }
                     }
                 }
             }
-            if (__ballot(active) == 0ull) return blocked;
+            bool still = false;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) still |= active[q];
+            if (__ballot(still) == 0ull) return;
         }
         if (sp == 0) break;
         --sp;
         node = __builtin_amdgcn_readfirstlane(wstack[sp]);
     }
-    return blocked;
 }
 
 }  // namespace ocr
