@@ -249,7 +249,10 @@ size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params
         params->group_n != 8)
         return 0;
     if (params->pattern != OCR_WINDOW && params->pattern != OCR_GROUP) return 0;
-    return (size_t)width * (size_t)height * (size_t)pair_words(*params) * sizeof(uint32_t);
+    size_t bytes = (size_t)width * (size_t)height * (size_t)pair_words(*params) * sizeof(uint32_t);
+    // window validation also keeps a candidate list: a count and one index per pixel
+    if (params->pattern == OCR_WINDOW) bytes += ((size_t)width * (size_t)height + 1) * sizeof(uint32_t);
+    return bytes;
 }
 
 ocr_status ocr_validate_pairs(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ, int32_t mode,

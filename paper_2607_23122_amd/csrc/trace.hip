@@ -90,34 +90,57 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g
 // z_j's triangle and k's own, decides Occ(x_k, z_j).  All segments of a wave
 // end at the same point, so their traversals stay coherent.  Bit q of j's
 // words is set when z_j is the first hit from o_k (k == j: always).
-template <int MODE, int NR>
-__global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
-                                                                 LightF L, int D, int words, uint32_t *bits,
-                                                                 int tiles_x, int ntiles) {
-    __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
-    __shared__ uint32_t s_list[kBlock];
-    __shared__ int s_count;
+// Candidate list for the window validation: every pixel whose ray found an
+// occluder, appended in (per-wave) tile order; other pixels' validation words
+// are cleared here.  list[0] holds the count, list[1 + n] the pixel index.
+__global__ __launch_bounds__(kBlock) void clear_count_kernel(uint32_t *list) {
+    if (threadIdx.x == 0) list[0] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ, int words, uint32_t *bits,
+                                                         uint32_t *list, int tiles_x, int ntiles) {
     int tx, ty;
     tile_of_block(tiles_x, ntiles, tx, ty);
     if (ty * tiles_x + tx >= ntiles) return;
-    if (threadIdx.x == 0) s_count = 0;
-    __syncthreads();
-    {
-        int px, py;
-        pixel_of_thread(tx, ty, px, py);
-        if (px < g.w && py < g.h) {
-            int64_t j = (int64_t)py * g.w + px;
-            if (occ.hit[j] < OCR_HIT_SELF) s_list[atomicAdd(&s_count, 1)] = (uint32_t)j;
-            else
-                for (int q = 0; q < words; ++q) bits[j * words + q] = 0u;
-        }
-    }
-    __syncthreads();
+    int px, py;
+    pixel_of_thread(tx, ty, px, py);
+    const bool inside = px < g.w && py < g.h;
+    const int64_t j = inside ? (int64_t)py * g.w + px : 0;
+    const bool cand = inside && occ.hit[j] < OCR_HIT_SELF;
+    if (inside && !cand)
+        for (int q = 0; q < words; ++q) bits[j * words + q] = 0u;
+    const unsigned long long m = __ballot(cand);
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (lane == 0 && m) base = atomicAdd(list, (uint32_t)__popcll(m));
+    base = __shfl(base, 0);
+    if (cand) list[1 + base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)j;
+}
+
+// First-hit validation (Eq. occ-first-hit) for the sliding window, one
+// wavefront per candidate j: lane q takes the receiver k = j + (q % side - D,
+// q / side - D), side = 2D + 1, D = 2r; when the density of z_j at k is
+// positive, an any-hit segment o_k -> z_j over t in (0, 1 - 1e-4), ignoring
+// z_j's triangle and k's own, decides Occ(x_k, z_j).  The wave walks the BVH
+// once per 64 receivers along the union of their segments, which all end at
+// z_j (traverse_wave_any).  Bit q of j's words is set when z_j is the first
+// hit from o_k (k == j: always).  Persistent grid: the candidates are split
+// into 8 contiguous ranges, one per XCD (blocks are dealt to XCDs
+// round-robin), and the waves of an XCD stride through its range.
+template <int MODE, int NR>
+__global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
+                                                                 LightF L, int D, int words, uint32_t *bits,
+                                                                 const uint32_t *list) {
+    __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int side = 2 * D + 1, npairs = side * side;
-    const int ncand = s_count;
-    for (int li = wave; li < ncand; li += kBlock / 64) {
-        const int64_t j = __builtin_amdgcn_readfirstlane((int)s_list[li]);
+    const uint32_t ncand = list[0];
+    const uint32_t per = (ncand + 7) / 8;
+    const uint32_t xcd = blockIdx.x & 7, blocks_per_xcd = gridDim.x >> 3;
+    const uint32_t lo = xcd * per, hi = min(ncand, lo + per);
+    const uint32_t stride = blocks_per_xcd * (kBlock / 64);
+    for (uint32_t li = lo + (blockIdx.x >> 3) * (kBlock / 64) + wave; li < hi; li += stride) {
+        const int64_t j = __builtin_amdgcn_readfirstlane((int)list[1 + li]);
         const int jx = (int)(j % g.w), jy = (int)(j / g.w);
         const uint32_t hj = occ.hit[j];
         float xj[3], nj[3], oj[3], dzj[3], nzj[3];
@@ -126,7 +149,6 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
         offset_point(xj, nj, oj);
         load3(occ.dz, j, dzj);
         load3(occ.nz, j, nzj);
-        // pairs base .. base + 64*NR - 1 in one coherent walk; lane takes pair base + 64*s + lane
         for (int base = 0; base < npairs; base += 64 * NR) {
             TRay r[NR];
             bool want[NR], self[NR], blocked[NR];
@@ -315,24 +337,17 @@ hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccVie
     if (p.pattern == OCR_WINDOW) {
         int tiles_x;
         int nt = ntiles_for(g, tiles_x);
-        dim3 grid(grid_for(nt)), block(kBlock);
-        // all (4r+1)^2 segments of a candidate in one walk: ceil(side^2 / 64) per lane (up to 5; larger
-        // windows walk in several passes)
-        const int side = 2 * D + 1, nr = (side * side + 63) / 64;
-#define OCR_VAL(M, N)                                                                                               \
-    hipLaunchKernelGGL((validate_window_kernel<M, N>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, \
-                       tiles_x, nt)
-        if (mode == OCR_AO) {
-            if (nr <= 1) OCR_VAL(OCR_AO, 1);
-            else if (nr == 2) OCR_VAL(OCR_AO, 2);
-            else if (nr == 3) OCR_VAL(OCR_AO, 3);
-            else OCR_VAL(OCR_AO, 5);
-        } else {
-            if (nr <= 1) OCR_VAL(OCR_SHADOW, 1);
-            else if (nr == 2) OCR_VAL(OCR_SHADOW, 2);
-            else if (nr == 3) OCR_VAL(OCR_SHADOW, 3);
-            else OCR_VAL(OCR_SHADOW, 5);
-        }
+        // the candidate list lives after the bits in the workspace
+        uint32_t *list = bits + (size_t)g.w * g.h * words;
+        hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(kBlock), 0, st, list);
+        hipLaunchKernelGGL(compact_kernel, dim3(grid_for(nt)), dim3(kBlock), 0, st, g, occ, words, bits, list,
+                           tiles_x, nt);
+        // persistent grid: a multiple of 8 blocks (one share per XCD), ~32 per CU
+        dim3 grid(8192), block(kBlock);
+#define OCR_VAL(M, N) \
+    hipLaunchKernelGGL((validate_window_kernel<M, N>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, list)
+        if (mode == OCR_AO) OCR_VAL(OCR_AO, 1);
+        else OCR_VAL(OCR_SHADOW, 1);
 #undef OCR_VAL
     } else {
         int gw, gh;
