@@ -29,8 +29,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue rate with packed FP32 disabled: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# FP32 VALU rate with packed FP32 disabled, one op per lane per cycle:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T ops/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 operations of one test of one segment, counted from the kernels:
+# box: 6 subtractions + 6 multiplies (slabs), 6 min/max (per-axis order),
+# 3 max + 2 min (entry/exit), 1 scale, 1 clamp, 1 compare = 26;
+# watertight triangle: 9 translations, 18 (shear), 9 (edge functions),
+# 6 (sign tests), 2 (determinant), 9 (depths), 3 (T), 1 division, 2 compares = 59
+OPS_BOX, OPS_TRI = 26, 59
 
 WORKLOADS = {
     "ao_1080p": dict(mode="ao", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2, sample_seed=1),
@@ -152,6 +159,12 @@ def main():
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f}); " +
         ", ".join(f"{k} {v:.3f}" for k, v in per.items()))
 
+    # work counted by the validation walk for one sample (outside the timed region)
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    ocr.trace_occluders(bvh, dg, mode, R, light, cfg["sample_seed"], args.steps - 1, occ)
+    ocr.validate_pairs(bvh, dg, occ, mode, R, light, p_u, ws, stats=stats)
+    torch.cuda.synchronize()
+    walks, nodes, box_tests, tri_tests = [int(v) for v in stats.cpu().tolist()]
     valid_px = int(gb.valid.sum())
     hits = int((occ.hit_u32() < ocr.HIT_SELF).sum())
     # Algorithmic bytes of one reuse launch: the G-buffer (pos, nrm, prim:
@@ -161,18 +174,14 @@ def main():
     # pair densities a window launch evaluates: (4r+1)^2 per candidate
     pair_evals = hits * (4 * r + 1) ** 2
     dominant = max(names, key=lambda n: per[n])
-    if dominant in ("trace", "validate"):
-        # Traversal: no dense arithmetic or streaming roof binds it.  Its
-        # algorithmic work is bounded below by the bytes it must move; the
-        # fraction of HBM peak it reaches is reported as such.
-        algo_bytes = 56.0 * rays if dominant == "trace" else 60.0 * W * H
-        achieved = algo_bytes / (per[dominant] * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None, kernel=dominant)
+    val_tops = (OPS_BOX * box_tests + OPS_TRI * tri_tests) / (per["validate"] * 1e-3) / 1e12
+    if dominant == "validate":
+        # traversal is VALU-bound: price the useful box and triangle tests
+        roof = dict(bound="alu", achieved=round(val_tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
+                    frac=round(val_tops / VALU_PEAK_TOPS, 4), traffic=None, kernel="validate_window_kernel")
     else:
-        achieved = reuse_gbs
-        roof = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None, kernel=dominant)
+        roof = dict(bound="hbm", achieved=round(reuse_gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(reuse_gbs / HBM_PEAK_GBS, 5), traffic=None, kernel=dominant)
 
     result = {
         "metric": "Mrays/s + reuse-pass GB/s at 1080p; frames/s and p99 frame latency served",
@@ -199,6 +208,8 @@ def main():
         "rays_per_step": rays,
         "occluder_hits": hits,
         "valid_pixels": valid_px,
+        "validation": {"walks": walks, "node_visits": nodes, "box_tests": box_tests, "tri_tests": tri_tests,
+                       "segments_per_s": None, "useful_tflops": round(val_tops, 3)},
         "bvh": {"nodes": info.nnodes, "depth": info.depth, "device_mb": round(info.device_bytes / 2 ** 20, 1),
                 "build_ms": round(info.build_ms, 1)},
         "roofline": roof,

@@ -187,10 +187,13 @@ size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params
  * ignoring z_j's triangle and k's own, decides whether z_j is the first hit
  * from x_k.  Writes one bit per pair into workspace (layout internal; size
  * from ocr_workspace_bytes with estimator OCR_UNBIASED).  mode, ao_radius and
- * light as for the trace.  Errors as ocr_reuse_ao. */
+ * light as for the trace.  stats: NULL, or device uint64[4] to which the
+ * window validation adds its work -- BVH walks, node visits, box tests and
+ * triangle tests of active segments (a test of one segment counts once).
+ * Errors as ocr_reuse_ao. */
 ocr_status ocr_validate_pairs(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ, int32_t mode,
                               float ao_radius, const ocr_rect_light *light, const ocr_reuse_params *params,
-                              void *workspace, size_t workspace_bytes, void *stream);
+                              void *workspace, size_t workspace_bytes, uint64_t *stats, void *stream);
 
 /* AO reuse (Sec. 4.3): out[i] = 1 - B_i with
  *   B_i = sum_{j in S(i), hit_j} [p(z_j|x_i) > 0 and P_i(j) > 0] p(z_j|x_i) / P_i(j),

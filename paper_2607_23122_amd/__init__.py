@@ -90,7 +90,8 @@ def lib():
     L.ocr_workspace_bytes.argtypes = [i32, i32, ctypes.POINTER(ReuseParams)]
     L.ocr_validate_pairs.restype = i32
     L.ocr_validate_pairs.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), i32, ctypes.c_float,
-                                     ctypes.POINTER(_Light), ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp]
+                                     ctypes.POINTER(_Light), ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp,
+                                     vp]
     L.ocr_reuse_ao.restype = i32
     L.ocr_reuse_ao.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), ctypes.c_float,
                                ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
@@ -266,15 +267,18 @@ def _workspace(gbuf, params, workspace):
 
 
 def validate_pairs(bvh: BVH, gbuf: DeviceGBuffer, occ: Occluders, mode="ao", ao_radius=1.0, light=None,
-                   params: ReuseParams | None = None, workspace=None, stream=None):
-    """First-hit validation bits of the unbiased estimator into `workspace`."""
+                   params: ReuseParams | None = None, workspace=None, stream=None, stats=None):
+    """First-hit validation bits of the unbiased estimator into `workspace`;
+    `stats` (optional int64 device tensor of 4) accumulates walks, node
+    visits, box tests and triangle tests."""
     params = params or reuse_params(estimator="unbiased")
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     ws, nbytes = _workspace(gbuf, params, workspace)
     g, o = gbuf.c(), occ.c()
     lp = ctypes.byref(light_struct(light)) if light is not None else None
     _check(lib().ocr_validate_pairs(bvh.h, ctypes.byref(g), ctypes.byref(o), m, float(ao_radius), lp,
-                                    ctypes.byref(params), _dptr(ws), nbytes, _stream(stream)))
+                                    ctypes.byref(params), _dptr(ws), nbytes,
+                                    _dptr(stats) if stats is not None else None, _stream(stream)))
     return ws
 
 

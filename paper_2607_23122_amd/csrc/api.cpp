@@ -118,7 +118,7 @@ ocr_status reuse_common(const ocr_bvh *bvh, const ocr_gbuffer *g, const ocr_occl
     GBufView gv = view(g);
     hipError_t e;
     if (p->estimator == OCR_UNBIASED && !p->validated) {
-        e = launch_validate(bvh->dev, gv, ov, mode, R, L, *p, (uint32_t *)ws, s);
+        e = launch_validate(bvh->dev, gv, ov, mode, R, L, *p, (uint32_t *)ws, nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "validation launch");
     }
     e = launch_reuse(gv, ov, mode, R, L, *p, (const uint32_t *)ws, out, s);
@@ -257,7 +257,7 @@ size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params
 
 ocr_status ocr_validate_pairs(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ, int32_t mode,
                               float ao_radius, const ocr_rect_light *light, const ocr_reuse_params *params,
-                              void *workspace, size_t workspace_bytes, void *stream) {
+                              void *workspace, size_t workspace_bytes, uint64_t *stats, void *stream) {
     if (!bvh) return fail(OCR_ERR_INVALID_ARG, "bvh is NULL");
     ocr_status st = check_gbuf(gbuf);
     if (st) return st;
@@ -279,7 +279,7 @@ ocr_status ocr_validate_pairs(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const
     if (!workspace || workspace_bytes < need)
         return fail(OCR_ERR_INVALID_ARG, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
     hipError_t e = launch_validate(bvh->dev, view(gbuf), OccView{occ->dz, occ->nz, occ->hit}, mode, ao_radius, L,
-                                   *params, (uint32_t *)workspace, (hipStream_t)stream);
+                                   *params, (uint32_t *)workspace, stats, (hipStream_t)stream);
     return e == hipSuccess ? OCR_OK : hip_fail(e, "validation launch");
 }
 

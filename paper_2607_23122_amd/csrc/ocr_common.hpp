@@ -159,7 +159,8 @@ struct OccView {
 hipError_t launch_trace(const DeviceBVH &bvh, const GBufView &g, int mode, float R, const LightF &L, uint32_t seed32,
                         uint32_t sample, const OccView &out, hipStream_t st);
 hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, int mode, float R,
-                           const LightF &L, const ocr_reuse_params &p, uint32_t *bits, hipStream_t st);
+                           const LightF &L, const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats,
+                           hipStream_t st);
 hipError_t launch_reuse(const GBufView &g, const OccView &occ, int mode, float R, const LightF &L,
                         const ocr_reuse_params &p, const uint32_t *bits, float *out, hipStream_t st);
 hipError_t launch_scale(float *out, int64_t n, float s, hipStream_t st);

@@ -130,8 +130,9 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ
 template <int MODE, int NR>
 __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
                                                                  LightF L, int D, int words, uint32_t *bits,
-                                                                 const uint32_t *list) {
+                                                                 const uint32_t *list, uint64_t *stats) {
     __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
+    WalkStats ws;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int side = 2 * D + 1, npairs = side * side;
     const uint32_t ncand = list[0];
@@ -186,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
                     }
                 }
             }
-            traverse_wave_any<NR>(bvh, r, 1.0f - 1e-4f, want, blocked, wstack[wave]);
+            traverse_wave_any<NR>(bvh, r, 1.0f - 1e-4f, want, blocked, wstack[wave], ws);
 #pragma unroll
             for (int sl = 0; sl < NR; ++sl) {
                 const bool bit = self[sl] || (want[sl] && !blocked[sl]);
@@ -196,6 +197,12 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
                 if (lane == 1 && w0 + 1 < words) bits[j * words + w0 + 1] = (uint32_t)(m >> 32);
             }
         }
+    }
+    if (stats != nullptr && lane == 0) {
+        atomicAdd((unsigned long long *)&stats[0], (unsigned long long)ws.walks);
+        atomicAdd((unsigned long long *)&stats[1], (unsigned long long)ws.nodes);
+        atomicAdd((unsigned long long *)&stats[2], (unsigned long long)ws.box_tests);
+        atomicAdd((unsigned long long *)&stats[3], (unsigned long long)ws.tri_tests);
     }
 }
 
@@ -332,7 +339,8 @@ hipError_t launch_trace(const DeviceBVH &bvh, const GBufView &g, int mode, float
 }
 
 hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, int mode, float R,
-                           const LightF &L, const ocr_reuse_params &p, uint32_t *bits, hipStream_t st) {
+                           const LightF &L, const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats,
+                           hipStream_t st) {
     const int D = pair_extent(p), words = pair_words(p);
     if (p.pattern == OCR_WINDOW) {
         int tiles_x;
@@ -345,7 +353,8 @@ hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccVie
         // persistent grid: a multiple of 8 blocks (one share per XCD), ~32 per CU
         dim3 grid(8192), block(kBlock);
 #define OCR_VAL(M, N) \
-    hipLaunchKernelGGL((validate_window_kernel<M, N>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, list)
+    hipLaunchKernelGGL((validate_window_kernel<M, N>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, list, \
+                       stats)
         if (mode == OCR_AO) OCR_VAL(OCR_AO, 1);
         else OCR_VAL(OCR_SHADOW, 1);
 #undef OCR_VAL

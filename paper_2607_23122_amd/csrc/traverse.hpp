@@ -223,9 +223,16 @@ typedef __attribute__((address_space(4))) const uint32_t cuint;
 // against the shared node's four boxes and the leaf's triangles and drops a
 // segment as soon as it is blocked.  blocked[q] reports segment q (t in
 // (0, tmax)).
+// Work counters of a walk (wave-uniform): node visits, and box / triangle
+// tests performed for active segments (lane-tests).
+struct WalkStats {
+    uint64_t walks = 0, nodes = 0, box_tests = 0, tri_tests = 0;
+};
+
 template <int NR>
 __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[NR], float tmax,
-                                         const bool (&want)[NR], bool (&blocked)[NR], uint32_t *wstack) {
+                                         const bool (&want)[NR], bool (&blocked)[NR], uint32_t *wstack,
+                                         WalkStats &st) {
     bool active[NR];
     bool any = false;
 #pragma unroll
@@ -235,11 +242,19 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
         any |= active[q];
     }
     if (__ballot(any) == 0ull) return;
+    st.walks += 1;
     const float grow = 1.0f + 0x1p-20f;
     int sp = 0;
     uint32_t node = 0;
     for (;;) {
         if (!(node & kLeafBit)) {
+            {
+                uint32_t na = 0;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) na += __popcll(__ballot(active[q]));
+                st.nodes += 1;
+                st.box_tests += 4u * na;
+            }
             const cfloat *np = (const cfloat *)(bvh.nodes + node);
             const cuint *cp = (const cuint *)(bvh.nodes + node);
             float lxs[4], hxs[4], lys[4], hys[4], lzs[4], hzs[4];
@@ -295,6 +310,8 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
                 v1.x = tp[4]; v1.y = tp[5]; v1.z = tp[6]; v1.w = tp[7];
                 v2.x = tp[8]; v2.y = tp[9]; v2.z = tp[10]; v2.w = tp[11];
                 const uint32_t id = __float_as_uint(v0.w);
+#pragma unroll
+                for (int q = 0; q < NR; ++q) st.tri_tests += __popcll(__ballot(active[q] && id != r[q].ign0 && id != r[q].ign1));
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
                     if (active[q] && id != r[q].ign0 && id != r[q].ign1) {
