@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--workload", default="ao_1080p", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-baseline", default="on", choices=["on", "off"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle work for the baseline")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this size (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (a frame would shard by image "
@@ -136,6 +138,14 @@ def main():
             mark(4)
             ocr.reuse_shadow(None, dg, occ, light, p_u, out_u, ws)
         mark(5)
+
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib * 2 ** 20 // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     for s in range(args.warmup):
         step(1000 + s)
