@@ -83,22 +83,23 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g
     }
 }
 
-// First-hit validation (Eq. occ-first-hit) for the sliding window, one
-// wavefront per candidate j: lane q takes the receiver k = j + (q % side - D,
-// q / side - D), side = 2D + 1, D = 2r; when the density of z_j at k is
-// positive, an any-hit segment o_k -> z_j over t in (0, 1 - 1e-4), ignoring
-// z_j's triangle and k's own, decides Occ(x_k, z_j).  All segments of a wave
-// end at the same point, so their traversals stay coherent.  Bit q of j's
-// words is set when z_j is the first hit from o_k (k == j: always).
-// Candidate list for the window validation: every pixel whose ray found an
-// occluder, appended in (per-wave) tile order; other pixels' validation words
-// are cleared here.  list[0] holds the count, list[1 + n] the pixel index.
-__global__ __launch_bounds__(kBlock) void clear_count_kernel(uint32_t *list) {
-    if (threadIdx.x == 0) list[0] = 0u;
+// Candidate lists for the window validation: every pixel whose ray found an
+// occluder.  One list per XCD (blocks are dealt to the XCDs round-robin):
+// the compaction block on XCD x appends its tile's candidates to list x with a
+// single atomic, and the validation blocks of XCD x consume list x, so each
+// XCD's L2 sees one contiguous set of tiles.  Layout: counts[8] (padded to a
+// cache line each), then list x at offset x * per_xcd.  Only candidates'
+// validation words are ever read, so other pixels' words are left as they are.
+constexpr int kCountStride = 32;  // uint32 per counter: one 128-byte line
+
+__global__ __launch_bounds__(kBlock) void clear_count_kernel(uint32_t *lists) {
+    if (threadIdx.x < 8) lists[threadIdx.x * kCountStride] = 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ, int words, uint32_t *bits,
-                                                         uint32_t *list, int tiles_x, int ntiles) {
+__global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ, uint32_t *lists, uint32_t per_xcd,
+                                                         int tiles_x, int ntiles) {
+    __shared__ uint32_t s_wave[kBlock / 64];
+    __shared__ uint32_t s_base;
     int tx, ty;
     tile_of_block(tiles_x, ntiles, tx, ty);
     if (ty * tiles_x + tx >= ntiles) return;
@@ -107,14 +108,20 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ
     const bool inside = px < g.w && py < g.h;
     const int64_t j = inside ? (int64_t)py * g.w + px : 0;
     const bool cand = inside && occ.hit[j] < OCR_HIT_SELF;
-    if (inside && !cand)
-        for (int q = 0; q < words; ++q) bits[j * words + q] = 0u;
     const unsigned long long m = __ballot(cand);
-    const int lane = threadIdx.x & 63;
-    uint32_t base = 0;
-    if (lane == 0 && m) base = atomicAdd(list, (uint32_t)__popcll(m));
-    base = __shfl(base, 0);
-    if (cand) list[1 + base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)j;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    const uint32_t xcd = blockIdx.x & 7;
+    if (threadIdx.x == 0) {
+        uint32_t total = 0;
+        for (int w2 = 0; w2 < kBlock / 64; ++w2) total += s_wave[w2];
+        s_base = total ? atomicAdd(&lists[xcd * kCountStride], total) : 0u;
+    }
+    __syncthreads();
+    uint32_t off = s_base;
+    for (int w2 = 0; w2 < wave; ++w2) off += s_wave[w2];
+    if (cand) lists[8 * kCountStride + xcd * per_xcd + off + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)j;
 }
 
 // First-hit validation (Eq. occ-first-hit) for the sliding window, one
@@ -124,24 +131,23 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ
 // z_j's triangle and k's own, decides Occ(x_k, z_j).  The wave walks the BVH
 // once per 64 receivers along the union of their segments, which all end at
 // z_j (traverse_wave_any).  Bit q of j's words is set when z_j is the first
-// hit from o_k (k == j: always).  Persistent grid: the candidates are split
-// into 8 contiguous ranges, one per XCD (blocks are dealt to XCDs
-// round-robin), and the waves of an XCD stride through its range.
+// hit from o_k (k == j: always).  Persistent grid: the waves of XCD x stride
+// through candidate list x.
 template <int MODE, int NR>
 __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
                                                                  LightF L, int D, int words, uint32_t *bits,
-                                                                 const uint32_t *list, uint64_t *stats) {
+                                                                 const uint32_t *lists, uint32_t per_xcd,
+                                                                 uint64_t *stats) {
     __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
     WalkStats ws;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int side = 2 * D + 1, npairs = side * side;
-    const uint32_t ncand = list[0];
-    const uint32_t per = (ncand + 7) / 8;
     const uint32_t xcd = blockIdx.x & 7, blocks_per_xcd = gridDim.x >> 3;
-    const uint32_t lo = xcd * per, hi = min(ncand, lo + per);
+    const uint32_t ncand = lists[xcd * kCountStride];
+    const uint32_t *list = lists + 8 * kCountStride + xcd * per_xcd;
     const uint32_t stride = blocks_per_xcd * (kBlock / 64);
-    for (uint32_t li = lo + (blockIdx.x >> 3) * (kBlock / 64) + wave; li < hi; li += stride) {
-        const int64_t j = __builtin_amdgcn_readfirstlane((int)list[1 + li]);
+    for (uint32_t li = (blockIdx.x >> 3) * (kBlock / 64) + wave; li < ncand; li += stride) {
+        const int64_t j = __builtin_amdgcn_readfirstlane((int)list[li]);
         const int jx = (int)(j % g.w), jy = (int)(j / g.w);
         const uint32_t hj = occ.hit[j];
         float xj[3], nj[3], oj[3], dzj[3], nzj[3];
@@ -345,16 +351,18 @@ hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccVie
     if (p.pattern == OCR_WINDOW) {
         int tiles_x;
         int nt = ntiles_for(g, tiles_x);
-        // the candidate list lives after the bits in the workspace
-        uint32_t *list = bits + (size_t)g.w * g.h * words;
-        hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(kBlock), 0, st, list);
-        hipLaunchKernelGGL(compact_kernel, dim3(grid_for(nt)), dim3(kBlock), 0, st, g, occ, words, bits, list,
-                           tiles_x, nt);
+        // the candidate lists live after the bits in the workspace; XCD x holds at most
+        // per_xcd = ceil(ntiles / 8) tiles of 256 pixels
+        uint32_t *lists = bits + (size_t)g.w * g.h * words;
+        const uint32_t per_xcd = (uint32_t)((nt + 7) / 8) * (uint32_t)kBlock;
+        hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(kBlock), 0, st, lists);
+        hipLaunchKernelGGL(compact_kernel, dim3(grid_for(nt)), dim3(kBlock), 0, st, g, occ, lists, per_xcd, tiles_x,
+                           nt);
         // persistent grid: a multiple of 8 blocks (one share per XCD), ~32 per CU
         dim3 grid(8192), block(kBlock);
 #define OCR_VAL(M, N) \
-    hipLaunchKernelGGL((validate_window_kernel<M, N>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, list, \
-                       stats)
+    hipLaunchKernelGGL((validate_window_kernel<M, N>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, \
+                       lists, per_xcd, stats)
         if (mode == OCR_AO) OCR_VAL(OCR_AO, 1);
         else OCR_VAL(OCR_SHADOW, 1);
 #undef OCR_VAL

@@ -31,9 +31,10 @@ def test_workspace_bytes():
     import paper_2607_23122_amd as ocr
     assert ocr.workspace_bytes(1920, 1080, ocr.reuse_params("window", 3, 0, "biased")) == 0
     # 13 x 13 pairs per receiver -> 169 bits -> 6 words
-    # plus the candidate list of the window validation (count + one index per pixel)
+    # plus the window validation's per-XCD candidate lists (8 padded counters + 8 x ceil(tiles/8) x 256 slots)
+    tiles = 120 * 68
     assert ocr.workspace_bytes(1920, 1080, ocr.reuse_params("window", 3, 0, "unbiased")) == \
-        1920 * 1080 * 6 * 4 + (1920 * 1080 + 1) * 4
+        1920 * 1080 * 6 * 4 + (8 * 32 + ((tiles + 7) // 8) * 8 * 256) * 4
     # 4 x 2 groups: offsets in [-3, 3]^2 -> 49 bits -> 2 words
     assert ocr.workspace_bytes(100, 10, ocr.reuse_params("group", 0, 8, "unbiased")) == 100 * 10 * 2 * 4
     assert ocr.workspace_bytes(100, 10, ocr.reuse_params("window", 9, 0, "unbiased")) == 0
