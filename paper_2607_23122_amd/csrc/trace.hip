@@ -131,8 +131,9 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ
 // z_j's triangle and k's own, decides Occ(x_k, z_j).  The wave walks the BVH
 // once per 64 receivers along the union of their segments, which all end at
 // z_j (traverse_wave_any).  Bit q of j's words is set when z_j is the first
-// hit from o_k (k == j: always).  Persistent grid: the waves of XCD x stride
-// through candidate list x.
+// hit from o_k (k == j: always).  Persistent grid: the candidate lists,
+// concatenated, are split into 8 equal ranges, one per XCD (blocks are dealt
+// to XCDs round-robin), and the waves of an XCD stride through its range.
 template <int MODE, int NR>
 __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
                                                                  LightF L, int D, int words, uint32_t *bits,
@@ -142,12 +143,21 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
     WalkStats ws;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int side = 2 * D + 1, npairs = side * side;
+    // the 8 lists, concatenated, split into 8 equal ranges (one per XCD)
+    uint32_t start[9];
+    start[0] = 0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) start[x + 1] = start[x] + lists[x * kCountStride];
+    const uint32_t total = start[8], per = (total + 7) / 8;
     const uint32_t xcd = blockIdx.x & 7, blocks_per_xcd = gridDim.x >> 3;
-    const uint32_t ncand = lists[xcd * kCountStride];
-    const uint32_t *list = lists + 8 * kCountStride + xcd * per_xcd;
+    const uint32_t hi = min(total, (xcd + 1) * per);
     const uint32_t stride = blocks_per_xcd * (kBlock / 64);
-    for (uint32_t li = (blockIdx.x >> 3) * (kBlock / 64) + wave; li < ncand; li += stride) {
-        const int64_t j = __builtin_amdgcn_readfirstlane((int)list[li]);
+    for (uint32_t li = xcd * per + (blockIdx.x >> 3) * (kBlock / 64) + wave; li < hi; li += stride) {
+        int x = 0;
+#pragma unroll
+        for (int q = 1; q < 8; ++q) x += li >= start[q] ? 1 : 0;
+        const int64_t j = __builtin_amdgcn_readfirstlane(
+            (int)lists[8 * kCountStride + (uint32_t)x * per_xcd + (li - start[x])]);
         const int jx = (int)(j % g.w), jy = (int)(j / g.w);
         const uint32_t hj = occ.hit[j];
         float xj[3], nj[3], oj[3], dzj[3], nzj[3];
