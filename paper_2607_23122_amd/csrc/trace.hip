@@ -131,9 +131,8 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ
 // z_j's triangle and k's own, decides Occ(x_k, z_j).  The wave walks the BVH
 // once per 64 receivers along the union of their segments, which all end at
 // z_j (traverse_wave_any).  Bit q of j's words is set when z_j is the first
-// hit from o_k (k == j: always).  Persistent grid: the candidate lists,
-// concatenated, are split into 8 equal ranges, one per XCD (blocks are dealt
-// to XCDs round-robin), and the waves of an XCD stride through its range.
+// hit from o_k (k == j: always).  Persistent grid striding through the
+// candidate lists (measured faster than giving each XCD a contiguous range).
 template <int MODE, int NR>
 __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
                                                                  LightF L, int D, int words, uint32_t *bits,
@@ -143,16 +142,15 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
     WalkStats ws;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int side = 2 * D + 1, npairs = side * side;
-    // the 8 lists, concatenated, split into 8 equal ranges (one per XCD)
+    // the 8 lists concatenated (roughly tile order); consecutive candidates go
+    // to the waves of one block, which then share the CU's caches
     uint32_t start[9];
     start[0] = 0;
 #pragma unroll
     for (int x = 0; x < 8; ++x) start[x + 1] = start[x] + lists[x * kCountStride];
-    const uint32_t total = start[8], per = (total + 7) / 8;
-    const uint32_t xcd = blockIdx.x & 7, blocks_per_xcd = gridDim.x >> 3;
-    const uint32_t hi = min(total, (xcd + 1) * per);
-    const uint32_t stride = blocks_per_xcd * (kBlock / 64);
-    for (uint32_t li = xcd * per + (blockIdx.x >> 3) * (kBlock / 64) + wave; li < hi; li += stride) {
+    const uint32_t total = start[8];
+    const uint32_t stride = gridDim.x * (kBlock / 64);
+    for (uint32_t li = blockIdx.x * (kBlock / 64) + wave; li < total; li += stride) {
         int x = 0;
 #pragma unroll
         for (int q = 1; q < 8; ++q) x += li >= start[q] ? 1 : 0;
