@@ -227,6 +227,177 @@ ocr_status ocr_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const o
  * into their mean (the final line of App. D / App. H). */
 ocr_status ocr_scale(float *out, int64_t n, float s, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched schedule.  The paper runs one view per pass; a plan runs many views
+ * of uneven size, over several scenes and mixed effects, as one persistent
+ * trace launch and one persistent reuse launch over a (view, tile) work list,
+ * recorded once into a HIP graph and replayed.  Each view's output is bitwise
+ * identical to ocr_trace_occluders followed by ocr_reuse_ao/_shadow (and, for
+ * OCR_UNBIASED, ocr_validate_pairs) with the same arguments: the schedule
+ * changes only which lane or block computes a pixel, never its arithmetic.
+ * ------------------------------------------------------------------------- */
+
+/* One view of a plan.  All pointers are borrowed and must stay valid for the
+ * plan's lifetime.
+ *   bvh:       the view's scene
+ *   gbuf:      device G-buffer (as for ocr_trace_occluders)
+ *   mode, ao_radius, light, seed, sample: as for ocr_trace_occluders (light
+ *              ignored for AO)
+ *   params:    reuse configuration (accumulate and validated must be 0)
+ *   out:       device float[h][w], the estimate (as for ocr_reuse_ao/_shadow) */
+typedef struct {
+    const ocr_bvh *bvh;
+    ocr_gbuffer gbuf;
+    int32_t mode;
+    float ao_radius;
+    ocr_rect_light light;
+    uint64_t seed;
+    uint32_t sample;
+    ocr_reuse_params params;
+    float *out;
+} ocr_view_desc;
+
+typedef struct ocr_plan ocr_plan;
+
+/* Performance knobs of a plan (none changes a result).
+ *   tile_w x tile_h: pixels one wavefront traces per work item (8x8, 16x8,
+ *                    16x16, 32x8 or 32x16; tile_w*tile_h/64 rays per lane)
+ *   packing:         order of a tile's pixels over lanes and passes:
+ *                    0 row-major, 1 8x8 blocks, 2 Morton
+ *   use_graph:       1 = record the schedule into a HIP graph on the first
+ *                    launch and replay it; 0 = enqueue the kernels each time */
+enum { OCR_PACK_ROW = 0, OCR_PACK_BLOCK8 = 1, OCR_PACK_MORTON = 2 };
+typedef struct {
+    int32_t tile_w, tile_h;
+    int32_t packing;
+    int32_t use_graph;
+} ocr_plan_tuning;
+
+typedef struct {
+    int32_t nviews;
+    int64_t pixels;           /* sum of w*h over views */
+    int64_t trace_items;      /* (view, tile) work items of the trace launch */
+    int64_t reuse_items;      /* (view, 16x16 tile) work items of the reuse launch */
+    int64_t device_bytes;     /* records, workspaces and tables the plan owns */
+    ocr_plan_tuning tuning;   /* the knobs in use */
+    int32_t tuned;            /* 1 when the knobs came from the autotuner */
+    int32_t candidates;       /* knob settings the autotuner timed */
+    double tune_ms;           /* autotuner wall time */
+    double best_trace_ms;     /* autotuner's time for the chosen trace knobs */
+} ocr_plan_info;
+
+/* Create a plan over `nviews` views (1..4096).  The plan allocates, once, the
+ * occluder records of every view, the validation workspaces of OCR_UNBIASED
+ * views and its work tables.  tuning: NULL = autotune (time every tile and
+ * packing setting on these views with `stream` and keep the fastest; only
+ * the plan's own records are written meanwhile), else use the given knobs.
+ * Synchronous.  Errors: OCR_ERR_INVALID_ARG (any view argument that the
+ * per-view calls would refuse, accumulate or validated set, bad knobs),
+ * OCR_ERR_OOM, OCR_ERR_HIP. */
+ocr_status ocr_plan_create(const ocr_view_desc *views, int32_t nviews, const ocr_plan_tuning *tuning, void *stream,
+                           ocr_plan **out);
+/* Enqueue one pass of every view on `stream`: reset the work queues, trace,
+ * validate (OCR_UNBIASED views), reuse.  With use_graph the first call records
+ * the graph (on a stream the plan owns) and every call replays it on
+ * `stream`.  Allocates nothing after the first call.  Calls that overlap in
+ * time on one plan race; one plan at a time per stream. */
+ocr_status ocr_plan_launch(ocr_plan *plan, void *stream);
+ocr_status ocr_plan_get_info(const ocr_plan *plan, ocr_plan_info *info);
+/* The plan's occluder records of view v (device pointers the plan owns). */
+ocr_status ocr_plan_get_records(const ocr_plan *plan, int32_t view, ocr_occluders *out);
+/* Wait for the device, then free the plan's memory, graph and stream. */
+ocr_status ocr_plan_free(ocr_plan *plan);
+
+/* ---------------------------------------------------------------------------
+ * Served loop: frame requests against resident scenes, admitted under an HBM
+ * budget, run concurrently on a pool of stream slots (continuous batching:
+ * a request is admitted as soon as a slot and memory are free, while others
+ * are still on the device).  A request's result is bitwise identical to the
+ * per-view calls with the same arguments, whatever else is in flight.
+ * ------------------------------------------------------------------------- */
+typedef struct ocr_server ocr_server;
+
+/*   hbm_budget_bytes: device arena for per-request state (occluder records,
+ *                     validation workspace, server-held outputs), allocated
+ *                     once at creation (>= 4096)
+ *   max_slots:        requests in flight at once (1..64), one stream each
+ *   max_queue:        queued requests before submit returns OCR_ERR_BUSY
+ *                     (0 = unbounded)
+ *   poll_us:          completion polling interval of the worker (0 = 20)
+ *   mock:             1 = no device work: each request "runs" for
+ *                     mock_ns_per_pixel * w * h, for scheduler tests on a
+ *                     machine without a GPU (no HIP call is made) */
+typedef struct {
+    size_t hbm_budget_bytes;
+    int32_t max_slots;
+    int32_t max_queue;
+    int32_t poll_us;
+    int32_t mock;
+    double mock_ns_per_pixel;
+} ocr_server_options;
+
+/* A frame request.  scene_id / view select a resident G-buffer.  out: device
+ * float[h][w] to write, or NULL to have the server keep the output in its
+ * arena (ocr_result.out) until ocr_server_release.  arrival_ms: arrival time
+ * on the server clock (ocr_server_now_ms), 0 = stamped at submission. */
+typedef struct {
+    int32_t scene_id;
+    int32_t view;
+    int32_t mode;
+    float ao_radius;
+    ocr_rect_light light;
+    uint64_t seed;
+    uint32_t sample;
+    ocr_reuse_params params;
+    float *out;
+    double arrival_ms;
+} ocr_request;
+
+typedef struct {
+    uint64_t ticket;
+    ocr_status status;
+    int32_t width, height;
+    float *out;          /* where the estimate is (device) */
+    double arrival_ms;   /* server clock */
+    double start_ms;     /* admitted and enqueued */
+    double end_ms;       /* completion observed */
+    double latency_ms;   /* end - arrival */
+} ocr_result;
+
+typedef struct {
+    int64_t submitted, completed, refused, queued, in_flight;
+    int64_t waited_for_memory;  /* admission attempts that found the head request too big for the free arena */
+    int64_t peak_bytes, budget_bytes;
+    int64_t max_in_flight;
+    double p50_ms, p99_ms, mean_ms, max_ms;  /* arrival-to-completion latency of completed requests */
+    double frames_per_s;                     /* completed / (last completion - first arrival) */
+} ocr_server_stats;
+
+/* Create a server on the current device (mock: no device).  Starts one worker
+ * thread.  Errors: OCR_ERR_INVALID_ARG, OCR_ERR_OOM (arena), OCR_ERR_HIP. */
+ocr_status ocr_server_create(const ocr_server_options *opt, ocr_server **out);
+/* Register a resident scene: its BVH and a pool of G-buffers (copied
+ * descriptors; the device arrays are borrowed for the server's lifetime). */
+ocr_status ocr_server_add_scene(ocr_server *s, const ocr_bvh *bvh, const ocr_gbuffer *views, int32_t nviews,
+                                int32_t *scene_id);
+/* Queue a request (first in, first out).  The server's streams do not wait
+ * for other streams: the G-buffer and a caller-given output must be ready
+ * (their producers finished) when the request is submitted.  Errors:
+ * OCR_ERR_INVALID_ARG (as the per-view calls), OCR_ERR_BUDGET (its state can
+ * never fit the arena), OCR_ERR_BUSY (queue full, or server stopping). */
+ocr_status ocr_server_submit(ocr_server *s, const ocr_request *req, uint64_t *ticket);
+/* Move up to `max` completed results to `out` (host), completion order. */
+ocr_status ocr_server_poll(ocr_server *s, ocr_result *out, int32_t max, int32_t *n);
+/* Give back a server-held output (request submitted with out == NULL). */
+ocr_status ocr_server_release(ocr_server *s, uint64_t ticket);
+/* Block until nothing is queued or in flight. */
+ocr_status ocr_server_drain(ocr_server *s);
+ocr_status ocr_server_get_stats(ocr_server *s, ocr_server_stats *st);
+/* Milliseconds on the server clock (steady, shared by all servers). */
+double ocr_server_now_ms(void);
+/* Drain, stop the worker and free the arena and streams. */
+ocr_status ocr_server_destroy(ocr_server *s);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *ocr_last_error(void);
 

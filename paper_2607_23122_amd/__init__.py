@@ -58,9 +58,61 @@ class BvhInfo(ctypes.Structure):
                 ("max_leaf", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double)]
 
 
+class ViewDesc(ctypes.Structure):
+    _fields_ = [("bvh", ctypes.c_void_p), ("gbuf", _GBuffer), ("mode", ctypes.c_int32), ("ao_radius", ctypes.c_float),
+                ("light", _Light), ("seed", ctypes.c_uint64), ("sample", ctypes.c_uint32), ("params", ReuseParams),
+                ("out", ctypes.c_void_p)]
+
+
+OCR_PACK_ROW, OCR_PACK_BLOCK8, OCR_PACK_MORTON = 0, 1, 2
+PACKINGS = {"row": OCR_PACK_ROW, "block8": OCR_PACK_BLOCK8, "morton": OCR_PACK_MORTON}
+
+
+class PlanTuning(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("packing", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("nviews", ctypes.c_int32), ("pixels", ctypes.c_int64), ("trace_items", ctypes.c_int64),
+                ("reuse_items", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("tuning", PlanTuning),
+                ("tuned", ctypes.c_int32), ("candidates", ctypes.c_int32), ("tune_ms", ctypes.c_double),
+                ("best_trace_ms", ctypes.c_double)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("poll_us", ctypes.c_int32), ("mock", ctypes.c_int32), ("mock_ns_per_pixel", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("scene_id", ctypes.c_int32), ("view", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("ao_radius", ctypes.c_float), ("light", _Light), ("seed", ctypes.c_uint64),
+                ("sample", ctypes.c_uint32), ("params", ReuseParams), ("out", ctypes.c_void_p),
+                ("arrival_ms", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("out", ctypes.c_void_p), ("arrival_ms", ctypes.c_double),
+                ("start_ms", ctypes.c_double), ("end_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("refused", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64), ("waited_for_memory", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("max_in_flight", ctypes.c_int64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("frames_per_s", ctypes.c_double)]
+
+
 EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders", "ocr_sample_rays",
            "ocr_workspace_bytes", "ocr_validate_pairs",
-           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_scale", "ocr_last_error", "ocr_version"]
+           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_scale", "ocr_last_error", "ocr_version",
+           "ocr_plan_create", "ocr_plan_launch", "ocr_plan_get_info", "ocr_plan_get_records", "ocr_plan_free",
+           "ocr_server_create", "ocr_server_add_scene", "ocr_server_submit", "ocr_server_poll",
+           "ocr_server_release", "ocr_server_drain", "ocr_server_get_stats", "ocr_server_now_ms",
+           "ocr_server_destroy"]
 
 _lib = None
 
@@ -100,6 +152,35 @@ def lib():
                                    ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
     L.ocr_scale.restype = i32
     L.ocr_scale.argtypes = [vp, i64, ctypes.c_float, vp]
+    P = ctypes.POINTER
+    L.ocr_plan_create.restype = i32
+    L.ocr_plan_create.argtypes = [P(ViewDesc), i32, P(PlanTuning), vp, P(vp)]
+    L.ocr_plan_launch.restype = i32
+    L.ocr_plan_launch.argtypes = [vp, vp]
+    L.ocr_plan_get_info.restype = i32
+    L.ocr_plan_get_info.argtypes = [vp, P(PlanInfo)]
+    L.ocr_plan_get_records.restype = i32
+    L.ocr_plan_get_records.argtypes = [vp, i32, P(_Occ)]
+    L.ocr_plan_free.restype = i32
+    L.ocr_plan_free.argtypes = [vp]
+    L.ocr_server_create.restype = i32
+    L.ocr_server_create.argtypes = [P(ServerOptions), P(vp)]
+    L.ocr_server_add_scene.restype = i32
+    L.ocr_server_add_scene.argtypes = [vp, vp, P(_GBuffer), i32, P(i32)]
+    L.ocr_server_submit.restype = i32
+    L.ocr_server_submit.argtypes = [vp, P(Request), P(ctypes.c_uint64)]
+    L.ocr_server_poll.restype = i32
+    L.ocr_server_poll.argtypes = [vp, P(Result), i32, P(i32)]
+    L.ocr_server_release.restype = i32
+    L.ocr_server_release.argtypes = [vp, ctypes.c_uint64]
+    L.ocr_server_drain.restype = i32
+    L.ocr_server_drain.argtypes = [vp]
+    L.ocr_server_get_stats.restype = i32
+    L.ocr_server_get_stats.argtypes = [vp, P(ServerStats)]
+    L.ocr_server_now_ms.restype = ctypes.c_double
+    L.ocr_server_now_ms.argtypes = []
+    L.ocr_server_destroy.restype = i32
+    L.ocr_server_destroy.argtypes = [vp]
     L.ocr_last_error.restype = ctypes.c_char_p
     L.ocr_version.restype = ctypes.c_char_p
     _lib = L
@@ -341,3 +422,181 @@ def render(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, light=None, 
 
 def version() -> str:
     return lib().ocr_version().decode()
+
+
+_hip = None
+
+
+def device_to_host(ptr: int, shape, dtype) -> np.ndarray:
+    """Copy library-owned device memory (plan records, server-held outputs)
+    to a new host array with hipMemcpy of the process's HIP runtime (the one
+    torch and libocr.so share).  Synchronous; the caller makes sure the
+    producing work has finished."""
+    global _hip
+    if _hip is None:
+        import torch  # noqa: F401  (loads the runtime libocr.so resolves to)
+        _hip = ctypes.CDLL("libamdhip64.so.7")
+        _hip.hipMemcpy.restype = ctypes.c_int
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    out = np.empty(shape, dtype)
+    if out.nbytes:
+        rc = _hip.hipMemcpy(out.ctypes.data, ctypes.c_void_p(int(ptr)), out.nbytes, 2)  # device to host
+        if rc != 0:
+            raise OcrError(-3, f"hipMemcpy failed ({rc})")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Batched schedule (ocr_plan_*)
+# ---------------------------------------------------------------------------
+def _mode(mode) -> int:
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+def view_desc(bvh: BVH, gbuf: DeviceGBuffer, out, mode="ao", ao_radius=1.0, light=None, seed=1, sample=0,
+              params: ReuseParams | None = None) -> ViewDesc:
+    d = ViewDesc()
+    d.bvh = bvh.h.value
+    d.gbuf = gbuf.c()
+    d.mode = _mode(mode)
+    d.ao_radius = float(ao_radius)
+    if light is not None:
+        d.light = light_struct(light)
+    d.seed = int(seed)
+    d.sample = int(sample)
+    d.params = params or reuse_params()
+    d.out = _dptr(out)
+    return d
+
+
+def plan_tuning(tile=(16, 16), packing="block8", use_graph=True) -> PlanTuning:
+    return PlanTuning(int(tile[0]), int(tile[1]), PACKINGS[packing] if isinstance(packing, str) else int(packing),
+                      1 if use_graph else 0)
+
+
+class Plan:
+    """A batched schedule over many views (ocr_plan_*).  The caller keeps the
+    BVHs, G-buffers and output tensors alive; `keep` holds references."""
+
+    def __init__(self, views: list, tuning: PlanTuning | None = None, stream=None, keep=None):
+        arr = (ViewDesc * len(views))(*views)
+        h = ctypes.c_void_p()
+        _check(lib().ocr_plan_create(arr, len(views), ctypes.byref(tuning) if tuning is not None else None,
+                                     _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.keep = keep
+
+    def launch(self, stream=None):
+        _check(lib().ocr_plan_launch(self.h, _stream(stream)))
+
+    def info(self) -> PlanInfo:
+        out = PlanInfo()
+        _check(lib().ocr_plan_get_info(self.h, ctypes.byref(out)))
+        return out
+
+    def records(self, v: int) -> _Occ:
+        o = _Occ()
+        _check(lib().ocr_plan_get_records(self.h, int(v), ctypes.byref(o)))
+        return o
+
+    def records_host(self, v: int, H: int, W: int):
+        """(dz, nz, hit) of view v copied to host (after the launch finished)."""
+        o = self.records(v)
+        return (device_to_host(o.dz, (H, W, 3), np.float32), device_to_host(o.nz, (H, W, 3), np.float32),
+                device_to_host(o.hit, (H, W), np.uint32))
+
+    def free(self):
+        if getattr(self, "h", None) and self.h.value:
+            _check(lib().ocr_plan_free(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Served loop (ocr_server_*)
+# ---------------------------------------------------------------------------
+def server_now_ms() -> float:
+    return float(lib().ocr_server_now_ms())
+
+
+def request(scene_id: int, view: int, mode="ao", ao_radius=1.0, light=None, seed=1, sample=0,
+            params: ReuseParams | None = None, out=None, arrival_ms=0.0) -> Request:
+    r = Request()
+    r.scene_id = int(scene_id)
+    r.view = int(view)
+    r.mode = _mode(mode)
+    r.ao_radius = float(ao_radius)
+    if light is not None:
+        r.light = light_struct(light)
+    r.seed = int(seed)
+    r.sample = int(sample)
+    r.params = params or reuse_params()
+    r.out = (_dptr(out) if not isinstance(out, int) else out) if out is not None else None
+    r.arrival_ms = float(arrival_ms)
+    return r
+
+
+class Server:
+    """Served loop (ocr_server_*): resident scenes, HBM-budget admission,
+    concurrent slots.  mock=True runs the scheduler without a device."""
+
+    def __init__(self, budget_bytes: int, slots: int = 8, max_queue: int = 0, poll_us: int = 0,
+                 mock: bool = False, mock_ns_per_pixel: float = 0.0):
+        opt = ServerOptions(int(budget_bytes), int(slots), int(max_queue), int(poll_us), 1 if mock else 0,
+                            float(mock_ns_per_pixel))
+        h = ctypes.c_void_p()
+        _check(lib().ocr_server_create(ctypes.byref(opt), ctypes.byref(h)))
+        self.h = h
+        self.keep = []
+
+    def add_scene(self, bvh: BVH | None, gbufs: list) -> int:
+        arr = (_GBuffer * len(gbufs))(*[g if isinstance(g, _GBuffer) else g.c() for g in gbufs])
+        sid = ctypes.c_int32()
+        _check(lib().ocr_server_add_scene(self.h, bvh.h if bvh is not None else None, arr, len(gbufs),
+                                          ctypes.byref(sid)))
+        self.keep.append((bvh, gbufs))
+        return int(sid.value)
+
+    def submit(self, req: Request) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().ocr_server_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
+        return int(t.value)
+
+    def try_submit(self, req: Request):
+        """(status, ticket): no exception for refusals."""
+        t = ctypes.c_uint64()
+        st = lib().ocr_server_submit(self.h, ctypes.byref(req), ctypes.byref(t))
+        return int(st), int(t.value)
+
+    def poll(self, max_results: int = 256) -> list:
+        buf = (Result * max_results)()
+        n = ctypes.c_int32()
+        _check(lib().ocr_server_poll(self.h, buf, max_results, ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def release(self, ticket: int):
+        _check(lib().ocr_server_release(self.h, int(ticket)))
+
+    def drain(self):
+        _check(lib().ocr_server_drain(self.h))
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(lib().ocr_server_get_stats(self.h, ctypes.byref(st)))
+        return st
+
+    def destroy(self):
+        if getattr(self, "h", None) and self.h.value:
+            _check(lib().ocr_server_destroy(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

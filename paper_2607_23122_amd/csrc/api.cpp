@@ -10,21 +10,17 @@
 #include <new>
 #include <string>
 
+#include "api_internal.hpp"
 #include "bvh_build.hpp"
-#include "ocr_common.hpp"
 
 using namespace ocr;
 
-struct ocr_bvh {
-    DeviceBVH dev;
-    void *mem = nullptr;  // one allocation: nodes then triangles
-    int device = 0;
-    ocr_bvh_info info{};
-};
-
 namespace {
-
 thread_local std::string g_err;
+bool finite3(const float *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+}  // namespace
+
+namespace ocr {
 
 ocr_status fail(ocr_status st, const char *fmt, ...) {
     char buf[512];
@@ -39,8 +35,6 @@ ocr_status fail(ocr_status st, const char *fmt, ...) {
 ocr_status hip_fail(hipError_t e, const char *what) {
     return fail(OCR_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
-
-bool finite3(const float *v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
 ocr_status check_gbuf(const ocr_gbuffer *g) {
     if (!g) return fail(OCR_ERR_INVALID_ARG, "gbuffer is NULL");
@@ -98,7 +92,20 @@ ocr_status check_params(const ocr_reuse_params *p) {
     return OCR_OK;
 }
 
-GBufView view(const ocr_gbuffer *g) { return GBufView{g->pos, g->nrm, g->prim, g->width, g->height}; }
+ocr_status check_effect(int32_t mode, float ao_radius, const ocr_rect_light *light, LightF &L) {
+    std::memset(&L, 0, sizeof L);
+    if (mode == OCR_AO) {
+        if (!(std::isfinite(ao_radius) && ao_radius > 0.0f))
+            return fail(OCR_ERR_INVALID_ARG, "AO radius %g must be finite and > 0", (double)ao_radius);
+        return OCR_OK;
+    }
+    if (mode == OCR_SHADOW) return make_light(light, L);
+    return fail(OCR_ERR_INVALID_ARG, "mode %d out of range", mode);
+}
+
+}  // namespace ocr
+
+namespace {
 
 ocr_status reuse_common(const ocr_bvh *bvh, const ocr_gbuffer *g, const ocr_occluders *occ, int mode, float R,
                         const LightF &L, const ocr_reuse_params *p, void *ws, size_t ws_bytes, float *out,

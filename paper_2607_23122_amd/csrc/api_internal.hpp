@@ -1,0 +1,31 @@
+// Host-side pieces shared by the C-ABI translation units (api.cpp, plan.cpp,
+// server.cpp): the BVH handle's layout, argument checks and the thread-local
+// error report.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ocr_common.hpp"
+
+struct ocr_bvh {
+    ocr::DeviceBVH dev;
+    void *mem = nullptr;  // one allocation: nodes then triangles
+    int device = 0;
+    ocr_bvh_info info{};
+};
+
+namespace ocr {
+
+// Record `fmt` as this thread's last error and return `st`.
+ocr_status fail(ocr_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+ocr_status hip_fail(hipError_t e, const char *what);
+
+ocr_status check_gbuf(const ocr_gbuffer *g);
+ocr_status check_params(const ocr_reuse_params *p);
+// Validate a rectangular light and derive the kernels' FP32 form.
+ocr_status make_light(const ocr_rect_light *l, LightF &L);
+// Validate (mode, AO radius, light) as the trace does; fills L (zero for AO).
+ocr_status check_effect(int32_t mode, float ao_radius, const ocr_rect_light *light, LightF &L);
+
+inline GBufView view(const ocr_gbuffer *g) { return GBufView{g->pos, g->nrm, g->prim, g->width, g->height}; }
+
+}  // namespace ocr

@@ -1,0 +1,228 @@
+// Sliding-window occluder-domain MIS reuse of one target tile (Sec. 4.2-4.4;
+// steps 2-3 of App. D / App. H), shared by the per-frame reuse kernel and the
+// batched schedule.
+//
+// For a target i with reuse set S(i):
+//   B_i = sum_{j in S(i), hit_j} [p_i(j) > 0 and P_i(j) > 0] p_i(j) / P_i(j),
+//   P_i(j) = sum_{k in S(i)} p_k(j),
+// p = the pair density (validated by the first-hit bits when unbiased).
+//
+// P_i(j) depends on both i and j, but only through the pair densities p_k(j)
+// with k - j in [-2R, 2R]^2, each needed by every target whose window holds
+// both.  So each candidate j is handled by one wave that evaluates those
+// (4R+1)^2 densities once, forms every P_i(j) for the (2R+1)^2 targets around
+// j as box sums, and scatters p_i(j)/P_i(j) to the targets.  A block owns a
+// 16x16 target tile and stages the receivers of the tile plus an R-pixel halo
+// in LDS; the scattered terms are summed in LDS as 32.32 fixed-point
+// integers, which makes the sum independent of the order in which waves
+// arrive (bitwise reproducible) at ~2^-33 absolute error per term.
+#pragma once
+#include "density.hpp"
+#include "ocr_common.hpp"
+
+namespace ocr {
+
+constexpr int kRBlock = 256;
+constexpr int kWT = 16;  // window tile side
+
+__device__ inline void ld3(const float *p, int64_t i, float v[3]) {
+    v[0] = p[3 * i];
+    v[1] = p[3 * i + 1];
+    v[2] = p[3 * i + 2];
+}
+
+__device__ inline float finish(int mode, bool valid, float B, float F, bool dark, float prev, int accumulate) {
+    float v;
+    if (mode == OCR_AO) v = valid ? 1.0f - B : 1.0f;
+    else v = valid ? (dark ? 0.0f : F - B) : 0.0f;
+    return accumulate ? prev + v : v;
+}
+
+// LDS layout of the window kernel for radius R (dynamic shared memory).
+struct WinLayout {
+    int RW, cells, side, dens, hsum, words;
+    size_t o_off, n_off, sh_off, valid_off, miss_off, list_off, B_off, wave_off, total;
+};
+
+__host__ __device__ inline size_t lds_take(size_t &off, size_t bytes) {
+    size_t at = off;
+    off += (bytes + 15) & ~(size_t)15;
+    return at;
+}
+
+__host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int words) {
+    WinLayout l;
+    l.RW = kWT + 2 * R;
+    l.cells = l.RW * l.RW;
+    l.side = 4 * R + 1;
+    l.dens = l.side * l.side;
+    l.hsum = l.side * (2 * R + 1);
+    l.words = words;
+    size_t off = 0;
+    l.B_off = lds_take(off, sizeof(unsigned long long) * kWT * kWT);
+    l.o_off = lds_take(off, sizeof(float) * 3 * l.cells);
+    l.n_off = lds_take(off, sizeof(float) * 3 * l.cells);
+    l.sh_off = lds_take(off, mode == OCR_SHADOW ? sizeof(float) * 3 * l.cells : 0);
+    l.valid_off = lds_take(off, l.cells);
+    l.miss_off = lds_take(off, l.cells);
+    l.list_off = lds_take(off, 4 * sizeof(int) + sizeof(uint16_t) * l.cells);
+    l.wave_off = lds_take(off, sizeof(float) * (kRBlock / 64) * (l.dens + l.hsum));
+    l.total = off;
+    return l;
+}
+
+// Make this wave's LDS writes visible to its other lanes before they read.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One 16x16 target tile (tx, ty) of the sliding-window estimator; every
+// thread of the block calls it.  `smem` holds win_layout(R, ...).total bytes.
+template <int MODE, bool UNB>
+__device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g, const OccView &occ, float R2,
+                                         const LightF &L, const uint32_t *__restrict__ bits, int words, int R,
+                                         int dark_guard, int accumulate, float *out, int tx, int ty) {
+    const WinLayout lay = win_layout(R, MODE, UNB, words);
+    const int T = kWT, RW = lay.RW, CELLS = lay.cells, D = 2 * R, SIDE = lay.side, TW = 2 * R + 1;
+    unsigned long long *s_B = reinterpret_cast<unsigned long long *>(smem + lay.B_off);
+    float *s_o = reinterpret_cast<float *>(smem + lay.o_off);    // [3][cells]
+    float *s_n = reinterpret_cast<float *>(smem + lay.n_off);    // [3][cells]
+    float *s_sh = reinterpret_cast<float *>(smem + lay.sh_off);  // [3][cells]
+    uint8_t *s_valid = smem + lay.valid_off;
+    uint8_t *s_miss = smem + lay.miss_off;
+    int *s_count = reinterpret_cast<int *>(smem + lay.list_off);
+    uint16_t *s_list = reinterpret_cast<uint16_t *>(smem + lay.list_off + 4 * sizeof(int));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float *w_dens = reinterpret_cast<float *>(smem + lay.wave_off) + wave * (lay.dens + lay.hsum);
+    float *w_h = w_dens + lay.dens;
+
+    const int x0 = tx * T - R, y0 = ty * T - R;
+    const int tid = threadIdx.x;
+    if (tid == 0) *s_count = 0;
+    for (int t = tid; t < T * T; t += kRBlock) s_B[t] = 0ull;
+    __syncthreads();
+
+    // Stage receivers (o, n, shadow terms), validity, misses, validation
+    // bits, and compact the cells whose ray found an occluder.
+    for (int c = tid; c < CELLS; c += kRBlock) {
+        int gx = x0 + c % RW, gy = y0 + c / RW;
+        bool inside = gx >= 0 && gx < g.w && gy >= 0 && gy < g.h;
+        int64_t gi = inside ? (int64_t)gy * g.w + gx : 0;
+        bool valid = inside && g.prim[gi] != OCR_HIT_MISS;
+        float o[3] = {0.f, 0.f, 0.f}, n[3] = {0.f, 0.f, 0.f};
+        uint32_t hit = OCR_HIT_MISS;
+        if (valid) {
+            float x[3];
+            ld3(g.pos, gi, x);
+            ld3(g.nrm, gi, n);
+            offset_point(x, n, o);
+            hit = occ.hit[gi];
+        }
+        for (int a = 0; a < 3; ++a) {
+            s_o[a * CELLS + c] = o[a];
+            s_n[a * CELLS + c] = n[a];
+        }
+        if (MODE == OCR_SHADOW) {
+            RecvShadow rk = {0.f, 0.f, 0.f};
+            if (valid) rk = recv_shadow(o, L);
+            s_sh[c] = rk.hk;
+            s_sh[CELLS + c] = rk.ak;
+            s_sh[2 * CELLS + c] = rk.bk;
+        }
+        s_valid[c] = valid;
+        s_miss[c] = valid && hit == OCR_HIT_MISS;
+        if (valid && hit < OCR_HIT_SELF) s_list[atomicAdd(s_count, 1)] = (uint16_t)c;
+    }
+    __syncthreads();
+
+    // One wave per candidate j.
+    const int ncand = *s_count;
+    for (int li = wave; li < ncand; li += kRBlock / 64) {
+        const int c = __builtin_amdgcn_readfirstlane((int)s_list[li]);
+        const int cx = c % RW, cy = c / RW;
+        const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
+        float oj[3] = {s_o[c], s_o[CELLS + c], s_o[2 * CELLS + c]};
+        float dzj[3], nzj[3];
+        ld3(occ.dz, gj, dzj);
+        ld3(occ.nz, gj, nzj);
+        // (1) densities p_k(j), k - j in [-2R, 2R]^2 (0 outside the staged region)
+        for (int q = lane; q < lay.dens; q += 64) {
+            const int dy = q / SIDE - D, dx = q % SIDE - D;
+            const int kx = cx + dx, ky = cy + dy;
+            float p = 0.0f;
+            if ((unsigned)kx < (unsigned)RW && (unsigned)ky < (unsigned)RW) {
+                const int kc = ky * RW + kx;
+                float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
+                float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
+                float w[3];
+                rel_vec(oj, ok, dzj, w);
+                if (MODE == OCR_AO) {
+                    p = dens_ao(w, nk, nzj, R2);
+                } else {
+                    RecvShadow rk = {s_sh[kc], s_sh[CELLS + kc], s_sh[2 * CELLS + kc]};
+                    p = dens_shadow(w, nk, rk, nzj, L);
+                }
+                if (UNB && p > 0.0f) {
+                    // candidate j's validation bit for the receiver at offset k - j = (dx, dy): bit q
+                    const uint32_t wv = bits[gj * words + (q >> 5)];
+                    if (!((wv >> (q & 31)) & 1u)) p = 0.0f;
+                }
+            }
+            w_dens[q] = p;
+        }
+        wave_sync();
+        // (2) row box sums H[row][t2] = sum_{e < 2R+1} p(row, t2 + e)
+        for (int q = lane; q < lay.hsum; q += 64) {
+            const int row = q / TW, t2 = q % TW;
+            const float *pr = w_dens + row * SIDE + t2;
+            float h = 0.0f;
+            for (int e = 0; e < TW; ++e) h += pr[e];
+            w_h[q] = h;
+        }
+        wave_sync();
+        // (3) target i = j + (t2 - R, r2 - R): P_i(j) is the column box sum of H
+        for (int q = lane; q < TW * TW; q += 64) {
+            const int r2 = q / TW, t2 = q % TW;
+            const int ix = cx + t2 - 2 * R, iy = cy + r2 - 2 * R;  // tile coordinates of i
+            if ((unsigned)ix < (unsigned)T && (unsigned)iy < (unsigned)T) {
+                float P = 0.0f;
+                for (int e = 0; e < TW; ++e) P += w_h[(r2 + e) * TW + t2];
+                const float pij = w_dens[(r2 + R) * SIDE + (t2 + R)];
+                if (pij > 0.0f && P > 0.0f)
+                    atomicAdd(&s_B[iy * T + ix], (unsigned long long)rintf((pij / P) * 4294967296.0f));
+            }
+        }
+        wave_sync();
+    }
+    __syncthreads();
+
+    // one lane per target
+    for (int t = tid; t < T * T; t += kRBlock) {
+        const int ix = t % T, iy = t / T;
+        const int px = tx * T + ix, py = ty * T + iy;
+        if (px >= g.w || py >= g.h) continue;
+        const int c = (iy + R) * RW + (ix + R);
+        const bool valid = s_valid[c];
+        const float B = (float)((double)s_B[t] * 0x1p-32);
+        float F = 1.0f;
+        bool dark = false;
+        if (MODE == OCR_SHADOW && valid) {
+            float o[3] = {s_o[c], s_o[CELLS + c], s_o[2 * CELLS + c]};
+            float n[3] = {s_n[c], s_n[CELLS + c], s_n[2 * CELLS + c]};
+            F = front_fraction(o, n, L);
+            if (dark_guard) {
+                int misses = 0;
+                for (int dy = -R; dy <= R; ++dy)
+                    for (int dx = -R; dx <= R; ++dx) misses += s_miss[c + dy * RW + dx];
+                dark = misses == 0;
+            }
+        }
+        const int64_t gi = (int64_t)py * g.w + px;
+        out[gi] = finish(MODE, valid, B, F, dark, accumulate ? out[gi] : 0.0f, accumulate);
+    }
+}
+
+
+}  // namespace ocr

@@ -2,6 +2,7 @@
 // validation rays of the unbiased estimators (Eq. occ-first-hit).
 #include "density.hpp"
 #include "ocr_common.hpp"
+#include "trace_pixel.hpp"
 #include "traverse.hpp"
 
 namespace ocr {
@@ -28,12 +29,6 @@ __device__ inline void pixel_of_thread(int tx, int ty, int &px, int &py) {
     py = ty * kTile + (wv >> 1) * 8 + (ln >> 3);
 }
 
-__device__ inline void load3(const float *p, int64_t i, float v[3]) {
-    v[0] = p[3 * i];
-    v[1] = p[3 * i + 1];
-    v[2] = p[3 * i + 2];
-}
-
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g, float R, LightF L, uint32_t sd,
                                                        uint32_t sample, OccView out, int tiles_x, int ntiles) {
@@ -44,43 +39,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g
     int px, py;
     pixel_of_thread(tx, ty, px, py);
     if (px >= g.w || py >= g.h) return;
-    int64_t i = (int64_t)py * g.w + px;
-    uint32_t prim = g.prim[i];
-    if (prim == OCR_HIT_MISS) {
-        out.hit[i] = OCR_HIT_MISS;
-        return;
-    }
-    float x[3], n[3], o[3], d[3];
-    load3(g.pos, i, x);
-    load3(g.nrm, i, n);
-    offset_point(x, n, o);
-    float tmax;
-    if (MODE == OCR_AO) {
-        ao_direction((uint32_t)px, (uint32_t)py, sample, sd, n, d);
-        tmax = R;
-    } else {
-        float y[3];
-        light_point((uint32_t)px, (uint32_t)py, sample, sd, L, y);
-        d[0] = y[0] - o[0];
-        d[1] = y[1] - o[1];
-        d[2] = y[2] - o[2];
-        if (!shadow_traced(n, o, d, L)) {
-            out.hit[i] = OCR_HIT_SELF;
-            return;
-        }
-        tmax = 1.0f;
-    }
-    TRay r;
-    make_ray(o, d, prim, OCR_HIT_MISS, r);
-    Hit h = traverse<false, MODE == OCR_AO>(bvh, r, tmax, stack + threadIdx.x, kBlock);
-    out.hit[i] = h.tri;
-    if (h.tri == OCR_HIT_MISS) return;
-    float nz[3];
-    oriented_normal(bvh, h.leaf_tri, d, nz);
-    for (int c = 0; c < 3; ++c) {
-        out.dz[3 * i + c] = h.t * d[c];
-        out.nz[3 * i + c] = nz[c];
-    }
+    trace_pixel<MODE>(bvh, g, R, L, sd, sample, out, px, py, stack + threadIdx.x, kBlock);
 }
 
 // Candidate lists for the window validation: every pixel whose ray found an

@@ -396,3 +396,13 @@ BATCH_SIZES = [(640, 360), (2560, 1440), (960, 540), (1920, 1080), (1280, 720), 
 def batch_scene(i: int) -> Scene:
     s = BATCH_SCENES[i]
     return terrain_scene(seed=s["seed"], cells=s["cells"], nspheres=s["spheres"])
+
+
+def batch_views():
+    """The sixteen views of the batched workload: view v shows scene v mod 4
+    from orbit angle 2*pi*v/16 at BATCH_SIZES[v]; AO (R = 2 m) if v is even,
+    else the 1 x 1 m shadow light.  Returns [(scene_index, camera, mode)]."""
+    out = []
+    for v, (W, H) in enumerate(BATCH_SIZES):
+        out.append((v % 4, orbit_camera(v, 16, W, H), "ao" if v % 2 == 0 else "shadow"))
+    return out
