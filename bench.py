@@ -1,10 +1,11 @@
 #!/usr/bin/env python3
 """Benchmark of the occlusion-point-reuse hot path on one MI355X.
 
-Workload (default): ambient occlusion at 1920x1080 over a displaced terrain
-(512x512 cells, fBm heights) with 2000 level-2 icospheres (1,164,288
+Workload ao_1080p (default): ambient occlusion at 1920x1080 over a displaced
+terrain (512x512 cells, fBm heights) with 2000 level-2 icospheres (1,164,288
 triangles), 1 sample per pixel, AO radius 2 m, 7x7 reuse window; synthetic,
-seeded inputs standing in for the paper's scenes.
+seeded inputs standing in for the paper's scenes.  shadow_1080p: the same
+with the 1 x 1 m rectangular light.
 
 One step = the whole per-frame path on one batch of input (a new sample
 index each step): occluder tracing (sample generation fused), the no-reuse
@@ -12,10 +13,21 @@ estimate, the biased 7x7 reuse, the first-hit validation rays and the
 unbiased 7x7 reuse.  `value` is Mrays/s over the whole step: traced primary
 rays per second.  Inputs are resident in HBM before the timed region.
 
+batched_16: sixteen views of uneven size (640x360 .. 2560x1440, 24,652,800
+px) over four terrain scenes (50k .. 2M triangles), AO on even views and
+shadows on odd ones, biased 7x7, as one autotuned plan (persistent trace and
+reuse launches replayed from a HIP graph); a step is one plan launch, the
+baseline sixteen separate per-view launch pairs.
+
+served: Poisson arrivals over eight resident scenes and a pool of 720p,
+1080p and 1440p G-buffers per scene, AO or shadow at 1 spp with biased 7x7
+reuse, admitted under an HBM budget onto 8 stream slots; the baseline is a
+one-slot FIFO server on the same arrival trace.
+
 Per-kernel times come from HIP events on the stream the library launches
 on (torch's current stream, passed through the C-ABI).  The roofline entry
 is for the kernel with the largest share of the step.  The CPU baseline is
-the oracle on a bounded sample of the same frame.
+the oracle on a bounded sample of the same work.
 """
 import argparse
 import json
@@ -43,7 +55,31 @@ WORKLOADS = {
     "ao_1080p": dict(mode="ao", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2, sample_seed=1),
     "shadow_1080p": dict(mode="shadow", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2,
                          sample_seed=1),
+    "batched_16": dict(radius=2.0, window_r=3, sample_seed=1),
+    "served": dict(radius=2.0, window_r=3, rate=400.0, budget_gib=4.0, slots=8),
 }
+# served scenes: the batched generator's sizes twice, seeds 100..107
+SERVED_SCENES = [dict(seed=100 + i, cells=c, spheres=n)
+                 for i, (c, n) in enumerate([(128, 54), (256, 375), (512, 2000), (768, 2560)] * 2)]
+SERVED_SIZES = [(1280, 720), (1920, 1080), (2560, 1440)]
+
+
+def alu_roofline(stats, ms, kernel):
+    """Useful FP32 ops of the counted box and triangle tests per launch over
+    the launch's average duration, against the VALU peak."""
+    ops = OPS_BOX * stats[2] + OPS_TRI * stats[3]
+    tops = ops / (ms * 1e-3) / 1e12
+    return dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
+                frac=round(tops / VALU_PEAK_TOPS, 4), traffic=None, kernel=kernel,
+                work={"walks": int(stats[0]), "node_visits": int(stats[1]), "box_tests": int(stats[2]),
+                      "tri_tests": int(stats[3])})
+
+
+def counted_trace(ocr, torch, bvh, dg, mode, R, light, seed, sample):
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    ocr.trace_occluders_counted(bvh, dg, stats, mode, R, light, seed, sample)
+    torch.cuda.synchronize()
+    return [int(v) for v in stats.cpu().tolist()]
 
 
 def log(msg):
@@ -71,21 +107,38 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle work for the baseline")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this size (to scale HBM byte counters)")
+    ap.add_argument("--served-seconds", type=float, default=10.0, help="measured arrival window (served)")
+    ap.add_argument("--served-warmup-seconds", type=float, default=2.0, help="arrivals before measuring (served)")
+    ap.add_argument("--served-poses", type=int, default=2, help="camera poses per scene and resolution (served)")
+    ap.add_argument("--served-baseline", default="on", choices=["on", "off"],
+                    help="also run the one-slot FIFO server on the same arrivals")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (a frame would shard by image "
               "bands with halo recompute, see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "batched_16":
+        result = run_batched(args)
+    elif args.workload == "served":
+        result = run_served(args)
+    else:
+        result = run_frame(args)
+    print(json.dumps(result), flush=True)
+
+
+def run_frame(args):
     import numpy as np
     import torch
 
     import paper_2607_23122_amd as ocr
     import workloads as w
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(2)
     cfg = WORKLOADS[args.workload]
     mode, W, H, R, r = cfg["mode"], cfg["width"], cfg["height"], cfg["radius"], cfg["window_r"]
     t0 = time.time()
@@ -225,9 +278,265 @@ def main():
         "roofline": roof,
     }
 
+    result["trace_roofline"] = alu_roofline(
+        counted_trace(ocr, torch, bvh, dg, mode, R, light, cfg["sample_seed"], args.steps - 1), per["trace"],
+        "trace_kernel")
     if args.cpu_baseline == "on":
         result["cpu_baseline"] = cpu_baseline(scene, gb, cfg, light, args.cpu_seconds)
-    print(json.dumps(result), flush=True)
+    return result
+
+
+def _events(torch, n):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+
+    import paper_2607_23122_amd as ocr
+    import workloads as w
+
+    cfg = WORKLOADS["batched_16"]
+    R, r, seed = cfg["radius"], cfg["window_r"], cfg["sample_seed"]
+    t0 = time.time()
+    scenes = [w.batch_scene(i) for i in range(4)]
+    light = w.terrain_light()
+    views = []
+    for si, cam, mode in w.batch_views():
+        views.append((si, w.render_gbuffer(scenes[si], cam), mode))
+    px = sum(gb.width * gb.height for _, gb, _ in views)
+    log(f"[bench] batched inputs {time.time() - t0:.1f}s: {[s.ntris for s in scenes]} tris, 16 views, {px} px")
+    bvhs = [ocr.build_bvh(s.V, s.F) for s in scenes]
+    dgs = [ocr.DeviceGBuffer.from_host(gb) for _, gb, _ in views]
+    params = ocr.reuse_params("window", r, 0, "biased")
+    outs = [torch.empty((gb.height, gb.width), dtype=torch.float32, device="cuda") for _, gb, _ in views]
+    descs = [ocr.view_desc(bvhs[si], dgs[v], outs[v], mode, R, light if mode == "shadow" else None, seed, 0, params)
+             for v, (si, gb, mode) in enumerate(views)]
+    plan = ocr.Plan(descs)  # autotuned
+    info = plan.info()
+    tun = info.tuning
+    log(f"[bench] autotuned: tile {tun.tile_w}x{tun.tile_h} packing {tun.packing}, trace {info.best_trace_ms:.3f} ms "
+        f"({info.candidates} settings, {info.tune_ms:.0f} ms)")
+    plan_eager = ocr.Plan(descs, ocr.PlanTuning(tun.tile_w, tun.tile_h, tun.packing, 0))
+    stream = torch.cuda.current_stream()
+    # per-view baseline: sixteen separate launch pairs into the same outputs
+    occs = [ocr.Occluders.empty(gb.height, gb.width) for _, gb, _ in views]
+
+    def per_view():
+        for v, (si, gb, mode) in enumerate(views):
+            lt = light if mode == "shadow" else None
+            ocr.trace_occluders(bvhs[si], dgs[v], mode, R, lt, seed, 0, occs[v])
+            if mode == "ao":
+                ocr.reuse_ao(None, dgs[v], occs[v], R, params, outs[v])
+            else:
+                ocr.reuse_shadow(None, dgs[v], occs[v], light, params, outs[v])
+
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        ev = _events(torch, 2)
+        t = time.perf_counter()
+        ev[0].record(stream)
+        for _ in range(steps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps, (time.perf_counter() - t) * 1e3 / steps
+
+    ms_plan, wall_plan = timed(plan.launch, args.steps, args.warmup)
+    ms_eager, _ = timed(plan_eager.launch, args.steps, args.warmup)
+    ms_pv, wall_pv = timed(per_view, args.steps, args.warmup)
+    log(f"[bench] batched {ms_plan:.3f} ms/launch (wall {wall_plan:.3f}), no graph {ms_eager:.3f}, "
+        f"16 per-view pairs {ms_pv:.3f} (wall {wall_pv:.3f})")
+    # trace-phase time of the tuned plan, and the traced work (counted per view)
+    plan_trace_ms = info.best_trace_ms
+    work = np.zeros(4, np.int64)
+    for v, (si, gb, mode) in enumerate(views):
+        work += np.array(counted_trace(ocr, torch, bvhs[si], dgs[v], mode, R, light if mode == "shadow" else None,
+                                       seed, 0), np.int64)
+    frames_s = 16.0 / (ms_plan * 1e-3)
+    result = {
+        "metric": "frames/s, 16 batched views of uneven size (24.65 Mpx), biased 7x7",
+        "value": round(frames_s, 1),
+        "unit": "frames/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_plan, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched_16: 4 terrain scenes " + str([s.ntris for s in scenes]) +
+                               " tris, 16 orbit views 640x360..2560x1440, AO even / shadow odd, R=2 m, 7x7 biased, "
+                               "one autotuned plan launch",
+                   "global_batch": 16, "seq_len": px, "parallelism": "single-gpu"},
+        "mpx_per_s": round(px / (ms_plan * 1e-3) / 1e6, 1),
+        "plan_ms": round(ms_plan, 4),
+        "plan_no_graph_ms": round(ms_eager, 4),
+        "per_view_pairs_ms": round(ms_pv, 4),
+        "speedup_vs_per_view": round(ms_pv / ms_plan, 3),
+        "tuning": {"tile": f"{tun.tile_w}x{tun.tile_h}", "packing": ["row", "block8", "morton"][tun.packing],
+                   "candidates": info.candidates, "tune_ms": round(info.tune_ms, 1),
+                   "trace_phase_ms": round(plan_trace_ms, 4)},
+        "roofline": alu_roofline(work, plan_trace_ms, "batch_trace_kernel"),
+    }
+    if args.cpu_baseline == "on":
+        result["cpu_baseline"] = cpu_baseline_views(scenes, views, cfg, light, args.cpu_seconds, px / 16.0)
+    return result
+
+
+def run_served(args):
+    import numpy as np
+    import torch
+
+    import paper_2607_23122_amd as ocr
+    import workloads as w
+
+    cfg = WORKLOADS["served"]
+    R, r = cfg["radius"], cfg["window_r"]
+    t0 = time.time()
+    light = w.terrain_light()
+    bvhs, pools, scenes = [], [], []
+    for i, sc in enumerate(SERVED_SCENES):
+        s = w.terrain_scene(seed=sc["seed"], cells=sc["cells"], nspheres=sc["spheres"])
+        scenes.append(s)
+        bvhs.append(ocr.build_bvh(s.V, s.F))
+        pool = []
+        for pose in range(args.served_poses):
+            for (W, H) in SERVED_SIZES:
+                cam = w.orbit_camera(pose * 3 + i, 8 * args.served_poses, W, H)
+                pool.append(ocr.DeviceGBuffer.from_host(w.render_gbuffer(s, cam)))
+        pools.append(pool)
+        log(f"[bench] served scene {i}: {s.ntris} tris, {len(pool)} G-buffers ({time.time() - t0:.0f} s)")
+    torch.cuda.synchronize()
+    params = ocr.reuse_params("window", r, 0, "biased")
+    rate = cfg["rate"]
+    total_s = args.served_warmup_seconds + args.served_seconds
+    rng = np.random.default_rng(7)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * total_s * 1.5) + 16))
+    arrivals = arrivals[arrivals < total_s]
+    picks = [(int(rng.integers(8)), int(rng.integers(len(pools[0]))), "ao" if rng.random() < 0.5 else "shadow")
+             for _ in range(len(arrivals))]
+    px_of = [[dg.width * dg.height for dg in pool] for pool in pools]
+    offered_gpx = sum(px_of[s][v] for s, v, _ in picks) / total_s / 1e9
+
+    def serve(slots):
+        srv = ocr.Server(int(cfg["budget_gib"] * 2 ** 30), slots=slots, poll_us=10)
+        sids = [srv.add_scene(bvhs[i], pools[i]) for i in range(8)]
+        start = ocr.server_now_ms() + 50.0
+        lat = {}
+        k = 0
+        while len(lat) < len(arrivals):
+            now = ocr.server_now_ms()
+            while k < len(arrivals) and start + arrivals[k] * 1e3 <= now:
+                si, vi, mode = picks[k]
+                srv.submit(ocr.request(sids[si], vi, mode, R, light if mode == "shadow" else None, k, 0, params,
+                                       None, start + arrivals[k] * 1e3))
+                k += 1
+            for res in srv.poll(1024):
+                if res.status != 0:
+                    raise RuntimeError(f"request failed: {res.status}")
+                lat[res.ticket] = (res.arrival_ms - start, res.latency_ms, res.end_ms - start)
+                srv.release(res.ticket)
+            if k < len(arrivals):
+                nxt = start + arrivals[k] * 1e3
+                time.sleep(max(0.0, min(nxt - ocr.server_now_ms(), 1.0)) * 1e-3)
+            else:
+                time.sleep(0.0002)
+        st = srv.stats()
+        srv.destroy()
+        warm = args.served_warmup_seconds * 1e3
+        meas = [(a, l, e) for a, l, e in lat.values() if a >= warm]
+        ls = np.sort(np.array([l for _, l, _ in meas]))
+        span = (max(e for _, _, e in meas) - warm) * 1e-3
+
+        def pct(q):
+            return float(ls[min(len(ls) - 1, max(0, int(np.ceil(q * len(ls))) - 1))])
+        return dict(requests=len(meas), frames_per_s=round(len(meas) / span, 1), p50_ms=round(pct(0.5), 3),
+                    p99_ms=round(pct(0.99), 3), max_ms=round(float(ls[-1]), 3), mean_ms=round(float(ls.mean()), 3),
+                    max_in_flight=int(st.max_in_flight), waited_for_memory=int(st.waited_for_memory),
+                    peak_mb=round(st.peak_bytes / 2 ** 20, 1))
+
+    log(f"[bench] served: {len(arrivals)} Poisson arrivals at {rate}/s over {total_s:.0f} s, "
+        f"offered {offered_gpx:.3f} Gpx/s")
+    main_run = serve(cfg["slots"])
+    log(f"[bench] {cfg['slots']} slots: {main_run}")
+    base = None
+    if args.served_baseline == "on":
+        base = serve(1)
+        log(f"[bench] 1-slot FIFO: {base}")
+    # the dominant kernel as served: the trace of one 1080p request, timed and counted
+    si, vi = 2, 1
+    dg = pools[si][vi]
+    occ = ocr.Occluders.empty(dg.height, dg.width)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        ocr.trace_occluders(bvhs[si], dg, "ao", R, None, 1, 0, occ)
+    ev = _events(torch, 2)
+    ev[0].record(stream)
+    for s in range(10):
+        ocr.trace_occluders(bvhs[si], dg, "ao", R, None, 1, s, occ)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    trace_ms = ev[0].elapsed_time(ev[1]) / 10
+    work = counted_trace(ocr, torch, bvhs[si], dg, "ao", R, None, 1, 0)
+    stable = main_run["frames_per_s"] >= 0.95 * rate
+    result = {
+        "metric": "frames/s and p99 frame latency, served (Poisson 400/s, 720p-1440p, AO/shadow, biased 7x7)",
+        "value": main_run["frames_per_s"],
+        "unit": "frames/s",
+        "n_gpus": 1, "steps": main_run["requests"], "warmup": len(arrivals) - main_run["requests"],
+        "ms_per_step": round(1e3 / main_run["frames_per_s"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"served: 8 resident terrain scenes ({min(s.ntris for s in scenes)}.."
+                               f"{max(s.ntris for s in scenes)} tris), {args.served_poses} poses x 720p/1080p/1440p "
+                               f"G-buffers each, Poisson {rate}/s, {cfg['slots']} slots, "
+                               f"{cfg['budget_gib']} GiB budget",
+                   "global_batch": 1, "seq_len": None, "parallelism": "single-gpu"},
+        "p50_ms": main_run["p50_ms"], "p99_ms": main_run["p99_ms"],
+        "offered_gpx_per_s": round(offered_gpx, 3), "stable": bool(stable),
+        "served": main_run, "fifo_one_slot": base,
+        "roofline": alu_roofline(work, trace_ms, "trace_kernel (1080p request)"),
+    }
+    if args.cpu_baseline == "on":
+        avg_px = float(np.mean([px_of[s][v] for s, v, _ in picks]))
+        result["cpu_baseline"] = cpu_baseline_views(
+            [scenes[2]], [(0, w.render_gbuffer(scenes[2], w.orbit_camera(2, 8, 1920, 1080)), "ao")],
+            WORKLOADS["batched_16"], light, args.cpu_seconds, avg_px)
+    return result
+
+
+def cpu_baseline_views(scenes, views, cfg, light, budget_s, px_per_frame):
+    """The oracle on 64x64-target tiles drawn from the given views (records
+    for the tile's halo, then the biased 7x7 estimate) for about budget_s
+    seconds; reported as frames/s of px_per_frame pixels."""
+    import numpy as np
+
+    import oracle
+    oscs = [oracle.Scene(s.V, s.F) for s in scenes]
+    rng = np.random.default_rng(7)
+    done_px, ntiles = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        si, gb, mode = views[int(rng.integers(len(views)))]
+        W, H = gb.width, gb.height
+        x = int(rng.integers(0, W - 64))
+        y = int(rng.integers(0, H - 64))
+        t = (x, y, x + 64, y + 64)
+        p = oracle.params(mode, "biased", "window", radius=cfg["window_r"], ao_radius=cfg["radius"],
+                          light=light if mode == "shadow" else None, seed=1)
+        rec = oracle.records(oscs[si], gb, p, oracle.halo_region(p, W, H, t))
+        oracle.reuse(oscs[si], gb, p, rec, t)
+        done_px += 64 * 64
+        ntiles += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": round(done_px / el / px_per_frame, 5), "unit": "frames/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{ntiles} random 64x64-pixel tiles (with halos) of the workload's views, records + biased "
+                      f"7x7, {el:.1f} s on {cpu_model()}; {done_px / el / 1e6:.4f} Mpx/s over "
+                      f"{px_per_frame:.0f} px per frame"}
 
 
 def cpu_baseline(scene, gb, cfg, light, budget_s):

@@ -164,6 +164,16 @@ ocr_status ocr_trace_occluders(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int3
                                const ocr_rect_light *light, uint64_t seed, uint32_t sample,
                                ocr_occluders *out, void *stream);
 
+/* ocr_trace_occluders with the walks' work counted: the same records, and
+ * adds the number of rays traced, BVH node visits, box tests (4 per node
+ * visit) and triangle tests to stats (device uint64[4], caller-zeroed).  A
+ * separate, slower kernel for work accounting (roofline figures), not for
+ * frames.  Errors as ocr_trace_occluders, and OCR_ERR_INVALID_ARG for a
+ * NULL stats. */
+ocr_status ocr_trace_occluders_counted(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int32_t mode, float ao_radius,
+                                       const ocr_rect_light *light, uint64_t seed, uint32_t sample,
+                                       ocr_occluders *out, uint64_t *stats, void *stream);
+
 /* The sample step alone (row A1 of the trace): for every pixel, the offset
  * receiver point o, the ray direction (AO: the cosine-weighted direction;
  * shadow: y - o for the uniform light point y) and its kind (0 traced,

@@ -106,7 +106,8 @@ class ServerStats(ctypes.Structure):
                 ("max_ms", ctypes.c_double), ("frames_per_s", ctypes.c_double)]
 
 
-EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders", "ocr_sample_rays",
+EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders",
+           "ocr_trace_occluders_counted", "ocr_sample_rays",
            "ocr_workspace_bytes", "ocr_validate_pairs",
            "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_scale", "ocr_last_error", "ocr_version",
            "ocr_plan_create", "ocr_plan_launch", "ocr_plan_get_info", "ocr_plan_get_records", "ocr_plan_free",
@@ -135,6 +136,10 @@ def lib():
     L.ocr_trace_occluders.restype = i32
     L.ocr_trace_occluders.argtypes = [vp, ctypes.POINTER(_GBuffer), i32, ctypes.c_float, ctypes.POINTER(_Light),
                                       ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(_Occ), vp]
+    L.ocr_trace_occluders_counted.restype = i32
+    L.ocr_trace_occluders_counted.argtypes = [vp, ctypes.POINTER(_GBuffer), i32, ctypes.c_float,
+                                              ctypes.POINTER(_Light), ctypes.c_uint64, ctypes.c_uint32,
+                                              ctypes.POINTER(_Occ), vp, vp]
     L.ocr_sample_rays.restype = i32
     L.ocr_sample_rays.argtypes = [ctypes.POINTER(_GBuffer), i32, ctypes.POINTER(_Light), ctypes.c_uint64,
                                   ctypes.c_uint32, vp, vp, vp, vp]
@@ -315,6 +320,20 @@ def trace_occluders(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, lig
     lp = ctypes.byref(light_struct(light)) if light is not None else None
     _check(lib().ocr_trace_occluders(bvh.h, ctypes.byref(g), m, float(ao_radius), lp, int(seed), int(sample),
                                      ctypes.byref(o), _stream(stream)))
+    return out
+
+
+def trace_occluders_counted(bvh: BVH, gbuf: DeviceGBuffer, stats, mode="ao", ao_radius=1.0, light=None, seed=1,
+                            sample=0, out: Occluders | None = None, stream=None) -> Occluders:
+    """trace_occluders that also adds (rays, node visits, box tests, triangle
+    tests) to `stats` (int64 device tensor of 4)."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    out = out or Occluders.empty(gbuf.height, gbuf.width, gbuf.prim.device)
+    g = gbuf.c()
+    o = out.c()
+    lp = ctypes.byref(light_struct(light)) if light is not None else None
+    _check(lib().ocr_trace_occluders_counted(bvh.h, ctypes.byref(g), m, float(ao_radius), lp, int(seed),
+                                             int(sample), ctypes.byref(o), _dptr(stats), _stream(stream)))
     return out
 
 

@@ -232,6 +232,21 @@ ocr_status ocr_trace_occluders(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int3
     return e == hipSuccess ? OCR_OK : hip_fail(e, "trace launch");
 }
 
+ocr_status ocr_trace_occluders_counted(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int32_t mode, float ao_radius,
+                                       const ocr_rect_light *light, uint64_t seed, uint32_t sample,
+                                       ocr_occluders *out, uint64_t *stats, void *stream) {
+    if (!bvh) return fail(OCR_ERR_INVALID_ARG, "bvh is NULL");
+    if (!stats) return fail(OCR_ERR_INVALID_ARG, "stats is NULL");
+    ocr_status st = check_gbuf(gbuf);
+    if (st) return st;
+    if (!out || !out->dz || !out->nz || !out->hit) return fail(OCR_ERR_INVALID_ARG, "occluder records incomplete");
+    LightF L;
+    if ((st = check_effect(mode, ao_radius, light, L))) return st;
+    hipError_t e = launch_trace_count(bvh->dev, view(gbuf), mode, ao_radius, L, fold_seed(seed), sample,
+                                      OccView{out->dz, out->nz, out->hit}, stats, (hipStream_t)stream);
+    return e == hipSuccess ? OCR_OK : hip_fail(e, "counted trace launch");
+}
+
 ocr_status ocr_sample_rays(const ocr_gbuffer *gbuf, int32_t mode, const ocr_rect_light *light, uint64_t seed,
                            uint32_t sample, float *origin, float *dir, uint8_t *kind, void *stream) {
     ocr_status st = check_gbuf(gbuf);

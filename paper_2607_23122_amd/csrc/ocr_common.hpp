@@ -158,6 +158,8 @@ struct OccView {
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_trace(const DeviceBVH &bvh, const GBufView &g, int mode, float R, const LightF &L, uint32_t seed32,
                         uint32_t sample, const OccView &out, hipStream_t st);
+hipError_t launch_trace_count(const DeviceBVH &bvh, const GBufView &g, int mode, float R, const LightF &L,
+                              uint32_t seed32, uint32_t sample, const OccView &out, uint64_t *stats, hipStream_t st);
 hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, int mode, float R,
                            const LightF &L, const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats,
                            hipStream_t st);

@@ -42,6 +42,33 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g
     trace_pixel<MODE>(bvh, g, R, L, sd, sample, out, px, py, stack + threadIdx.x, kBlock);
 }
 
+// The trace with its walk work counted (walks, node visits, box and
+// triangle tests), summed over the wave and added to stats[0..3].  Same
+// records as trace_kernel; used for work accounting, not timed.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void trace_count_kernel(DeviceBVH bvh, GBufView g, float R, LightF L,
+                                                             uint32_t sd, uint32_t sample, OccView out, int tiles_x,
+                                                             int ntiles, uint64_t *stats) {
+    __shared__ uint32_t stack[kStackLds * kBlock];
+    int tx, ty;
+    tile_of_block(tiles_x, ntiles, tx, ty);
+    if (ty * tiles_x + tx >= ntiles) return;
+    int px, py;
+    pixel_of_thread(tx, ty, px, py);
+    WalkStats ws;
+    if (px < g.w && py < g.h)
+        trace_pixel<MODE, true>(bvh, g, R, L, sd, sample, out, px, py, stack + threadIdx.x, kBlock, &ws);
+    uint64_t v[4] = {ws.walks, ws.nodes, ws.box_tests, ws.tri_tests};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) atomicAdd((unsigned long long *)&stats[k], (unsigned long long)v[k]);
+    }
+}
+
 // Candidate lists for the window validation: every pixel whose ray found an
 // occluder.  One list per XCD (blocks are dealt to the XCDs round-robin):
 // the compaction block on XCD x appends its tile's candidates to list x with a
@@ -308,6 +335,20 @@ hipError_t launch_trace(const DeviceBVH &bvh, const GBufView &g, int mode, float
     else
         hipLaunchKernelGGL(trace_kernel<OCR_SHADOW>, grid, block, 0, st, bvh, g, R, L, seed32, sample, out, tiles_x,
                            nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_count(const DeviceBVH &bvh, const GBufView &g, int mode, float R, const LightF &L,
+                              uint32_t seed32, uint32_t sample, const OccView &out, uint64_t *stats, hipStream_t st) {
+    int tiles_x;
+    int nt = ntiles_for(g, tiles_x);
+    dim3 grid(grid_for(nt)), block(kBlock);
+    if (mode == OCR_AO)
+        hipLaunchKernelGGL(trace_count_kernel<OCR_AO>, grid, block, 0, st, bvh, g, R, L, seed32, sample, out, tiles_x,
+                           nt, stats);
+    else
+        hipLaunchKernelGGL(trace_count_kernel<OCR_SHADOW>, grid, block, 0, st, bvh, g, R, L, seed32, sample, out,
+                           tiles_x, nt, stats);
     return hipGetLastError();
 }
 

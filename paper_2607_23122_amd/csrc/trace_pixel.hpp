@@ -13,11 +13,12 @@ __device__ inline void load3(const float *p, int64_t i, float v[3]) {
 }
 
 // Sample pixel (px, py), trace its ray and write its occluder record.
-// `stack` is this lane's LDS stack, `stride` apart between entries.
-template <int MODE>
+// `stack` is this lane's LDS stack, `stride` apart between entries.  With
+// COUNT the walk's work is added to *ws.
+template <int MODE, bool COUNT = false>
 __device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, float R, const LightF &L, uint32_t sd,
                                    uint32_t sample, const OccView &out, int px, int py, uint32_t *stack,
-                                   int stride) {
+                                   int stride, WalkStats *ws = nullptr) {
     int64_t i = (int64_t)py * g.w + px;
     uint32_t prim = g.prim[i];
     if (prim == OCR_HIT_MISS) {
@@ -46,7 +47,7 @@ __device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, floa
     }
     TRay r;
     make_ray(o, d, prim, OCR_HIT_MISS, r);
-    Hit h = traverse<false, MODE == OCR_AO>(bvh, r, tmax, stack, stride);
+    Hit h = traverse<false, MODE == OCR_AO, COUNT>(bvh, r, tmax, stack, stride, ws);
     out.hit[i] = h.tri;
     if (h.tri == OCR_HIT_MISS) return;
     float nz[3];

@@ -85,6 +85,12 @@ __device__ inline float tri_hit(const TRay &r, const float4 &v0, const float4 &v
     return t > 0.0f ? t : -1.0f;
 }
 
+// Work of BVH walks: walks, node visits, box tests and triangle tests (a
+// test of one ray or segment counts once).
+struct WalkStats {
+    uint64_t walks = 0, nodes = 0, box_tests = 0, tri_tests = 0;
+};
+
 // Result of a closest-hit query: `tri` is the scene triangle index or
 // OCR_HIT_MISS, `leaf_tri` its position in the leaf-ordered array.
 struct Hit {
@@ -95,9 +101,12 @@ struct Hit {
 
 // Closest hit over t in (0, tmax] (INCLUSIVE) or (0, tmax); with ANY, the
 // first hit found over (0, tmax) ends the query.  Equal distances resolve
-// to the smaller scene triangle index.
-template <bool ANY, bool INCLUSIVE>
-__device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, uint32_t *lds_stack, int stride) {
+// to the smaller scene triangle index.  With COUNT the walk's work is added
+// to *ws (a separate instantiation; the result is the same).
+template <bool ANY, bool INCLUSIVE, bool COUNT = false>
+__device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, uint32_t *lds_stack, int stride,
+                               WalkStats *ws = nullptr) {
+    if (COUNT) ws->walks += 1;
     Hit h;
     h.t = tmax;
     h.tri = OCR_HIT_MISS;
@@ -108,6 +117,10 @@ __device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, 
     const float grow = 1.0f + 0x1p-20f;
     for (;;) {
         if (!(node & kLeafBit)) {
+            if (COUNT) {
+                ws->nodes += 1;
+                ws->box_tests += 4;
+            }
             const float4 *np = reinterpret_cast<const float4 *>(bvh.nodes + node);
             float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
             uint4 ch = reinterpret_cast<const uint4 *>(np)[6];
@@ -162,6 +175,7 @@ __device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, 
                 float4 v0 = tp[0], v1 = tp[1], v2 = tp[2];
                 uint32_t id = __float_as_uint(v0.w);
                 if (id == r.ign0 || id == r.ign1) continue;
+                if (COUNT) ws->tri_tests += 1;
                 float t = tri_hit(r, v0, v1, v2);
                 if (!(t > 0.0f)) continue;
                 bool take;
@@ -225,10 +239,6 @@ typedef __attribute__((address_space(4))) const uint32_t cuint;
 // (0, tmax)).
 // Work counters of a walk (wave-uniform): node visits, and box / triangle
 // tests performed for active segments (lane-tests).
-struct WalkStats {
-    uint64_t walks = 0, nodes = 0, box_tests = 0, tri_tests = 0;
-};
-
 template <int NR>
 __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[NR], float tmax,
                                          const bool (&want)[NR], bool (&blocked)[NR], uint32_t *wstack,

@@ -275,3 +275,23 @@ def test_error_paths_on_device(ocr, boxes):
         ocr.trace_occluders(boxes.bvh, boxes.dg, "shadow", 1.0, bad)
     info = boxes.bvh.info()
     assert info.ntris == 770 and info.depth >= 1 and info.max_leaf <= 8
+
+
+def test_counted_trace_same_records(ocr, terrain_small):
+    # the work-counting trace writes the same records and counts one walk per traced ray
+    case = terrain_small
+    for mode in ("ao", "shadow"):
+        log(f"[counted trace] {case.name} {mode}")
+        occ = _trace(ocr, case, mode, seed=6)
+        stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+        occ2 = ocr.trace_occluders_counted(case.bvh, case.dg, stats, mode, case.R,
+                                           case.light if mode == "shadow" else None, 6, 0)
+        torch.cuda.synchronize()
+        h1, h2 = occ.hit_u32(), occ2.hit_u32()
+        assert np.array_equal(h1, h2)
+        m = h1 < oracle.SELF
+        assert np.array_equal(to_np(occ.dz)[m].view(np.uint32), to_np(occ2.dz)[m].view(np.uint32))
+        walks, nodes, boxes, tris = [int(v) for v in stats.cpu().tolist()]
+        traced = int((case.gb.valid & (h1 != oracle.SELF)).sum())
+        assert walks == traced
+        assert boxes == 4 * nodes and nodes >= walks and tris > 0
