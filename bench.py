@@ -44,7 +44,10 @@ HBM_PEAK_GBS = 8000.0
 # FP32 VALU rate with packed FP32 disabled, one op per lane per cycle:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T ops/s
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# FP32 operations of one test of one segment, counted from the kernels:
+# FP32 operations of one test of one ray or segment, counted from the kernels
+# (the counted tests are those each ray or segment needs on its own; lanes
+# of a wave that execute a test their segment does not need are not useful
+# work):
 # box: 6 subtractions + 6 multiplies (slabs), 6 min/max (per-axis order),
 # 3 max + 2 min (entry/exit), 1 scale, 1 clamp, 1 compare = 26;
 # watertight triangle: 9 translations, 18 (shear), 9 (edge functions),
@@ -76,7 +79,7 @@ def alu_roofline(stats, ms, kernel):
 
 
 def counted_trace(ocr, torch, bvh, dg, mode, R, light, seed, sample):
-    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    stats = torch.zeros(5, dtype=torch.int64, device="cuda")
     ocr.trace_occluders_counted(bvh, dg, stats, mode, R, light, seed, sample)
     torch.cuda.synchronize()
     return [int(v) for v in stats.cpu().tolist()]
@@ -223,11 +226,11 @@ def run_frame(args):
         ", ".join(f"{k} {v:.3f}" for k, v in per.items()))
 
     # work counted by the validation walk for one sample (outside the timed region)
-    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    stats = torch.zeros(5, dtype=torch.int64, device=dev)
     ocr.trace_occluders(bvh, dg, mode, R, light, cfg["sample_seed"], args.steps - 1, occ)
     ocr.validate_pairs(bvh, dg, occ, mode, R, light, p_u, ws, stats=stats)
     torch.cuda.synchronize()
-    walks, nodes, box_tests, tri_tests = [int(v) for v in stats.cpu().tolist()]
+    walks, nodes, box_tests, tri_tests, segments = [int(v) for v in stats.cpu().tolist()]
     valid_px = int(gb.valid.sum())
     hits = int((occ.hit_u32() < ocr.HIT_SELF).sum())
     # Algorithmic bytes of one reuse launch: the G-buffer (pos, nrm, prim:
@@ -272,7 +275,8 @@ def run_frame(args):
         "occluder_hits": hits,
         "valid_pixels": valid_px,
         "validation": {"walks": walks, "node_visits": nodes, "box_tests": box_tests, "tri_tests": tri_tests,
-                       "segments_per_s": None, "useful_tflops": round(val_tops, 3)},
+                       "segments": segments,
+                       "segments_per_s": round(segments / (per["validate"] * 1e-3), 1), "useful_tflops": round(val_tops, 3)},
         "bvh": {"nodes": info.nnodes, "depth": info.depth, "device_mb": round(info.device_bytes / 2 ** 20, 1),
                 "build_ms": round(info.build_ms, 1)},
         "roofline": roof,
@@ -352,7 +356,7 @@ def run_batched(args):
         f"16 per-view pairs {ms_pv:.3f} (wall {wall_pv:.3f})")
     # trace-phase time of the tuned plan, and the traced work (counted per view)
     plan_trace_ms = info.best_trace_ms
-    work = np.zeros(4, np.int64)
+    work = np.zeros(5, np.int64)
     for v, (si, gb, mode) in enumerate(views):
         work += np.array(counted_trace(ocr, torch, bvhs[si], dgs[v], mode, R, light if mode == "shadow" else None,
                                        seed, 0), np.int64)

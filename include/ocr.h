@@ -166,7 +166,8 @@ ocr_status ocr_trace_occluders(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int3
 
 /* ocr_trace_occluders with the walks' work counted: the same records, and
  * adds the number of rays traced, BVH node visits, box tests (4 per node
- * visit) and triangle tests to stats (device uint64[4], caller-zeroed).  A
+ * visit), triangle tests and again the rays traced to stats (device
+ * uint64[5], caller-zeroed; the layout of ocr_validate_pairs' counts).  A
  * separate, slower kernel for work accounting (roofline figures), not for
  * frames.  Errors as ocr_trace_occluders, and OCR_ERR_INVALID_ARG for a
  * NULL stats. */
@@ -197,9 +198,12 @@ size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params
  * ignoring z_j's triangle and k's own, decides whether z_j is the first hit
  * from x_k.  Writes one bit per pair into workspace (layout internal; size
  * from ocr_workspace_bytes with estimator OCR_UNBIASED).  mode, ao_radius and
- * light as for the trace.  stats: NULL, or device uint64[4] to which the
- * window validation adds its work -- BVH walks, node visits, box tests and
- * triangle tests of active segments (a test of one segment counts once).
+ * light as for the trace.  stats: NULL, or device uint64[5] to which the
+ * window validation adds its useful work -- wave walks, node visits, the
+ * box and triangle tests each segment needs on its own (a segment tests the
+ * children of the nodes whose box it touches, and the triangles of the
+ * leaves it reaches), and the segments traced.  With stats the validation runs a slower
+ * work-accounting instantiation of the walk; the bits are the same.
  * Errors as ocr_reuse_ao. */
 ocr_status ocr_validate_pairs(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ, int32_t mode,
                               float ao_radius, const ocr_rect_light *light, const ocr_reuse_params *params,

@@ -326,7 +326,7 @@ def trace_occluders(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, lig
 def trace_occluders_counted(bvh: BVH, gbuf: DeviceGBuffer, stats, mode="ao", ao_radius=1.0, light=None, seed=1,
                             sample=0, out: Occluders | None = None, stream=None) -> Occluders:
     """trace_occluders that also adds (rays, node visits, box tests, triangle
-    tests) to `stats` (int64 device tensor of 4)."""
+    tests, rays) to `stats` (int64 device tensor of 5)."""
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     out = out or Occluders.empty(gbuf.height, gbuf.width, gbuf.prim.device)
     g = gbuf.c()
@@ -369,8 +369,8 @@ def _workspace(gbuf, params, workspace):
 def validate_pairs(bvh: BVH, gbuf: DeviceGBuffer, occ: Occluders, mode="ao", ao_radius=1.0, light=None,
                    params: ReuseParams | None = None, workspace=None, stream=None, stats=None):
     """First-hit validation bits of the unbiased estimator into `workspace`;
-    `stats` (optional int64 device tensor of 4) accumulates walks, node
-    visits, box tests and triangle tests."""
+    `stats` (optional int64 device tensor of 5) accumulates walks, node
+    visits, useful box and triangle tests, and segments."""
     params = params or reuse_params(estimator="unbiased")
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     ws, nbytes = _workspace(gbuf, params, workspace)

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g
 }
 
 // The trace with its walk work counted (walks, node visits, box and
-// triangle tests), summed over the wave and added to stats[0..3].  Same
+// triangle tests, rays), summed over the wave and added to stats[0..4].  Same
 // records as trace_kernel; used for work accounting, not timed.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void trace_count_kernel(DeviceBVH bvh, GBufView g, float R, LightF L,
@@ -58,14 +58,14 @@ __global__ __launch_bounds__(kBlock) void trace_count_kernel(DeviceBVH bvh, GBuf
     WalkStats ws;
     if (px < g.w && py < g.h)
         trace_pixel<MODE, true>(bvh, g, R, L, sd, sample, out, px, py, stack + threadIdx.x, kBlock, &ws);
-    uint64_t v[4] = {ws.walks, ws.nodes, ws.box_tests, ws.tri_tests};
+    uint64_t v[5] = {ws.walks, ws.nodes, ws.box_tests, ws.tri_tests, ws.walks};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
         for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
     }
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) atomicAdd((unsigned long long *)&stats[k], (unsigned long long)v[k]);
+        for (int k = 0; k < 5; ++k) atomicAdd((unsigned long long *)&stats[k], (unsigned long long)v[k]);
     }
 }
 
@@ -119,12 +119,15 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ
 // z_j (traverse_wave_any).  Bit q of j's words is set when z_j is the first
 // hit from o_k (k == j: always).  Persistent grid striding through the
 // candidate lists (measured faster than giving each XCD a contiguous range).
-template <int MODE, int NR>
+// COUNT: the work-accounting instantiation (lane-masked walk, same bits),
+// which adds the segments' useful work to stats[0..4].
+template <int MODE, bool COUNT>
 __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
                                                                  LightF L, int D, int words, uint32_t *bits,
                                                                  const uint32_t *lists, uint32_t per_xcd,
                                                                  uint64_t *stats) {
-    __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
+    __shared__ uint32_t wnode[kBlock / 64][kStackTotal];
+    __shared__ unsigned long long wmask[kBlock / 64][COUNT ? kStackTotal : 1];
     WalkStats ws;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int side = 2 * D + 1, npairs = side * side;
@@ -150,59 +153,61 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
         offset_point(xj, nj, oj);
         load3(occ.dz, j, dzj);
         load3(occ.nz, j, nzj);
-        for (int base = 0; base < npairs; base += 64 * NR) {
-            TRay r[NR];
-            bool want[NR], self[NR], blocked[NR];
-#pragma unroll
-            for (int sl = 0; sl < NR; ++sl) {
-                const int q = base + 64 * sl + lane;
-                want[sl] = false;
-                self[sl] = false;
-                r[sl].ign0 = r[sl].ign1 = OCR_HIT_MISS;
-                if (q < npairs) {
-                    const int kx = jx + q % side - D, ky = jy + q / side - D;
-                    if (kx >= 0 && kx < g.w && ky >= 0 && ky < g.h) {
-                        const int64_t k = (int64_t)ky * g.w + kx;
-                        const uint32_t primk = g.prim[k];
-                        if (k == j) {
-                            self[sl] = true;
-                        } else if (primk != OCR_HIT_MISS) {
-                            float xk[3], nk[3], ok[3], w[3];
-                            load3(g.pos, k, xk);
-                            load3(g.nrm, k, nk);
-                            offset_point(xk, nk, ok);
-                            rel_vec(oj, ok, dzj, w);
-                            float p;
-                            if (MODE == OCR_AO) {
-                                p = dens_ao(w, nk, nzj, R2);
-                            } else {
-                                RecvShadow rk = recv_shadow(ok, L);
-                                p = dens_shadow(w, nk, rk, nzj, L);
-                            }
-                            if (p > 0.0f) {
-                                make_ray(ok, w, hj, primk, r[sl]);
-                                want[sl] = true;
-                            }
+        for (int base = 0; base < npairs; base += 64) {
+            TRay r;
+            bool want = false, self = false;
+            r.ign0 = r.ign1 = OCR_HIT_MISS;
+            const int q = base + lane;
+            if (q < npairs) {
+                const int kx = jx + q % side - D, ky = jy + q / side - D;
+                if (kx >= 0 && kx < g.w && ky >= 0 && ky < g.h) {
+                    const int64_t k = (int64_t)ky * g.w + kx;
+                    const uint32_t primk = g.prim[k];
+                    if (k == j) {
+                        self = true;
+                    } else if (primk != OCR_HIT_MISS) {
+                        float xk[3], nk[3], ok[3], w[3];
+                        load3(g.pos, k, xk);
+                        load3(g.nrm, k, nk);
+                        offset_point(xk, nk, ok);
+                        rel_vec(oj, ok, dzj, w);
+                        float p;
+                        if (MODE == OCR_AO) {
+                            p = dens_ao(w, nk, nzj, R2);
+                        } else {
+                            RecvShadow rk = recv_shadow(ok, L);
+                            p = dens_shadow(w, nk, rk, nzj, L);
+                        }
+                        if (p > 0.0f) {
+                            make_ray(ok, w, hj, primk, r);
+                            want = true;
                         }
                     }
                 }
             }
-            traverse_wave_any<NR>(bvh, r, 1.0f - 1e-4f, want, blocked, wstack[wave], ws);
-#pragma unroll
-            for (int sl = 0; sl < NR; ++sl) {
-                const bool bit = self[sl] || (want[sl] && !blocked[sl]);
-                const unsigned long long m = __ballot(bit);
-                const int w0 = (base + 64 * sl) >> 5;
-                if (lane == 0 && w0 < words) bits[j * words + w0] = (uint32_t)m;
-                if (lane == 1 && w0 + 1 < words) bits[j * words + w0 + 1] = (uint32_t)(m >> 32);
+            bool blocked;
+            if (COUNT) {
+                blocked = traverse_wave_any_masked(bvh, r, 1.0f - 1e-4f, want, wnode[wave], wmask[wave], ws);
+            } else {
+                TRay rr[1] = {r};
+                const bool wr[1] = {want};
+                bool br[1];
+                traverse_wave_any<1>(bvh, rr, 1.0f - 1e-4f, wr, br, wnode[wave], ws);
+                blocked = br[0];
             }
+            const bool bit = self || (want && !blocked);
+            const unsigned long long m = __ballot(bit);
+            const int w0 = base >> 5;
+            if (lane == 0 && w0 < words) bits[j * words + w0] = (uint32_t)m;
+            if (lane == 1 && w0 + 1 < words) bits[j * words + w0 + 1] = (uint32_t)(m >> 32);
         }
     }
-    if (stats != nullptr && lane == 0) {
+    if (COUNT && lane == 0) {
         atomicAdd((unsigned long long *)&stats[0], (unsigned long long)ws.walks);
         atomicAdd((unsigned long long *)&stats[1], (unsigned long long)ws.nodes);
         atomicAdd((unsigned long long *)&stats[2], (unsigned long long)ws.box_tests);
         atomicAdd((unsigned long long *)&stats[3], (unsigned long long)ws.tri_tests);
+        atomicAdd((unsigned long long *)&stats[4], (unsigned long long)ws.segments);
     }
 }
 
@@ -368,11 +373,16 @@ hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccVie
                            nt);
         // persistent grid: a multiple of 8 blocks (one share per XCD), ~32 per CU
         dim3 grid(8192), block(kBlock);
-#define OCR_VAL(M, N) \
-    hipLaunchKernelGGL((validate_window_kernel<M, N>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, \
+#define OCR_VAL(M, C)                                                                                        \
+    hipLaunchKernelGGL((validate_window_kernel<M, C>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, \
                        lists, per_xcd, stats)
-        if (mode == OCR_AO) OCR_VAL(OCR_AO, 1);
-        else OCR_VAL(OCR_SHADOW, 1);
+        if (mode == OCR_AO) {
+            if (stats) OCR_VAL(OCR_AO, true);
+            else OCR_VAL(OCR_AO, false);
+        } else {
+            if (stats) OCR_VAL(OCR_SHADOW, true);
+            else OCR_VAL(OCR_SHADOW, false);
+        }
 #undef OCR_VAL
     } else {
         int gw, gh;

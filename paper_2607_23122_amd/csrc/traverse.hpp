@@ -88,7 +88,7 @@ __device__ inline float tri_hit(const TRay &r, const float4 &v0, const float4 &v
 // Work of BVH walks: walks, node visits, box tests and triangle tests (a
 // test of one ray or segment counts once).
 struct WalkStats {
-    uint64_t walks = 0, nodes = 0, box_tests = 0, tri_tests = 0;
+    uint64_t walks = 0, nodes = 0, box_tests = 0, tri_tests = 0, segments = 0;
 };
 
 // Result of a closest-hit query: `tri` is the scene triangle index or
@@ -342,6 +342,111 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
         --sp;
         node = __builtin_amdgcn_readfirstlane(wstack[sp]);
     }
+}
+
+// The same walk with lane masks, for work accounting: each stack entry
+// carries the ballot mask of the lanes whose segment touches that child's
+// box, and only those lanes (less any found blocked since) test the
+// subtree, so the counts are the tests each segment needs on its own
+// (useful work), not the tests every unblocked lane of the wave executes.
+// Same results as traverse_wave_any.  On SIMD hardware the masks do not
+// save time (the wave visits the same nodes), so frames use the plain walk.
+// `wnode` / `wmask` are this wave's stack (kStackTotal entries each, LDS).
+__device__ inline bool traverse_wave_any_masked(const DeviceBVH &bvh, const TRay &r, float tmax, bool want, uint32_t *wnode,
+                                         unsigned long long *wmask, WalkStats &st) {
+    unsigned long long mask = __ballot(want);
+    if (mask == 0ull) return false;
+    st.walks += 1;
+    st.segments += (uint64_t)__popcll(mask);
+    const unsigned long long me = 1ull << (threadIdx.x & 63);
+    bool blocked = false;
+    const float grow = 1.0f + 0x1p-20f;
+    int sp = 0;
+    uint32_t node = 0;
+    for (;;) {
+        const bool in = (mask & me) != 0ull && !blocked;
+        const unsigned long long live = __ballot(in);
+        if (live != 0ull) {
+            if (!(node & kLeafBit)) {
+                st.nodes += 1;
+                st.box_tests += 4u * (uint32_t)__popcll(live);
+                // the whole node in one batch of scalar loads, before any test
+                const cfloat *np = (const cfloat *)(bvh.nodes + node);
+                const cuint *cp = (const cuint *)(bvh.nodes + node);
+                float lxs[4], hxs[4], lys[4], hys[4], lzs[4], hzs[4];
+                uint32_t chs[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    lxs[i] = np[i];
+                    hxs[i] = np[4 + i];
+                    lys[i] = np[8 + i];
+                    hys[i] = np[12 + i];
+                    lzs[i] = np[16 + i];
+                    hzs[i] = np[20 + i];
+                    chs[i] = cp[24 + i];
+                }
+                uint32_t next = kEmpty;
+                unsigned long long next_mask = 0ull;
+#pragma unroll
+                for (int i = 3; i >= 0; --i) {
+                    const float t0x = (lxs[i] - r.o[0]) * r.inv[0], t1x = (hxs[i] - r.o[0]) * r.inv[0];
+                    const float t0y = (lys[i] - r.o[1]) * r.inv[1], t1y = (hys[i] - r.o[1]) * r.inv[1];
+                    const float t0z = (lzs[i] - r.o[2]) * r.inv[2], t1z = (hzs[i] - r.o[2]) * r.inv[2];
+                    const float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+                    float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
+                    tfar = fminf(tfar, tmax * grow);
+                    const unsigned long long m = __ballot(in && tnear <= tfar);
+                    const uint32_t ch = chs[i];
+                    if (ch != kEmpty && m != 0ull) {
+                        // children pushed in reverse so that child 0 is visited first
+                        if (next != kEmpty) {
+                            wnode[sp] = next;
+                            wmask[sp] = next_mask;
+                            ++sp;
+                        }
+                        next = ch;
+                        next_mask = m;
+                    }
+                }
+                if (next != kEmpty) {
+                    node = __builtin_amdgcn_readfirstlane(next);
+                    mask = next_mask;
+                    continue;
+                }
+            } else {
+                const uint32_t first = node & 0x07FFFFFFu;
+                const uint32_t count = ((node >> 27) & 0xFu) + 1u;
+                bool test = in;
+                for (uint32_t t3 = 0; t3 < count; ++t3) {
+                    const cfloat *tp = (const cfloat *)(bvh.tris + 3 * (size_t)(first + t3));
+                    float4 v0, v1, v2;
+                    v0.x = tp[0]; v0.y = tp[1]; v0.z = tp[2]; v0.w = tp[3];
+                    v1.x = tp[4]; v1.y = tp[5]; v1.z = tp[6]; v1.w = tp[7];
+                    v2.x = tp[8]; v2.y = tp[9]; v2.z = tp[10]; v2.w = tp[11];
+                    const uint32_t id = __float_as_uint(v0.w);
+                    const bool mine = test && id != r.ign0 && id != r.ign1;
+                    st.tri_tests += (uint32_t)__popcll(__ballot(mine));
+                    if (mine) {
+                        const float t = tri_hit(r, v0, v1, v2);
+                        if (t > 0.0f && t < tmax) {
+                            blocked = true;
+                            test = false;
+                        }
+                    }
+                }
+                // every wanted segment decided: done
+                if (__ballot(want && !blocked) == 0ull) return blocked;
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        node = __builtin_amdgcn_readfirstlane(wnode[sp]);
+        const unsigned long long mm = wmask[sp];
+        // (readfirstlane returns int: widen through uint32_t, not by sign)
+        mask = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(mm >> 32)) << 32) |
+               (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)mm);
+    }
+    return blocked;
 }
 
 }  // namespace ocr

@@ -283,7 +283,7 @@ def test_counted_trace_same_records(ocr, terrain_small):
     for mode in ("ao", "shadow"):
         log(f"[counted trace] {case.name} {mode}")
         occ = _trace(ocr, case, mode, seed=6)
-        stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+        stats = torch.zeros(5, dtype=torch.int64, device="cuda")
         occ2 = ocr.trace_occluders_counted(case.bvh, case.dg, stats, mode, case.R,
                                            case.light if mode == "shadow" else None, 6, 0)
         torch.cuda.synchronize()
@@ -291,7 +291,30 @@ def test_counted_trace_same_records(ocr, terrain_small):
         assert np.array_equal(h1, h2)
         m = h1 < oracle.SELF
         assert np.array_equal(to_np(occ.dz)[m].view(np.uint32), to_np(occ2.dz)[m].view(np.uint32))
-        walks, nodes, boxes, tris = [int(v) for v in stats.cpu().tolist()]
+        walks, nodes, boxes, tris, rays = [int(v) for v in stats.cpu().tolist()]
+        assert rays == walks
         traced = int((case.gb.valid & (h1 != oracle.SELF)).sum())
         assert walks == traced
         assert boxes == 4 * nodes and nodes >= walks and tris > 0
+
+
+def test_counted_validation_same_bits(ocr, terrain_small):
+    # the work-accounting validation (lane-masked walk) decides every pair as the timed one does
+    case = terrain_small
+    for mode in ("ao", "shadow"):
+        log(f"[counted validation] {case.name} {mode}")
+        occ = _trace(ocr, case, mode, seed=8)
+        p = ocr.reuse_params("window", 3, 0, "unbiased")
+        lt = case.light if mode == "shadow" else None
+        ws1 = ocr.validate_pairs(case.bvh, case.dg, occ, mode, case.R, lt, p)
+        stats = torch.zeros(5, dtype=torch.int64, device="cuda")
+        ws2 = ocr.validate_pairs(case.bvh, case.dg, occ, mode, case.R, lt, p, stats=stats)
+        torch.cuda.synchronize()
+        H, W, words = case.gb.height, case.gb.width, 6
+        cand = (occ.hit_u32() < oracle.SELF).ravel()
+        b1 = to_np(ws1)[:H * W * words * 4].view(np.uint32).reshape(H * W, words)[cand]
+        b2 = to_np(ws2)[:H * W * words * 4].view(np.uint32).reshape(H * W, words)[cand]
+        assert np.array_equal(b1, b2)
+        walks, nodes, boxes, tris, segs = [int(v) for v in stats.cpu().tolist()]
+        assert 0 < walks <= segs <= 168 * int(cand.sum())
+        assert 0 < boxes <= 4 * 64 * nodes and tris > 0
