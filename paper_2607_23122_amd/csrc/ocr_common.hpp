@@ -139,6 +139,13 @@ __device__ inline bool shadow_traced(const float n[3], const float o[3], const f
     return front > 0.0f && lit > 0.0f;
 }
 
+// Make this wave's LDS writes visible to its other lanes before they read.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // ---------------------------------------------------------------------------
 // Launch-side helpers
 // ---------------------------------------------------------------------------

@@ -71,13 +71,6 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     return l;
 }
 
-// Make this wave's LDS writes visible to its other lanes before they read.
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // One 16x16 target tile (tx, ty) of the sliding-window estimator; every
 // thread of the block calls it.  `smem` holds win_layout(R, ...).total bytes.
 template <int MODE, bool UNB>

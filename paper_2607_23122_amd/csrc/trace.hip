@@ -111,14 +111,37 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ
 }
 
 // First-hit validation (Eq. occ-first-hit) for the sliding window, one
-// wavefront per candidate j: lane q takes the receiver k = j + (q % side - D,
-// q / side - D), side = 2D + 1, D = 2r; when the density of z_j at k is
-// positive, an any-hit segment o_k -> z_j over t in (0, 1 - 1e-4), ignoring
-// z_j's triangle and k's own, decides Occ(x_k, z_j).  The wave walks the BVH
-// once per 64 receivers along the union of their segments, which all end at
+// wavefront per candidate j.  The receivers k = j + (q % side - D,
+// q / side - D), side = 2D + 1, D = 2r, whose density of z_j is positive
+// are gathered first (lane q of each 64-wide round, then compacted into a
+// list in LDS), and the wave then walks the BVH once per 64 listed
+// receivers: an any-hit segment o_k -> z_j over t in (0, 1 - 1e-4), ignoring
+// z_j's triangle and k's own, decides Occ(x_k, z_j), all segments ending at
 // z_j (traverse_wave_any).  Bit q of j's words is set when z_j is the first
-// hit from o_k (k == j: always).  Persistent grid striding through the
-// candidate lists (measured faster than giving each XCD a contiguous range).
+// hit from o_k (k == j: always).  An oversubscribed grid (8192 blocks)
+// strides through the concatenated candidate lists; the hardware dispatcher
+// then balances the uneven per-candidate work at block granularity.  This
+// was measured faster than giving each XCD a contiguous range, than a
+// resident-sized grid, and than taking candidates from atomic counters.
+constexpr int kMaxPairs = 33 * 33;             // (4r+1)^2 at r = 8
+constexpr int kMaxWords = (kMaxPairs + 31) / 32;
+
+// receiver k of candidate j at pair index q, its offset point and the segment
+// vector w = z_j - o_k; false if k is outside the image or background
+__device__ inline bool pair_receiver(const GBufView &g, int jx, int jy, int side, int D, int q, int64_t &k,
+                                     uint32_t &primk, float ok[3], float nk[3]) {
+    const int kx = jx + q % side - D, ky = jy + q / side - D;
+    if (kx < 0 || kx >= g.w || ky < 0 || ky >= g.h) return false;
+    k = (int64_t)ky * g.w + kx;
+    primk = g.prim[k];
+    if (primk == OCR_HIT_MISS) return false;
+    float xk[3];
+    load3(g.pos, k, xk);
+    load3(g.nrm, k, nk);
+    offset_point(xk, nk, ok);
+    return true;
+}
+
 // COUNT: the work-accounting instantiation (lane-masked walk, same bits),
 // which adds the segments' useful work to stats[0..4].
 template <int MODE, bool COUNT>
@@ -128,8 +151,11 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
                                                                  uint64_t *stats) {
     __shared__ uint32_t wnode[kBlock / 64][kStackTotal];
     __shared__ unsigned long long wmask[kBlock / 64][COUNT ? kStackTotal : 1];
+    __shared__ uint16_t wq[kBlock / 64][kMaxPairs];
+    __shared__ uint32_t wbits[kBlock / 64][kMaxWords];
     WalkStats ws;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
     const int side = 2 * D + 1, npairs = side * side;
     // the 8 lists concatenated (roughly tile order); consecutive candidates go
     // to the waves of one block, which then share the CU's caches
@@ -153,37 +179,47 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
         offset_point(xj, nj, oj);
         load3(occ.dz, j, dzj);
         load3(occ.nz, j, nzj);
+        // (1) the receivers with positive density, compacted in q order
+        for (int w = lane; w < words; w += 64) wbits[wave][w] = 0u;
+        int count = 0;
         for (int base = 0; base < npairs; base += 64) {
-            TRay r;
-            bool want = false, self = false;
-            r.ign0 = r.ign1 = OCR_HIT_MISS;
             const int q = base + lane;
-            if (q < npairs) {
-                const int kx = jx + q % side - D, ky = jy + q / side - D;
-                if (kx >= 0 && kx < g.w && ky >= 0 && ky < g.h) {
-                    const int64_t k = (int64_t)ky * g.w + kx;
-                    const uint32_t primk = g.prim[k];
-                    if (k == j) {
-                        self = true;
-                    } else if (primk != OCR_HIT_MISS) {
-                        float xk[3], nk[3], ok[3], w[3];
-                        load3(g.pos, k, xk);
-                        load3(g.nrm, k, nk);
-                        offset_point(xk, nk, ok);
-                        rel_vec(oj, ok, dzj, w);
-                        float p;
-                        if (MODE == OCR_AO) {
-                            p = dens_ao(w, nk, nzj, R2);
-                        } else {
-                            RecvShadow rk = recv_shadow(ok, L);
-                            p = dens_shadow(w, nk, rk, nzj, L);
-                        }
-                        if (p > 0.0f) {
-                            make_ray(ok, w, hj, primk, r);
-                            want = true;
-                        }
-                    }
+            bool want = false;
+            int64_t k;
+            uint32_t primk;
+            float ok[3], nk[3];
+            if (q < npairs && pair_receiver(g, jx, jy, side, D, q, k, primk, ok, nk) && k != j) {
+                float w[3];
+                rel_vec(oj, ok, dzj, w);
+                float p;
+                if (MODE == OCR_AO) {
+                    p = dens_ao(w, nk, nzj, R2);
+                } else {
+                    RecvShadow rk = recv_shadow(ok, L);
+                    p = dens_shadow(w, nk, rk, nzj, L);
                 }
+                want = p > 0.0f;
+            }
+            const unsigned long long m = __ballot(want);
+            if (want) wq[wave][count + __popcll(m & below)] = (uint16_t)q;
+            count += __popcll(m);
+        }
+        wave_sync();
+        // (2) one walk per 64 listed segments
+        for (int c0 = 0; c0 < count; c0 += 64) {
+            TRay r;
+            r.ign0 = r.ign1 = OCR_HIT_MISS;
+            const int idx = c0 + lane;
+            const bool want = idx < count;
+            int q = 0;
+            if (want) {
+                q = wq[wave][idx];
+                int64_t k;
+                uint32_t primk;
+                float ok[3], nk[3], w[3];
+                pair_receiver(g, jx, jy, side, D, q, k, primk, ok, nk);
+                rel_vec(oj, ok, dzj, w);
+                make_ray(ok, w, hj, primk, r);
             }
             bool blocked;
             if (COUNT) {
@@ -195,12 +231,14 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
                 traverse_wave_any<1>(bvh, rr, 1.0f - 1e-4f, wr, br, wnode[wave], ws);
                 blocked = br[0];
             }
-            const bool bit = self || (want && !blocked);
-            const unsigned long long m = __ballot(bit);
-            const int w0 = base >> 5;
-            if (lane == 0 && w0 < words) bits[j * words + w0] = (uint32_t)m;
-            if (lane == 1 && w0 + 1 < words) bits[j * words + w0 + 1] = (uint32_t)(m >> 32);
+            if (want && !blocked) atomicOr(&wbits[wave][q >> 5], 1u << (q & 31));
         }
+        // (3) z_j is its own first hit; write j's words
+        const int qself = D * side + D;
+        if (lane == 0) atomicOr(&wbits[wave][qself >> 5], 1u << (qself & 31));
+        wave_sync();
+        for (int w = lane; w < words; w += 64) bits[j * words + w] = wbits[wave][w];
+        wave_sync();  // the words are read before the next candidate clears them
     }
     if (COUNT && lane == 0) {
         atomicAdd((unsigned long long *)&stats[0], (unsigned long long)ws.walks);

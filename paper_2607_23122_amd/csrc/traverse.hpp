@@ -3,8 +3,9 @@
 // One lane per ray.  The traversal stack lives in LDS, one column per lane
 // (entry k of lane t at [k * blockDim + t], so lanes at equal depth hit
 // distinct banks), with a private spill area for the rare deep paths.
-// Child boxes are tested with a conservative slab test (far distances
-// widened by a few ulps so no box that the ray touches is skipped), and
+// Child boxes are tested with a conservative slab test (one FMA per plane,
+// offsets and far distances widened so no box that the ray touches is
+// skipped; see TRay), and
 // triangles with the watertight test of Woop, Benthin and Wald (JCGT 2013):
 // the edge functions are 2x2 determinants of sheared vertex coordinates,
 // evaluated without contraction and recomputed in FP64 when one is exactly
@@ -16,9 +17,19 @@
 
 namespace ocr {
 
+// Slab test with one FMA per plane: the distance to the plane x_c = l is
+// l * inv_c + off, with off = -o_c * inv_c moved by eps_c = 2^-21 |o_c inv_c|
+// towards the ray for the near plane of the axis and away from it for the
+// far plane (which plane is near follows the sign of inv_c).  Against
+// (l - o_c) * inv_c the FMA form adds an absolute error of at most about
+// 2^-23 |o_c inv_c| (the rounded product and offset), which eps_c covers;
+// the relative error is covered, as before, by widening the far distance by
+// 1 + 2^-20.  So the test stays conservative: no box the ray enters is
+// skipped, and hits do not depend on it.
 struct TRay {
     float o[3];
     float inv[3];   // 1 / d with zero components replaced by +-1e-20
+    float off_lo[3], off_hi[3];  // plane offsets for the box's low / high planes
     float m0[3], m1[3], m2[3];  // shear rows: x' = m0.(p-o), y' = m1.(p-o), z' = m2.(p-o)
     uint32_t ign0, ign1;
 };
@@ -28,6 +39,12 @@ __device__ inline void make_ray(const float o[3], const float d[3], uint32_t ign
         r.o[c] = o[c];
         float dc = fabsf(d[c]) < 1e-20f ? copysignf(1e-20f, d[c]) : d[c];
         r.inv[c] = 1.0f / dc;
+        const float oi = o[c] * r.inv[c];
+        const float eps = 0x1p-21f * fabsf(oi);
+        // inv > 0: the low plane is near (offset lowered), the high plane far (raised)
+        const float s = r.inv[c] > 0.0f ? eps : -eps;
+        r.off_lo[c] = -oi - s;
+        r.off_hi[c] = -oi + s;
     }
     float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
     int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
@@ -132,9 +149,9 @@ __device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, 
             uint32_t cand[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float t0x = (lxs[i] - r.o[0]) * r.inv[0], t1x = (hxs[i] - r.o[0]) * r.inv[0];
-                float t0y = (lys[i] - r.o[1]) * r.inv[1], t1y = (hys[i] - r.o[1]) * r.inv[1];
-                float t0z = (lzs[i] - r.o[2]) * r.inv[2], t1z = (hzs[i] - r.o[2]) * r.inv[2];
+                float t0x = __fmaf_rn(lxs[i], r.inv[0], r.off_lo[0]), t1x = __fmaf_rn(hxs[i], r.inv[0], r.off_hi[0]);
+                float t0y = __fmaf_rn(lys[i], r.inv[1], r.off_lo[1]), t1y = __fmaf_rn(hys[i], r.inv[1], r.off_hi[1]);
+                float t0z = __fmaf_rn(lzs[i], r.inv[2], r.off_lo[2]), t1z = __fmaf_rn(hzs[i], r.inv[2], r.off_hi[2]);
                 float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
                 float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
                 tfar = fminf(tfar, h.t * grow);
@@ -287,9 +304,12 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
                 for (int q = 0; q < NR; ++q) {
                     if (active[q]) {
                         const TRay &rq = r[q];
-                        float t0x = (lxs[i] - rq.o[0]) * rq.inv[0], t1x = (hxs[i] - rq.o[0]) * rq.inv[0];
-                        float t0y = (lys[i] - rq.o[1]) * rq.inv[1], t1y = (hys[i] - rq.o[1]) * rq.inv[1];
-                        float t0z = (lzs[i] - rq.o[2]) * rq.inv[2], t1z = (hzs[i] - rq.o[2]) * rq.inv[2];
+                        float t0x = __fmaf_rn(lxs[i], rq.inv[0], rq.off_lo[0]);
+                        float t1x = __fmaf_rn(hxs[i], rq.inv[0], rq.off_hi[0]);
+                        float t0y = __fmaf_rn(lys[i], rq.inv[1], rq.off_lo[1]);
+                        float t1y = __fmaf_rn(hys[i], rq.inv[1], rq.off_hi[1]);
+                        float t0z = __fmaf_rn(lzs[i], rq.inv[2], rq.off_lo[2]);
+                        float t1z = __fmaf_rn(hzs[i], rq.inv[2], rq.off_hi[2]);
                         float tnear =
                             fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
                         float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
@@ -389,9 +409,12 @@ __device__ inline bool traverse_wave_any_masked(const DeviceBVH &bvh, const TRay
                 unsigned long long next_mask = 0ull;
 #pragma unroll
                 for (int i = 3; i >= 0; --i) {
-                    const float t0x = (lxs[i] - r.o[0]) * r.inv[0], t1x = (hxs[i] - r.o[0]) * r.inv[0];
-                    const float t0y = (lys[i] - r.o[1]) * r.inv[1], t1y = (hys[i] - r.o[1]) * r.inv[1];
-                    const float t0z = (lzs[i] - r.o[2]) * r.inv[2], t1z = (hzs[i] - r.o[2]) * r.inv[2];
+                    const float t0x = __fmaf_rn(lxs[i], r.inv[0], r.off_lo[0]);
+                    const float t1x = __fmaf_rn(hxs[i], r.inv[0], r.off_hi[0]);
+                    const float t0y = __fmaf_rn(lys[i], r.inv[1], r.off_lo[1]);
+                    const float t1y = __fmaf_rn(hys[i], r.inv[1], r.off_hi[1]);
+                    const float t0z = __fmaf_rn(lzs[i], r.inv[2], r.off_lo[2]);
+                    const float t1z = __fmaf_rn(hzs[i], r.inv[2], r.off_hi[2]);
                     const float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
                     float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
                     tfar = fminf(tfar, tmax * grow);
