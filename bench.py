@@ -67,6 +67,30 @@ SERVED_SCENES = [dict(seed=100 + i, cells=c, spheres=n)
 SERVED_SIZES = [(1280, 720), (1920, 1080), (2560, 1440)]
 
 
+TRACE_TU = ["density.hpp", "ocr_common.hpp", "trace.hip", "trace_pixel.hpp", "traverse.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ao_1080p_hbm_traffic.md")
+
+
+def measured_traffic(kernel):
+    """Calibrated HBM bytes (read + write) per launch of `kernel` from the
+    committed counter summary, or None when the kernel's sources changed
+    since the counters were taken (or no summary covers it)."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        h = hashlib.sha256()
+        for f in TRACE_TU:
+            with open(os.path.join(ROOT, "paper_2607_23122_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        rec = txt.split("source_sha256:")[1].split()[0]
+        table = json.loads(txt.split("traffic_json:")[1].strip().splitlines()[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec != h.hexdigest() or kernel not in table:
+        return None
+    return int(table[kernel]["read_bytes"] + table[kernel]["write_bytes"])
+
+
 def alu_roofline(stats, ms, kernel):
     """Useful FP32 ops of the counted box and triangle tests per launch over
     the launch's average duration, against the VALU peak."""
@@ -243,8 +267,10 @@ def run_frame(args):
     val_tops = (OPS_BOX * box_tests + OPS_TRI * tri_tests) / (per["validate"] * 1e-3) / 1e12
     if dominant == "validate":
         # traversal is VALU-bound: price the useful box and triangle tests
+        kname = f"ocr::validate_window_kernel<{0 if mode == 'ao' else 1}, false>"
+        traffic = measured_traffic(kname) if args.workload == "ao_1080p" else None
         roof = dict(bound="alu", achieved=round(val_tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
-                    frac=round(val_tops / VALU_PEAK_TOPS, 4), traffic=None, kernel="validate_window_kernel")
+                    frac=round(val_tops / VALU_PEAK_TOPS, 4), traffic=traffic, kernel=kname)
     else:
         roof = dict(bound="hbm", achieved=round(reuse_gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(reuse_gbs / HBM_PEAK_GBS, 5), traffic=None, kernel=dominant)
