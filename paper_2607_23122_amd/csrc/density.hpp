@@ -67,11 +67,14 @@ __device__ inline float dens_shadow(const float w[3], const float nk[3], const R
     float front = dot3f(nk, w);
     float nlw = dot3f(L.nl, w);
     float zw = dot3f(nz, w);
-    float s = rk.hk / nlw;
+    // one hardware reciprocal (1 ulp) for s and the ratio; thresholds on s
+    // move by an ulp at most
+    float inl = __builtin_amdgcn_rcpf(nlw);
+    float s = rk.hk * inl;
     float a = __fmaf_rn(s, dot3f(L.uhat, w), rk.ak);
     float b = __fmaf_rn(s, dot3f(L.vhat, w), rk.bk);
     bool ok = front > 0.0f && nlw < 0.0f && zw < 0.0f && s > 1.0f && fabsf(a) <= 0.5f && fabsf(b) <= 0.5f;
-    float p = (s * s) * (zw / nlw);
+    float p = (s * s) * (zw * inl);
     return ok ? p : 0.0f;
 }
 

@@ -139,6 +139,14 @@ __device__ inline bool shadow_traced(const float n[3], const float o[3], const f
     return front > 0.0f && lit > 0.0f;
 }
 
+// q / d for 0 <= q < 2^22 and d >= 1 with one FP32 multiply by inv_d =
+// 1.0f / d (correctly rounded): (q + 1/2) / d lies at least 1/(2d) from an
+// integer and the FP32 product is within (q + 1/2) 2^-23 / d of it, so the
+// truncation is the exact quotient (checked exhaustively for q < 2^16,
+// d <= 1024).  Integer division by a runtime value is a long instruction
+// sequence on this hardware.
+__device__ inline int small_div(int q, float inv_d) { return (int)(((float)q + 0.5f) * inv_d); }
+
 // Make this wave's LDS writes visible to its other lanes before they read.
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
             P += s_p[kt][m];
         }
         const float pij = s_p[tid][m];
-        if (pij > 0.0f && P > 0.0f) B += pij / P;
+        if (pij > 0.0f && P > 0.0f) B += pij * __builtin_amdgcn_rcpf(P);
     }
     float F = 1.0f;
     bool dark = false;

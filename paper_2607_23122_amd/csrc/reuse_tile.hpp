@@ -79,6 +79,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                                          int dark_guard, int accumulate, float *out, int tx, int ty) {
     const WinLayout lay = win_layout(R, MODE, UNB, words);
     const int T = kWT, RW = lay.RW, CELLS = lay.cells, D = 2 * R, SIDE = lay.side, TW = 2 * R + 1;
+    const float inv_rw = 1.0f / (float)RW, inv_side = 1.0f / (float)SIDE, inv_tw = 1.0f / (float)TW;
     unsigned long long *s_B = reinterpret_cast<unsigned long long *>(smem + lay.B_off);
     float *s_o = reinterpret_cast<float *>(smem + lay.o_off);    // [3][cells]
     float *s_n = reinterpret_cast<float *>(smem + lay.n_off);    // [3][cells]
@@ -100,7 +101,8 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
     // Stage receivers (o, n, shadow terms), validity, misses, validation
     // bits, and compact the cells whose ray found an occluder.
     for (int c = tid; c < CELLS; c += kRBlock) {
-        int gx = x0 + c % RW, gy = y0 + c / RW;
+        const int cyy = small_div(c, inv_rw);
+        int gx = x0 + (c - cyy * RW), gy = y0 + cyy;
         bool inside = gx >= 0 && gx < g.w && gy >= 0 && gy < g.h;
         int64_t gi = inside ? (int64_t)gy * g.w + gx : 0;
         bool valid = inside && g.prim[gi] != OCR_HIT_MISS;
@@ -134,7 +136,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
     const int ncand = *s_count;
     for (int li = wave; li < ncand; li += kRBlock / 64) {
         const int c = __builtin_amdgcn_readfirstlane((int)s_list[li]);
-        const int cx = c % RW, cy = c / RW;
+        const int cy = small_div(c, inv_rw), cx = c - cy * RW;
         const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
         float oj[3] = {s_o[c], s_o[CELLS + c], s_o[2 * CELLS + c]};
         float dzj[3], nzj[3];
@@ -142,7 +144,8 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         ld3(occ.nz, gj, nzj);
         // (1) densities p_k(j), k - j in [-2R, 2R]^2 (0 outside the staged region)
         for (int q = lane; q < lay.dens; q += 64) {
-            const int dy = q / SIDE - D, dx = q % SIDE - D;
+            const int qy = small_div(q, inv_side);
+            const int dy = qy - D, dx = (q - qy * SIDE) - D;
             const int kx = cx + dx, ky = cy + dy;
             float p = 0.0f;
             if ((unsigned)kx < (unsigned)RW && (unsigned)ky < (unsigned)RW) {
@@ -168,7 +171,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         wave_sync();
         // (2) row box sums H[row][t2] = sum_{e < 2R+1} p(row, t2 + e)
         for (int q = lane; q < lay.hsum; q += 64) {
-            const int row = q / TW, t2 = q % TW;
+            const int row = small_div(q, inv_tw), t2 = q - row * TW;
             const float *pr = w_dens + row * SIDE + t2;
             float h = 0.0f;
             for (int e = 0; e < TW; ++e) h += pr[e];
@@ -177,14 +180,15 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         wave_sync();
         // (3) target i = j + (t2 - R, r2 - R): P_i(j) is the column box sum of H
         for (int q = lane; q < TW * TW; q += 64) {
-            const int r2 = q / TW, t2 = q % TW;
+            const int r2 = small_div(q, inv_tw), t2 = q - r2 * TW;
             const int ix = cx + t2 - 2 * R, iy = cy + r2 - 2 * R;  // tile coordinates of i
             if ((unsigned)ix < (unsigned)T && (unsigned)iy < (unsigned)T) {
                 float P = 0.0f;
                 for (int e = 0; e < TW; ++e) P += w_h[(r2 + e) * TW + t2];
                 const float pij = w_dens[(r2 + R) * SIDE + (t2 + R)];
                 if (pij > 0.0f && P > 0.0f)
-                    atomicAdd(&s_B[iy * T + ix], (unsigned long long)rintf((pij / P) * 4294967296.0f));
+                    atomicAdd(&s_B[iy * T + ix],
+                              (unsigned long long)rintf((pij * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
             }
         }
         wave_sync();

@@ -128,9 +128,10 @@ constexpr int kMaxWords = (kMaxPairs + 31) / 32;
 
 // receiver k of candidate j at pair index q, its offset point and the segment
 // vector w = z_j - o_k; false if k is outside the image or background
-__device__ inline bool pair_receiver(const GBufView &g, int jx, int jy, int side, int D, int q, int64_t &k,
-                                     uint32_t &primk, float ok[3], float nk[3]) {
-    const int kx = jx + q % side - D, ky = jy + q / side - D;
+__device__ inline bool pair_receiver(const GBufView &g, int jx, int jy, int side, float inv_side, int D, int q,
+                                     int64_t &k, uint32_t &primk, float ok[3], float nk[3]) {
+    const int qy = small_div(q, inv_side);
+    const int kx = jx + (q - qy * side) - D, ky = jy + qy - D;
     if (kx < 0 || kx >= g.w || ky < 0 || ky >= g.h) return false;
     k = (int64_t)ky * g.w + kx;
     primk = g.prim[k];
@@ -157,6 +158,7 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int side = 2 * D + 1, npairs = side * side;
+    const float inv_side = 1.0f / (float)side;
     // the 8 lists concatenated (roughly tile order); consecutive candidates go
     // to the waves of one block, which then share the CU's caches
     uint32_t start[9];
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
         for (int q = 1; q < 8; ++q) x += li >= start[q] ? 1 : 0;
         const int64_t j = __builtin_amdgcn_readfirstlane(
             (int)lists[8 * kCountStride + (uint32_t)x * per_xcd + (li - start[x])]);
-        const int jx = (int)(j % g.w), jy = (int)(j / g.w);
+        const int jy = (int)((uint32_t)j / (uint32_t)g.w), jx = (int)j - jy * g.w;
         const uint32_t hj = occ.hit[j];
         float xj[3], nj[3], oj[3], dzj[3], nzj[3];
         load3(g.pos, j, xj);
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
             int64_t k;
             uint32_t primk;
             float ok[3], nk[3];
-            if (q < npairs && pair_receiver(g, jx, jy, side, D, q, k, primk, ok, nk) && k != j) {
+            if (q < npairs && pair_receiver(g, jx, jy, side, inv_side, D, q, k, primk, ok, nk) && k != j) {
                 float w[3];
                 rel_vec(oj, ok, dzj, w);
                 float p;
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void validate_window_kernel(DeviceBVH bvh, 
                 int64_t k;
                 uint32_t primk;
                 float ok[3], nk[3], w[3];
-                pair_receiver(g, jx, jy, side, D, q, k, primk, ok, nk);
+                pair_receiver(g, jx, jy, side, inv_side, D, q, k, primk, ok, nk);
                 rel_vec(oj, ok, dzj, w);
                 make_ray(ok, w, hj, primk, r);
             }
