@@ -165,8 +165,9 @@ ocr_status ocr_trace_occluders(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int3
                                ocr_occluders *out, void *stream);
 
 /* ocr_trace_occluders with the walks' work counted: the same records, and
- * adds the number of rays traced, BVH node visits, box tests (4 per node
- * visit), triangle tests and again the rays traced to stats (device
+ * adds the number of rays traced, BVH node visits, box tests (one per
+ * non-empty child of a visited node), triangle tests and again the rays
+ * traced to stats (device
  * uint64[5], caller-zeroed; the layout of ocr_validate_pairs' counts).  A
  * separate, slower kernel for work accounting (roofline figures), not for
  * frames.  Errors as ocr_trace_occluders, and OCR_ERR_INVALID_ARG for a

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kBBlock) void batch_trace_kernel(const BatchView *_
     }
 }
 
-// One block per reuse item (a 16x16 target tile of a window or no-reuse view).
+// One block per reuse item (a window target tile of a window or no-reuse view).
 __global__ __launch_bounds__(kRBlock) void batch_reuse_kernel(const BatchView *__restrict__ views,
                                                               const uint32_t *__restrict__ r_first, int nviews,
                                                               const uint32_t *__restrict__ q_start, uint32_t *ctr) {
@@ -146,12 +146,15 @@ __global__ __launch_bounds__(kRBlock) void batch_reuse_kernel(const BatchView *_
         const uint32_t t = item - r_first[v];
         const int tx = (int)(t % (uint32_t)V.r_tiles_x), ty = (int)(t / (uint32_t)V.r_tiles_x);
         if (V.estimator == OCR_NOREUSE) {
-            const int px = tx * kWT + (threadIdx.x & 15), py = ty * kWT + (threadIdx.x >> 4);
-            if (px < V.g.w && py < V.g.h) {
-                const int64_t gi = (int64_t)py * V.g.w + px;
-                const bool valid = V.g.prim[gi] != OCR_HIT_MISS;
-                const bool miss = V.occ.hit[gi] == OCR_HIT_MISS;
-                V.out[gi] = V.mode == OCR_AO ? ((!valid || miss) ? 1.0f : 0.0f) : ((valid && miss) ? 1.0f : 0.0f);
+            for (int t = threadIdx.x; t < kWTX * kWTY; t += kRBlock) {
+                const int px = tx * kWTX + t % kWTX, py = ty * kWTY + t / kWTX;
+                if (px < V.g.w && py < V.g.h) {
+                    const int64_t gi = (int64_t)py * V.g.w + px;
+                    const bool valid = V.g.prim[gi] != OCR_HIT_MISS;
+                    const bool miss = V.occ.hit[gi] == OCR_HIT_MISS;
+                    V.out[gi] =
+                        V.mode == OCR_AO ? ((!valid || miss) ? 1.0f : 0.0f) : ((valid && miss) ? 1.0f : 0.0f);
+                }
             }
             continue;
         }

@@ -20,7 +20,7 @@ struct BatchView {
     int32_t radius;     // window radius
     int32_t dark_guard; // already restricted to the biased estimator
     int32_t words;      // validation words per pixel
-    int32_t r_tiles_x;  // 16x16 reuse tiles per row
+    int32_t r_tiles_x;  // reuse tiles (kWTX x kWTY) per row
     const uint32_t *bits;
     float *out;
 };

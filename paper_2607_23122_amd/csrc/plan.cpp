@@ -236,7 +236,7 @@ ocr_status ocr_plan_create(const ocr_view_desc *views, int32_t nviews, const ocr
         B.radius = d.params.radius;
         B.dark_guard = (d.params.estimator == OCR_BIASED && d.params.dark_guard) ? 1 : 0;
         B.words = pair_words(d.params);
-        B.r_tiles_x = (d.gbuf.width + 15) / 16;
+        B.r_tiles_x = (d.gbuf.width + kWTX - 1) / kWTX;
         B.out = d.out;
         wsb[v] = ocr_workspace_bytes(d.gbuf.width, d.gbuf.height, &d.params);
         pixels += (int64_t)d.gbuf.width * d.gbuf.height;
@@ -250,7 +250,7 @@ ocr_status ocr_plan_create(const ocr_view_desc *views, int32_t nviews, const ocr
     p->tun = tuning ? *tuning : ocr_plan_tuning{16, 16, OCR_PACK_BLOCK8, 1};
     if (!tuning) p->tun.use_graph = 1;
 
-    // reuse work: 16x16 tiles of window and no-reuse views; fixed groups go per view
+    // reuse work: window tiles of window and no-reuse views; fixed groups go per view
     std::vector<uint32_t> rfirst(nviews + 1, 0u);
     uint64_t racc = 0;
     for (int v = 0; v < nviews; ++v) {
@@ -258,7 +258,7 @@ ocr_status ocr_plan_create(const ocr_view_desc *views, int32_t nviews, const ocr
         rfirst[v] = (uint32_t)racc;
         const bool grp = d.params.estimator != OCR_NOREUSE && d.params.pattern == OCR_GROUP;
         if (grp) p->grp_views.push_back(v);
-        else racc += (uint64_t)((d.gbuf.width + 15) / 16) * (uint64_t)((d.gbuf.height + 15) / 16);
+        else racc += (uint64_t)((d.gbuf.width + kWTX - 1) / kWTX) * (uint64_t)((d.gbuf.height + kWTY - 1) / kWTY);
         if (d.params.estimator == OCR_UNBIASED) p->unb_views.push_back(v);
         if (!grp && d.params.estimator != OCR_NOREUSE)
             p->reuse_lds = std::max(p->reuse_lds, batch_reuse_lds(d.params.radius, d.mode,

@@ -165,7 +165,7 @@ __global__ void scale_kernel(float *out, int64_t n, float s) {
 template <int MODE, bool UNB>
 static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, const LightF &L, const uint32_t *bits,
                              int words, const ocr_reuse_params &p, float *out, hipStream_t st) {
-    int tiles_x = (g.w + kWT - 1) / kWT, tiles_y = (g.h + kWT - 1) / kWT;
+    int tiles_x = (g.w + kWTX - 1) / kWTX, tiles_y = (g.h + kWTY - 1) / kWTY;
     int nt = tiles_x * tiles_y;
     WinLayout lay = win_layout(p.radius, MODE, UNB, words);
     // dynamic-LDS limit raised so far (64 KB by default); several host

@@ -23,7 +23,6 @@
 namespace ocr {
 
 constexpr int kRBlock = 256;
-constexpr int kWT = 16;  // window tile side
 
 __device__ inline void ld3(const float *p, int64_t i, float v[3]) {
     v[0] = p[3 * i];
@@ -40,7 +39,7 @@ __device__ inline float finish(int mode, bool valid, float B, float F, bool dark
 
 // LDS layout of the window kernel for radius R (dynamic shared memory).
 struct WinLayout {
-    int RW, cells, side, dens, hsum, words;
+    int RWX, RWY, cells, side, dens, hsum, words;
     size_t o_off, n_off, sh_off, valid_off, miss_off, list_off, B_off, wave_off, total;
 };
 
@@ -52,14 +51,15 @@ __host__ __device__ inline size_t lds_take(size_t &off, size_t bytes) {
 
 __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int words) {
     WinLayout l;
-    l.RW = kWT + 2 * R;
-    l.cells = l.RW * l.RW;
+    l.RWX = kWTX + 2 * R;
+    l.RWY = kWTY + 2 * R;
+    l.cells = l.RWX * l.RWY;
     l.side = 4 * R + 1;
     l.dens = l.side * l.side;
     l.hsum = l.side * (2 * R + 1);
     l.words = words;
     size_t off = 0;
-    l.B_off = lds_take(off, sizeof(unsigned long long) * kWT * kWT);
+    l.B_off = lds_take(off, sizeof(unsigned long long) * kWTX * kWTY);
     l.o_off = lds_take(off, sizeof(float) * 3 * l.cells);
     l.n_off = lds_take(off, sizeof(float) * 3 * l.cells);
     l.sh_off = lds_take(off, mode == OCR_SHADOW ? sizeof(float) * 3 * l.cells : 0);
@@ -71,14 +71,15 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     return l;
 }
 
-// One 16x16 target tile (tx, ty) of the sliding-window estimator; every
+// One kWTX x kWTY target tile (tx, ty) of the sliding-window estimator; every
 // thread of the block calls it.  `smem` holds win_layout(R, ...).total bytes.
 template <int MODE, bool UNB>
 __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g, const OccView &occ, float R2,
                                          const LightF &L, const uint32_t *__restrict__ bits, int words, int R,
                                          int dark_guard, int accumulate, float *out, int tx, int ty) {
     const WinLayout lay = win_layout(R, MODE, UNB, words);
-    const int T = kWT, RW = lay.RW, CELLS = lay.cells, D = 2 * R, SIDE = lay.side, TW = 2 * R + 1;
+    const int TX = kWTX, TY = kWTY, RW = lay.RWX, RWY = lay.RWY, CELLS = lay.cells, D = 2 * R, SIDE = lay.side,
+              TW = 2 * R + 1;
     const float inv_rw = 1.0f / (float)RW, inv_side = 1.0f / (float)SIDE, inv_tw = 1.0f / (float)TW;
     unsigned long long *s_B = reinterpret_cast<unsigned long long *>(smem + lay.B_off);
     float *s_o = reinterpret_cast<float *>(smem + lay.o_off);    // [3][cells]
@@ -92,10 +93,10 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
     float *w_dens = reinterpret_cast<float *>(smem + lay.wave_off) + wave * (lay.dens + lay.hsum);
     float *w_h = w_dens + lay.dens;
 
-    const int x0 = tx * T - R, y0 = ty * T - R;
+    const int x0 = tx * TX - R, y0 = ty * TY - R;
     const int tid = threadIdx.x;
     if (tid == 0) *s_count = 0;
-    for (int t = tid; t < T * T; t += kRBlock) s_B[t] = 0ull;
+    for (int t = tid; t < TX * TY; t += kRBlock) s_B[t] = 0ull;
     __syncthreads();
 
     // Stage receivers (o, n, shadow terms), validity, misses, validation
@@ -148,7 +149,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
             const int dy = qy - D, dx = (q - qy * SIDE) - D;
             const int kx = cx + dx, ky = cy + dy;
             float p = 0.0f;
-            if ((unsigned)kx < (unsigned)RW && (unsigned)ky < (unsigned)RW) {
+            if ((unsigned)kx < (unsigned)RW && (unsigned)ky < (unsigned)RWY) {
                 const int kc = ky * RW + kx;
                 float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
                 float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
@@ -182,12 +183,12 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         for (int q = lane; q < TW * TW; q += 64) {
             const int r2 = small_div(q, inv_tw), t2 = q - r2 * TW;
             const int ix = cx + t2 - 2 * R, iy = cy + r2 - 2 * R;  // tile coordinates of i
-            if ((unsigned)ix < (unsigned)T && (unsigned)iy < (unsigned)T) {
+            if ((unsigned)ix < (unsigned)TX && (unsigned)iy < (unsigned)TY) {
                 float P = 0.0f;
                 for (int e = 0; e < TW; ++e) P += w_h[(r2 + e) * TW + t2];
                 const float pij = w_dens[(r2 + R) * SIDE + (t2 + R)];
                 if (pij > 0.0f && P > 0.0f)
-                    atomicAdd(&s_B[iy * T + ix],
+                    atomicAdd(&s_B[iy * TX + ix],
                               (unsigned long long)rintf((pij * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
             }
         }
@@ -196,9 +197,9 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
     __syncthreads();
 
     // one lane per target
-    for (int t = tid; t < T * T; t += kRBlock) {
-        const int ix = t % T, iy = t / T;
-        const int px = tx * T + ix, py = ty * T + iy;
+    for (int t = tid; t < TX * TY; t += kRBlock) {
+        const int ix = t % TX, iy = t / TX;
+        const int px = tx * TX + ix, py = ty * TY + iy;
         if (px >= g.w || py >= g.h) continue;
         const int c = (iy + R) * RW + (ix + R);
         const bool valid = s_valid[c];

@@ -134,13 +134,14 @@ __device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, 
     const float grow = 1.0f + 0x1p-20f;
     for (;;) {
         if (!(node & kLeafBit)) {
-            if (COUNT) {
-                ws->nodes += 1;
-                ws->box_tests += 4;
-            }
             const float4 *np = reinterpret_cast<const float4 *>(bvh.nodes + node);
             float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
             uint4 ch = reinterpret_cast<const uint4 *>(np)[6];
+            if (COUNT) {
+                // a useful box test per non-empty child
+                ws->nodes += 1;
+                ws->box_tests += (ch.x != kEmpty) + (ch.y != kEmpty) + (ch.z != kEmpty) + (ch.w != kEmpty);
+            }
             float lxs[4] = {lx.x, lx.y, lx.z, lx.w}, hxs[4] = {hx.x, hx.y, hx.z, hx.w};
             float lys[4] = {ly.x, ly.y, ly.z, ly.w}, hys[4] = {hy.x, hy.y, hy.z, hy.w};
             float lzs[4] = {lz.x, lz.y, lz.z, lz.w}, hzs[4] = {hz.x, hz.y, hz.z, hz.w};
@@ -299,6 +300,7 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
             uint32_t next = kEmpty;
 #pragma unroll
             for (int i = 3; i >= 0; --i) {
+                if (chs[i] == kEmpty) continue;  // wave-uniform: skip the slot's tests
                 bool hit = false;
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
@@ -389,7 +391,6 @@ __device__ inline bool traverse_wave_any_masked(const DeviceBVH &bvh, const TRay
         if (live != 0ull) {
             if (!(node & kLeafBit)) {
                 st.nodes += 1;
-                st.box_tests += 4u * (uint32_t)__popcll(live);
                 // the whole node in one batch of scalar loads, before any test
                 const cfloat *np = (const cfloat *)(bvh.nodes + node);
                 const cuint *cp = (const cuint *)(bvh.nodes + node);
@@ -409,6 +410,8 @@ __device__ inline bool traverse_wave_any_masked(const DeviceBVH &bvh, const TRay
                 unsigned long long next_mask = 0ull;
 #pragma unroll
                 for (int i = 3; i >= 0; --i) {
+                    if (chs[i] == kEmpty) continue;  // wave-uniform: skip the slot's tests
+                    st.box_tests += (uint32_t)__popcll(live);
                     const float t0x = __fmaf_rn(lxs[i], r.inv[0], r.off_lo[0]);
                     const float t1x = __fmaf_rn(hxs[i], r.inv[0], r.off_hi[0]);
                     const float t0y = __fmaf_rn(lys[i], r.inv[1], r.off_lo[1]);
