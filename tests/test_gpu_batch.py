@@ -239,3 +239,18 @@ def test_batched_workload_full_size(ocr):
                                                                            rec, p))
             log(f"    view {v} tile {t}: {st}")
     plan.free()
+
+
+def test_plan_without_window_views(ocr, mixed):
+    # only fixed-group and no-reuse views: no batched window reuse launch (group views go per view)
+    _, bvhs, views = mixed
+    sub = [v for v in views if v.opattern == "group" or v.oest == "none"]
+    assert len(sub) >= 3
+    for use_graph in (0, 1):
+        log(f"[plan] group / no-reuse views only, graph={use_graph}")
+        descs, outs = _descs(ocr, bvhs, sub)
+        plan = ocr.Plan(descs, ocr.plan_tuning((8, 8), "row", use_graph))
+        plan.launch()
+        plan.launch()
+        _check_plan(ocr, plan, sub, outs, f"group-only graph={use_graph}")
+        plan.free()
