@@ -53,6 +53,20 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # watertight triangle: 9 translations, 18 (shear), 9 (edge functions),
 # 6 (sign tests), 2 (determinant), 9 (depths), 3 (T), 1 division, 2 compares = 59
 OPS_BOX, OPS_TRI = 26, 59
+# FP32 operations of one pair density, counted from the kernels: the pair
+# vector w = (o_j - o_k) + dz_j (6), then AO: three dot products (9), three
+# support compares, |w|^4 (1), a reciprocal and two products, a select = 17;
+# shadow: five dot products (15), a reciprocal, s, two FMAs (a, b), six
+# support compares and two abs, s^2 and the Jacobian ratio (3), a select = 31.
+OPS_DENS = {"ao": 6 + 17, "shadow": 6 + 31}
+
+
+def window_reuse_ops(r, mode):
+    """Useful FP32 ops per hit candidate of a window-r reuse launch: the
+    (4r+1)^2 pair densities, the (4r+1)(2r+1) row box sums and (2r+1)^2
+    column box sums of 2r adds each, and a reciprocal and product per target."""
+    side, tw = 4 * r + 1, 2 * r + 1
+    return side * side * OPS_DENS[mode] + side * tw * 2 * r + tw * tw * 2 * r + tw * tw * 2
 
 WORKLOADS = {
     "ao_1080p": dict(mode="ao", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2, sample_seed=1),
@@ -264,9 +278,13 @@ def run_frame(args):
     # pair densities a window launch evaluates: (4r+1)^2 per candidate
     pair_evals = hits * (4 * r + 1) ** 2
     dominant = max(names, key=lambda n: per[n])
-    val_tops = (OPS_BOX * box_tests + OPS_TRI * tri_tests) / (per["validate"] * 1e-3) / 1e12
+    # validation: the useful box and triangle tests of the segments plus the
+    # pair densities deciding which pairs get a segment ((4r+1)^2 - 1 per candidate)
+    val_ops = OPS_BOX * box_tests + OPS_TRI * tri_tests + hits * ((4 * r + 1) ** 2 - 1) * OPS_DENS[mode]
+    val_tops = val_ops / (per["validate"] * 1e-3) / 1e12
+    reuse_tops = hits * window_reuse_ops(r, mode) / (per["reuse_biased"] * 1e-3) / 1e12
     if dominant == "validate":
-        # traversal is VALU-bound: price the useful box and triangle tests
+        # traversal and densities are VALU-bound: price the useful operations
         kname = f"ocr::validate_window_kernel<{0 if mode == 'ao' else 1}, false>"
         traffic = measured_traffic(kname) if args.workload == "ao_1080p" else None
         roof = dict(bound="alu", achieved=round(val_tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
@@ -297,6 +315,11 @@ def run_frame(args):
         "reused_samples_per_s": round(hits * (2 * r + 1) ** 2 / (per["reuse_biased"] * 1e-3), 1),
         "pair_densities_per_s": round(pair_evals / (per["reuse_biased"] * 1e-3), 1),
         "biased_frame_ms": round(per["trace"] + per["reuse_biased"], 4),
+        "reuse_roofline": dict(bound="alu", achieved=round(reuse_tops, 3), peak=round(VALU_PEAK_TOPS, 1),
+                               unit="TFLOP/s", frac=round(reuse_tops / VALU_PEAK_TOPS, 4),
+                               hbm_gbs=round(reuse_gbs, 1), hbm_frac=round(reuse_gbs / HBM_PEAK_GBS, 4),
+                               kernel=f"ocr::reuse_window_kernel<{0 if mode == 'ao' else 1}, false>",
+                               ops_per_candidate=window_reuse_ops(r, mode)),
         "rays_per_step": rays,
         "occluder_hits": hits,
         "valid_pixels": valid_px,

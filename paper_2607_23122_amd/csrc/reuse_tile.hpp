@@ -78,9 +78,8 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                                          const LightF &L, const uint32_t *__restrict__ bits, int words, int R,
                                          int dark_guard, int accumulate, float *out, int tx, int ty) {
     const WinLayout lay = win_layout(R, MODE, UNB, words);
-    const int TX = kWTX, TY = kWTY, RW = lay.RWX, RWY = lay.RWY, CELLS = lay.cells, D = 2 * R, SIDE = lay.side,
-              TW = 2 * R + 1;
-    const float inv_rw = 1.0f / (float)RW, inv_side = 1.0f / (float)SIDE, inv_tw = 1.0f / (float)TW;
+    const int TX = kWTX, TY = kWTY, RW = lay.RWX, CELLS = lay.cells, D = 2 * R, SIDE = lay.side, TW = 2 * R + 1;
+    const float inv_rw = 1.0f / (float)RW;
     unsigned long long *s_B = reinterpret_cast<unsigned long long *>(smem + lay.B_off);
     float *s_o = reinterpret_cast<float *>(smem + lay.o_off);    // [3][cells]
     float *s_n = reinterpret_cast<float *>(smem + lay.n_off);    // [3][cells]
@@ -143,54 +142,60 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         float dzj[3], nzj[3];
         ld3(occ.dz, gj, dzj);
         ld3(occ.nz, gj, nzj);
-        // (1) densities p_k(j), k - j in [-2R, 2R]^2 (0 outside the staged region)
-        for (int q = lane; q < lay.dens; q += 64) {
-            const int qy = small_div(q, inv_side);
-            const int dy = qy - D, dx = (q - qy * SIDE) - D;
-            const int kx = cx + dx, ky = cy + dy;
-            float p = 0.0f;
-            if ((unsigned)kx < (unsigned)RW && (unsigned)ky < (unsigned)RWY) {
-                const int kc = ky * RW + kx;
-                float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
-                float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
-                float w[3];
-                rel_vec(oj, ok, dzj, w);
-                if (MODE == OCR_AO) {
-                    p = dens_ao(w, nk, nzj, R2);
-                } else {
-                    RecvShadow rk = {s_sh[kc], s_sh[CELLS + kc], s_sh[2 * CELLS + kc]};
-                    p = dens_shadow(w, nk, rk, nzj, L);
-                }
-                if (UNB && p > 0.0f) {
-                    // candidate j's validation bit for the receiver at offset k - j = (dx, dy): bit q
-                    const uint32_t wv = bits[gj * words + (q >> 5)];
-                    if (!((wv >> (q & 31)) & 1u)) p = 0.0f;
-                }
+        // The targets of this tile that j reaches are the cells [tx0, tx1] x
+        // [ty0, ty1] (staged coordinates; the tile is [R, R + TX) x [R, R + TY));
+        // they need the receivers [tx0 - R, tx1 + R] x [ty0 - R, ty1 + R], a
+        // WD x HD rectangle inside the staged region (13 x 13 at R = 3 for a
+        // candidate whose targets are all in the tile, less in the halo).
+        const int tx0 = max(cx - R, R), tx1 = min(cx + R, R + TX - 1);
+        const int ty0 = max(cy - R, R), ty1 = min(cy + R, R + TY - 1);
+        const int ntx = tx1 - tx0 + 1, nty = ty1 - ty0 + 1;
+        const int WD = ntx + 2 * R, HD = nty + 2 * R;
+        const int kx0 = tx0 - R, ky0 = ty0 - R;
+        const float inv_wd = 1.0f / (float)WD, inv_ntx = 1.0f / (float)ntx;
+        // (1) densities p_k(j) over the rectangle, row stride SIDE
+        for (int q = lane; q < WD * HD; q += 64) {
+            const int qy = small_div(q, inv_wd), qx = q - qy * WD;
+            const int kx = kx0 + qx, ky = ky0 + qy;
+            const int kc = ky * RW + kx;
+            float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
+            float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
+            float w[3];
+            rel_vec(oj, ok, dzj, w);
+            float p;
+            if (MODE == OCR_AO) {
+                p = dens_ao(w, nk, nzj, R2);
+            } else {
+                RecvShadow rk = {s_sh[kc], s_sh[CELLS + kc], s_sh[2 * CELLS + kc]};
+                p = dens_shadow(w, nk, rk, nzj, L);
             }
-            w_dens[q] = p;
+            if (UNB && p > 0.0f) {
+                // candidate j's validation bit for the receiver at offset k - j
+                const int qb = (ky - cy + D) * SIDE + (kx - cx + D);
+                const uint32_t wv = bits[gj * words + (qb >> 5)];
+                if (!((wv >> (qb & 31)) & 1u)) p = 0.0f;
+            }
+            w_dens[qy * SIDE + qx] = p;
         }
         wave_sync();
-        // (2) row box sums H[row][t2] = sum_{e < 2R+1} p(row, t2 + e)
-        for (int q = lane; q < lay.hsum; q += 64) {
-            const int row = small_div(q, inv_tw), t2 = q - row * TW;
+        // (2) row box sums H[row][t] = sum_{e < 2R+1} p(row, t + e), t < ntx
+        for (int q = lane; q < HD * ntx; q += 64) {
+            const int row = small_div(q, inv_ntx), t2 = q - row * ntx;
             const float *pr = w_dens + row * SIDE + t2;
             float h = 0.0f;
             for (int e = 0; e < TW; ++e) h += pr[e];
-            w_h[q] = h;
+            w_h[row * TW + t2] = h;
         }
         wave_sync();
-        // (3) target i = j + (t2 - R, r2 - R): P_i(j) is the column box sum of H
-        for (int q = lane; q < TW * TW; q += 64) {
-            const int r2 = small_div(q, inv_tw), t2 = q - r2 * TW;
-            const int ix = cx + t2 - 2 * R, iy = cy + r2 - 2 * R;  // tile coordinates of i
-            if ((unsigned)ix < (unsigned)TX && (unsigned)iy < (unsigned)TY) {
-                float P = 0.0f;
-                for (int e = 0; e < TW; ++e) P += w_h[(r2 + e) * TW + t2];
-                const float pij = w_dens[(r2 + R) * SIDE + (t2 + R)];
-                if (pij > 0.0f && P > 0.0f)
-                    atomicAdd(&s_B[iy * TX + ix],
-                              (unsigned long long)rintf((pij * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
-            }
+        // (3) target i = (tx0 + t2, ty0 + r2): P_i(j) is the column box sum of H
+        for (int q = lane; q < nty * ntx; q += 64) {
+            const int r2 = small_div(q, inv_ntx), t2 = q - r2 * ntx;
+            float P = 0.0f;
+            for (int e = 0; e < TW; ++e) P += w_h[(r2 + e) * TW + t2];
+            const float pij = w_dens[(r2 + R) * SIDE + (t2 + R)];
+            if (pij > 0.0f && P > 0.0f)
+                atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],
+                          (unsigned long long)rintf((pij * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
         }
         wave_sync();
     }
