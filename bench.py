@@ -258,8 +258,9 @@ def run_frame(args):
     wall = time.perf_counter() - wall0
     total_ms = start.elapsed_time(end)
     ms_per_step = total_ms / args.steps
-    per = {n: float(np.mean([events[s][k].elapsed_time(events[s][k + 1]) for s in range(args.steps)]))
-           for k, n in enumerate(names)}
+    samples = {n: np.array([events[s][k].elapsed_time(events[s][k + 1]) for s in range(args.steps)])
+               for k, n in enumerate(names)}
+    per = {n: float(v.mean()) for n, v in samples.items()}
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f}); " +
         ", ".join(f"{k} {v:.3f}" for k, v in per.items()))
 
@@ -310,6 +311,8 @@ def run_frame(args):
                                f"{W}x{H}, 1 spp, R={R} m, 7x7 window, no-reuse + biased + unbiased",
                    "global_batch": 1, "seq_len": W * H, "parallelism": "single-gpu"},
         "kernels_ms": {k: round(v, 4) for k, v in per.items()},
+        "kernels_ms_p50": {k: round(float(np.percentile(v, 50)), 4) for k, v in samples.items()},
+        "kernels_ms_p90": {k: round(float(np.percentile(v, 90)), 4) for k, v in samples.items()},
         "trace_mrays_s": round(rays / (per["trace"] * 1e-3) / 1e6, 1),
         "reuse_gbs": round(reuse_gbs, 1),
         "reused_samples_per_s": round(hits * (2 * r + 1) ** 2 / (per["reuse_biased"] * 1e-3), 1),

@@ -102,7 +102,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
     // bits, and compact the cells whose ray found an occluder.
     for (int c = tid; c < CELLS; c += kRBlock) {
         const int cyy = small_div(c, inv_rw);
-        int gx = x0 + (c - cyy * RW), gy = y0 + cyy;
+        int gx = x0 + (c - __mul24(cyy, RW)), gy = y0 + cyy;
         bool inside = gx >= 0 && gx < g.w && gy >= 0 && gy < g.h;
         int64_t gi = inside ? (int64_t)gy * g.w + gx : 0;
         bool valid = inside && g.prim[gi] != OCR_HIT_MISS;
@@ -136,7 +136,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
     const int ncand = *s_count;
     for (int li = wave; li < ncand; li += kRBlock / 64) {
         const int c = __builtin_amdgcn_readfirstlane((int)s_list[li]);
-        const int cy = small_div(c, inv_rw), cx = c - cy * RW;
+        const int cy = small_div(c, inv_rw), cx = c - __mul24(cy, RW);
         const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
         float oj[3] = {s_o[c], s_o[CELLS + c], s_o[2 * CELLS + c]};
         float dzj[3], nzj[3];
@@ -155,9 +155,10 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         const float inv_wd = 1.0f / (float)WD, inv_ntx = 1.0f / (float)ntx;
         // (1) densities p_k(j) over the rectangle, row stride SIDE
         for (int q = lane; q < WD * HD; q += 64) {
-            const int qy = small_div(q, inv_wd), qx = q - qy * WD;
+            // (index products by 24-bit multiplies: full rate, all operands < 2^23)
+            const int qy = small_div(q, inv_wd), qx = q - __mul24(qy, WD);
             const int kx = kx0 + qx, ky = ky0 + qy;
-            const int kc = ky * RW + kx;
+            const int kc = __mul24(ky, RW) + kx;
             float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
             float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
             float w[3];
@@ -171,28 +172,32 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
             }
             if (UNB && p > 0.0f) {
                 // candidate j's validation bit for the receiver at offset k - j
-                const int qb = (ky - cy + D) * SIDE + (kx - cx + D);
+                const int qb = __mul24(ky - cy + D, SIDE) + (kx - cx + D);
                 const uint32_t wv = bits[gj * words + (qb >> 5)];
                 if (!((wv >> (qb & 31)) & 1u)) p = 0.0f;
             }
-            w_dens[qy * SIDE + qx] = p;
+            w_dens[__mul24(qy, SIDE) + qx] = p;
         }
         wave_sync();
         // (2) row box sums H[row][t] = sum_{e < 2R+1} p(row, t + e), t < ntx
         for (int q = lane; q < HD * ntx; q += 64) {
-            const int row = small_div(q, inv_ntx), t2 = q - row * ntx;
-            const float *pr = w_dens + row * SIDE + t2;
+            const int row = small_div(q, inv_ntx), t2 = q - __mul24(row, ntx);
+            const float *pr = w_dens + __mul24(row, SIDE) + t2;
             float h = 0.0f;
+            // unrolled so the LDS reads issue together; the additions keep their order
+#pragma unroll 4
             for (int e = 0; e < TW; ++e) h += pr[e];
-            w_h[row * TW + t2] = h;
+            w_h[__mul24(row, TW) + t2] = h;
         }
         wave_sync();
         // (3) target i = (tx0 + t2, ty0 + r2): P_i(j) is the column box sum of H
         for (int q = lane; q < nty * ntx; q += 64) {
-            const int r2 = small_div(q, inv_ntx), t2 = q - r2 * ntx;
+            const int r2 = small_div(q, inv_ntx), t2 = q - __mul24(r2, ntx);
+            const float *ph = w_h + __mul24(r2, TW) + t2;
             float P = 0.0f;
-            for (int e = 0; e < TW; ++e) P += w_h[(r2 + e) * TW + t2];
-            const float pij = w_dens[(r2 + R) * SIDE + (t2 + R)];
+#pragma unroll 4
+            for (int e = 0; e < TW; ++e) P += ph[__mul24(e, TW)];
+            const float pij = w_dens[__mul24(r2 + R, SIDE) + (t2 + R)];
             if (pij > 0.0f && P > 0.0f)
                 atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],
                           (unsigned long long)rintf((pij * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
@@ -206,7 +211,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         const int ix = t % TX, iy = t / TX;
         const int px = tx * TX + ix, py = ty * TY + iy;
         if (px >= g.w || py >= g.h) continue;
-        const int c = (iy + R) * RW + (ix + R);
+        const int c = __mul24(iy + R, RW) + (ix + R);
         const bool valid = s_valid[c];
         const float B = (float)((double)s_B[t] * 0x1p-32);
         float F = 1.0f;
