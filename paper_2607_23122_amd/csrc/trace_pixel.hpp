@@ -46,7 +46,7 @@ __device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, floa
         tmax = 1.0f;
     }
     TRay r;
-    make_ray(o, d, prim, OCR_HIT_MISS, r);
+    make_ray(o, d, prim, OCR_HIT_MISS, tmax, r);
     Hit h = traverse<false, MODE == OCR_AO, COUNT>(bvh, r, tmax, stack, stride, ws);
     out.hit[i] = h.tri;
     if (h.tri == OCR_HIT_MISS) return;

@@ -18,14 +18,15 @@
 namespace ocr {
 
 // Slab test with one FMA per plane: the distance to the plane x_c = l is
-// l * inv_c + off, with off = -o_c * inv_c moved by eps_c = 2^-21 |o_c inv_c|
-// towards the ray for the near plane of the axis and away from it for the
-// far plane (which plane is near follows the sign of inv_c).  Against
-// (l - o_c) * inv_c the FMA form adds an absolute error of at most about
-// 2^-23 |o_c inv_c| (the rounded product and offset), which eps_c covers;
-// the relative error is covered, as before, by widening the far distance by
-// 1 + 2^-20.  So the test stays conservative: no box the ray enters is
-// skipped, and hits do not depend on it.
+// l * inv_c + off, with off = -o_c * inv_c moved by eps_c towards the ray for
+// the near plane of the axis and away from it for the far plane (which plane
+// is near follows the sign of inv_c).  Against the exact (l - o_c) / d_c the
+// computed distance errs by at most about 2^-23 |o_c inv_c| (the rounded
+// product and offset) plus 2^-22 of the distance itself (the rounded 1/d_c
+// and FMA).  Only boxes entered before tmax can matter, so the relative part
+// is at most 2^-22 tmax there, and eps_c = 2^-21 |o_c inv_c| + 2^-20 tmax
+// covers both with margin.  So the test stays conservative: no box the ray
+// enters is skipped, and hits do not depend on it.
 struct TRay {
     float o[3];
     float inv[3];   // 1 / d with zero components replaced by +-1e-20
@@ -34,13 +35,15 @@ struct TRay {
     uint32_t ign0, ign1;
 };
 
-__device__ inline void make_ray(const float o[3], const float d[3], uint32_t ign0, uint32_t ign1, TRay &r) {
+// tmax: the end of the ray's t range (sets the relative part of the slack).
+__device__ inline void make_ray(const float o[3], const float d[3], uint32_t ign0, uint32_t ign1, float tmax,
+                                TRay &r) {
     for (int c = 0; c < 3; ++c) {
         r.o[c] = o[c];
         float dc = fabsf(d[c]) < 1e-20f ? copysignf(1e-20f, d[c]) : d[c];
         r.inv[c] = 1.0f / dc;
         const float oi = o[c] * r.inv[c];
-        const float eps = 0x1p-21f * fabsf(oi);
+        const float eps = __fmaf_rn(0x1p-21f, fabsf(oi), 0x1p-20f * tmax);
         // inv > 0: the low plane is near (offset lowered), the high plane far (raised)
         const float s = r.inv[c] > 0.0f ? eps : -eps;
         r.off_lo[c] = -oi - s;
@@ -154,7 +157,7 @@ __device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, 
                 float t0y = __fmaf_rn(lys[i], r.inv[1], r.off_lo[1]), t1y = __fmaf_rn(hys[i], r.inv[1], r.off_hi[1]);
                 float t0z = __fmaf_rn(lzs[i], r.inv[2], r.off_lo[2]), t1z = __fmaf_rn(hzs[i], r.inv[2], r.off_hi[2]);
                 float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-                float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
+                float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
                 tfar = fminf(tfar, h.t * grow);
                 bool hit = tnear <= tfar && chs[i] != kEmpty;
                 tn[i] = hit ? tnear : INFINITY;
@@ -314,7 +317,7 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
                         float t1z = __fmaf_rn(hzs[i], rq.inv[2], rq.off_hi[2]);
                         float tnear =
                             fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-                        float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
+                        float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
                         tfar = fminf(tfar, tmax * grow);
                         hit |= tnear <= tfar;
                     }
@@ -419,7 +422,7 @@ __device__ inline bool traverse_wave_any_masked(const DeviceBVH &bvh, const TRay
                     const float t0z = __fmaf_rn(lzs[i], r.inv[2], r.off_lo[2]);
                     const float t1z = __fmaf_rn(hzs[i], r.inv[2], r.off_hi[2]);
                     const float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-                    float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * grow;
+                    float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
                     tfar = fminf(tfar, tmax * grow);
                     const unsigned long long m = __ballot(in && tnear <= tfar);
                     const uint32_t ch = chs[i];
