@@ -88,30 +88,44 @@ __device__ inline float front_fraction(const float o[3], const float n[3], const
     float f0 = -dot3f(n, oc), fu = dot3f(n, L.eu), fv = dot3f(n, L.ev);
     const float ca[4] = {-0.5f, 0.5f, 0.5f, -0.5f};
     const float cb[4] = {-0.5f, -0.5f, 0.5f, 0.5f};
-    float pa[5], pb[5];
+    // Walk the square's edges emitting the clipped polygon's vertices in
+    // order and accumulate the shoelace sum on the fly (first and previous
+    // vertex only: no arrays, so nothing goes to private memory).
+    float area = 0.0f, a0 = 0.0f, b0 = 0.0f, ap = 0.0f, bp = 0.0f;
     int m = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int k1 = (k + 1) & 3;
-        float fa = f0 + ca[k] * fu + cb[k] * fv;
-        float fb = f0 + ca[k1] * fu + cb[k1] * fv;
-        if (fa > 0.0f) {
-            pa[m] = ca[k];
-            pb[m] = cb[k];
-            ++m;
-        }
-        if ((fa > 0.0f) != (fb > 0.0f)) {
-            float t = fa / (fa - fb);
-            pa[m] = ca[k] + t * (ca[k1] - ca[k]);
-            pb[m] = cb[k] + t * (cb[k1] - cb[k]);
-            ++m;
+        const int k1 = (k + 1) & 3;
+        const float fa = f0 + ca[k] * fu + cb[k] * fv;
+        const float fb = f0 + ca[k1] * fu + cb[k1] * fv;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            float va, vb;
+            bool emit;
+            if (e == 0) {
+                emit = fa > 0.0f;
+                va = ca[k];
+                vb = cb[k];
+            } else {
+                emit = (fa > 0.0f) != (fb > 0.0f);
+                const float t = emit ? fa / (fa - fb) : 0.0f;
+                va = ca[k] + t * (ca[k1] - ca[k]);
+                vb = cb[k] + t * (cb[k1] - cb[k]);
+            }
+            if (emit) {
+                if (m == 0) {
+                    a0 = va;
+                    b0 = vb;
+                } else {
+                    area += ap * vb - va * bp;
+                }
+                ap = va;
+                bp = vb;
+                ++m;
+            }
         }
     }
-    float area = 0.0f;
-    for (int k = 0; k < m; ++k) {
-        int k1 = k + 1 == m ? 0 : k + 1;
-        area += pa[k] * pb[k1] - pa[k1] * pb[k];
-    }
+    if (m > 0) area += ap * b0 - a0 * bp;
     return 0.5f * fabsf(area);
 }
 
