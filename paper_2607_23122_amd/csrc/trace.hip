@@ -157,24 +157,32 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
     __shared__ uint16_t wq[kBlock / 64][kMaxPairs];
     __shared__ uint32_t wbits[kBlock / 64][kMaxWords];
     WalkStats ws;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // wave-uniform by construction; readfirstlane lets the compiler keep the
+    // candidate bookkeeping derived from it in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int side = 2 * D + 1, npairs = side * side;
     const float inv_side = 1.0f / (float)side;
     // the 8 lists concatenated (roughly tile order); consecutive candidates go
     // to the waves of one block, which then share the CU's caches
-    uint32_t start[9];
-    start[0] = 0;
+    uint32_t total = 0;
 #pragma unroll
-    for (int x = 0; x < 8; ++x) start[x + 1] = start[x] + lists[x * kCountStride];
-    const uint32_t total = start[8];
+    for (int x = 0; x < 8; ++x) total += lists[x * kCountStride];
     const uint32_t stride = gridDim.x * (kBlock / 64);
     for (uint32_t li = blockIdx.x * (kBlock / 64) + wave; li < total; li += stride) {
-        int x = 0;
+        // list x and the position in it of the li-th candidate (scalar)
+        uint32_t off = li, base = 8 * kCountStride;
 #pragma unroll
-        for (int q = 1; q < 8; ++q) x += li >= start[q] ? 1 : 0;
-        const int64_t j = __builtin_amdgcn_readfirstlane(
-            (int)lists[8 * kCountStride + (uint32_t)x * per_xcd + (li - start[x])]);
+        for (int x = 0; x < 7; ++x) {
+            const uint32_t n = lists[x * kCountStride];
+            if (off >= n) {
+                off -= n;
+                base += per_xcd;
+            } else {
+                break;
+            }
+        }
+        const int64_t j = __builtin_amdgcn_readfirstlane((int)lists[base + off]);
         const int jy = (int)((uint32_t)j / (uint32_t)g.w), jx = (int)j - jy * g.w;
         const uint32_t hj = occ.hit[j];
         float xj[3], nj[3], oj[3], dzj[3], nzj[3];
