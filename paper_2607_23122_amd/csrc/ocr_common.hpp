@@ -149,12 +149,13 @@ __device__ inline bool shadow_traced(const float n[3], const float o[3], const f
     return front > 0.0f && lit > 0.0f;
 }
 
-// q / d for 0 <= q < 2^22 and d >= 1 with one FP32 multiply by inv_d =
-// 1.0f / d (correctly rounded): (q + 1/2) / d lies at least 1/(2d) from an
-// integer and the FP32 product is within (q + 1/2) 2^-23 / d of it, so the
-// truncation is the exact quotient (checked exhaustively for q < 2^16,
-// d <= 1024).  Integer division by a runtime value is a long instruction
-// sequence on this hardware.
+// q / d for 0 <= q < 2^21 and d >= 1 with one FP32 multiply by inv_d, an
+// approximation of 1/d within one ulp (correctly rounded, or the hardware
+// reciprocal): (q + 1/2) / d lies at least 1/(2d) from an integer and the
+// FP32 product is within (q + 1/2) 3 2^-24 / d of it, so the truncation is
+// the exact quotient (checked exhaustively on the host for q < 2^16,
+// d <= 1024 with both neighbours of 1/d).  Integer division by a runtime
+// value is a long instruction sequence on this hardware.
 __device__ inline int small_div(int q, float inv_d) { return (int)(((float)q + 0.5f) * inv_d); }
 
 // Make this wave's LDS writes visible to its other lanes before they read.

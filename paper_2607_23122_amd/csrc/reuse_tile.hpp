@@ -23,6 +23,9 @@
 namespace ocr {
 
 constexpr int kRBlock = 256;
+// A candidate with at most this many positive densities in its rectangle takes
+// the sparse path of the scatter.
+constexpr int kSparse = 8;
 
 __device__ inline void ld3(const float *p, int64_t i, float v[3]) {
     v[0] = p[3 * i];
@@ -56,7 +59,7 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     l.cells = l.RWX * l.RWY;
     l.side = 4 * R + 1;
     l.dens = l.side * l.side;
-    l.hsum = l.side * (2 * R + 1);
+    l.hsum = l.side * (2 * R + 1) > 2 * kSparse ? l.side * (2 * R + 1) : 2 * kSparse;
     l.words = words;
     size_t off = 0;
     l.B_off = lds_take(off, sizeof(unsigned long long) * kWTX * kWTY);
@@ -152,55 +155,117 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         const int ntx = tx1 - tx0 + 1, nty = ty1 - ty0 + 1;
         const int WD = ntx + 2 * R, HD = nty + 2 * R;
         const int kx0 = tx0 - R, ky0 = ty0 - R;
-        const float inv_wd = 1.0f / (float)WD, inv_ntx = 1.0f / (float)ntx;
-        // (1) densities p_k(j) over the rectangle, row stride SIDE
-        for (int q = lane; q < WD * HD; q += 64) {
-            // (index products by 24-bit multiplies: full rate, all operands < 2^23)
-            const int qy = small_div(q, inv_wd), qx = q - __mul24(qy, WD);
-            const int kx = kx0 + qx, ky = ky0 + qy;
-            const int kc = __mul24(ky, RW) + kx;
-            float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
-            float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
-            float w[3];
-            rel_vec(oj, ok, dzj, w);
-            float p;
-            if (MODE == OCR_AO) {
-                p = dens_ao(w, nk, nzj, R2);
-            } else {
-                RecvShadow rk = {s_sh[kc], s_sh[CELLS + kc], s_sh[2 * CELLS + kc]};
-                p = dens_shadow(w, nk, rk, nzj, L);
+        // (hardware reciprocals: small_div stays exact with a 1-ulp inverse
+        // for the quotients below, all < 2^12)
+        const float inv_wd = __builtin_amdgcn_rcpf((float)WD), inv_ntx = __builtin_amdgcn_rcpf((float)ntx);
+        const int nq = WD * HD;
+        // (1) densities p_k(j) over the rectangle, row stride SIDE; every lane
+        // runs every pass so that the count of positive densities is uniform.
+        // Shadow candidates have a few positive densities at most (the light
+        // subtends a narrow cone); AO candidates most often have dozens.
+        constexpr bool kSparsePath = MODE == OCR_SHADOW;
+        int npos = 0;
+        int *e_code = reinterpret_cast<int *>(w_h);  // positive entries, q order
+        float *e_p = w_h + kSparse;
+        for (int q0 = 0; q0 < nq; q0 += 64) {
+            const int q = q0 + lane;
+            float p = 0.0f;
+            int qy = 0, qx = 0;
+            if (q < nq) {
+                // (index products by 24-bit multiplies: full rate, all operands < 2^23)
+                qy = small_div(q, inv_wd);
+                qx = q - __mul24(qy, WD);
+                const int kx = kx0 + qx, ky = ky0 + qy;
+                const int kc = __mul24(ky, RW) + kx;
+                float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
+                float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
+                float w[3];
+                rel_vec(oj, ok, dzj, w);
+                if (MODE == OCR_AO) {
+                    p = dens_ao(w, nk, nzj, R2);
+                } else {
+                    RecvShadow rk = {s_sh[kc], s_sh[CELLS + kc], s_sh[2 * CELLS + kc]};
+                    p = dens_shadow(w, nk, rk, nzj, L);
+                }
+                if (UNB && p > 0.0f) {
+                    // candidate j's validation bit for the receiver at offset k - j
+                    const int qb = __mul24(ky - cy + D, SIDE) + (kx - cx + D);
+                    const uint32_t wv = bits[gj * words + (qb >> 5)];
+                    if (!((wv >> (qb & 31)) & 1u)) p = 0.0f;
+                }
+                w_dens[__mul24(qy, SIDE) + qx] = p;
             }
-            if (UNB && p > 0.0f) {
-                // candidate j's validation bit for the receiver at offset k - j
-                const int qb = __mul24(ky - cy + D, SIDE) + (kx - cx + D);
-                const uint32_t wv = bits[gj * words + (qb >> 5)];
-                if (!((wv >> (qb & 31)) & 1u)) p = 0.0f;
+            if (!kSparsePath) continue;
+            const unsigned long long pm = __ballot(p > 0.0f);
+            if (npos < kSparse) {
+                // keep the first kSparse positive entries for the sparse path
+                const int at = npos + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(pm >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
+                if (p > 0.0f && at < kSparse) {
+                    e_code[at] = (qy << 8) | qx;
+                    e_p[at] = p;
+                }
             }
-            w_dens[__mul24(qy, SIDE) + qx] = p;
+            npos += (int)__popcll(pm);
         }
         wave_sync();
-        // (2) row box sums H[row][t] = sum_{e < 2R+1} p(row, t + e), t < ntx
-        for (int q = lane; q < HD * ntx; q += 64) {
-            const int row = small_div(q, inv_ntx), t2 = q - __mul24(row, ntx);
-            const float *pr = w_dens + __mul24(row, SIDE) + t2;
-            float h = 0.0f;
-            // unrolled so the LDS reads issue together; the additions keep their order
+        if (kSparsePath && npos <= kSparse) {
+            // (2') Few positive densities (most shadow candidates): P_i(j) from
+            // the positive entries alone.  Lane e takes entry e; the sums run
+            // over the rows in order and within a row over the columns in
+            // order, the grouping of the box sums below, which only add zeros
+            // besides (exact), so both paths give the same bits.
+            int my_code = 0;
+            float my_p = 0.0f;
+            if (lane < npos) {
+                my_code = e_code[lane];
+                my_p = e_p[lane];
+            }
+            const int my_y = my_code >> 8, my_x = my_code & 255;
+            const bool tgt = lane < npos && my_x >= R && my_x < R + ntx && my_y >= R && my_y < R + nty;
+            if (__ballot(tgt) != 0ull) {
+                float P = 0.0f, h = 0.0f;
+                int row = -1;
+                for (int m = 0; m < npos; ++m) {
+                    const int cm = __builtin_amdgcn_readlane(my_code, m);
+                    const float pv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_p), m));
+                    const int ym = cm >> 8, xm = cm & 255;
+                    if (ym != row) {
+                        P += h;
+                        h = 0.0f;
+                        row = ym;
+                    }
+                    if (abs(ym - my_y) <= R && abs(xm - my_x) <= R) h += pv;
+                }
+                P += h;
+                if (tgt)
+                    atomicAdd(&s_B[(ky0 + my_y - R) * TX + (kx0 + my_x - R)],
+                              (unsigned long long)rintf((my_p * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
+            }
+        } else {
+            // (2) row box sums H[row][t] = sum_{e < 2R+1} p(row, t + e), t < ntx
+            for (int q = lane; q < HD * ntx; q += 64) {
+                const int row = small_div(q, inv_ntx), t2 = q - __mul24(row, ntx);
+                const float *pr = w_dens + __mul24(row, SIDE) + t2;
+                float h = 0.0f;
+                // unrolled so the LDS reads issue together; the additions keep their order
 #pragma unroll 4
-            for (int e = 0; e < TW; ++e) h += pr[e];
-            w_h[__mul24(row, TW) + t2] = h;
-        }
-        wave_sync();
-        // (3) target i = (tx0 + t2, ty0 + r2): P_i(j) is the column box sum of H
-        for (int q = lane; q < nty * ntx; q += 64) {
-            const int r2 = small_div(q, inv_ntx), t2 = q - __mul24(r2, ntx);
-            const float *ph = w_h + __mul24(r2, TW) + t2;
-            float P = 0.0f;
+                for (int e = 0; e < TW; ++e) h += pr[e];
+                w_h[__mul24(row, TW) + t2] = h;
+            }
+            wave_sync();
+            // (3) target i = (tx0 + t2, ty0 + r2): P_i(j) is the column box sum of H
+            for (int q = lane; q < nty * ntx; q += 64) {
+                const int r2 = small_div(q, inv_ntx), t2 = q - __mul24(r2, ntx);
+                const float *ph = w_h + __mul24(r2, TW) + t2;
+                float P = 0.0f;
 #pragma unroll 4
-            for (int e = 0; e < TW; ++e) P += ph[__mul24(e, TW)];
-            const float pij = w_dens[__mul24(r2 + R, SIDE) + (t2 + R)];
-            if (pij > 0.0f && P > 0.0f)
-                atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],
-                          (unsigned long long)rintf((pij * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
+                for (int e = 0; e < TW; ++e) P += ph[__mul24(e, TW)];
+                const float pij = w_dens[__mul24(r2 + R, SIDE) + (t2 + R)];
+                if (pij > 0.0f && P > 0.0f)
+                    atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],
+                              (unsigned long long)rintf((pij * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
+            }
         }
         wave_sync();
     }
