@@ -41,9 +41,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 VALU rate with packed FP32 disabled, one op per lane per cycle:
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T ops/s
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 VALU peak with packed FP32 disabled (the build turns it off): one
+# instruction per lane per cycle, an FMA counting as two operations, as in the
+# op counts below (a slab plane's subtract and multiply are one FMA):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz = 78.6 TFLOP/s.  (The published
+# 157.3 TFLOP/s needs packed FP32.)  Ops that are not FMAs (min/max, compares,
+# selects) count once but take a full issue slot, so an op mix like the box
+# test's (12 of its 26 ops in 6 FMAs; 17 instructions with three-operand
+# min/max) tops out near 26 / 34 = 0.76 of this peak.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # FP32 operations of one test of one ray or segment, counted from the kernels
 # (the counted tests are those each ray or segment needs on its own; lanes
 # of a wave that execute a test their segment does not need are not useful

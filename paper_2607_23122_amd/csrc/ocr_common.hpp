@@ -158,6 +158,11 @@ __device__ inline bool shadow_traced(const float n[3], const float o[3], const f
 // value is a long instruction sequence on this hardware.
 __device__ inline int small_div(int q, float inv_d) { return (int)(((float)q + 0.5f) * inv_d); }
 
+// Lane mask of the wave's lanes (active ones) where p holds; the compiler
+// builtin takes the compare's own mask, where __ballot materialises the bool
+// in a vector register and compares it again.
+__device__ inline unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 // Make this wave's LDS writes visible to its other lanes before they read.
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

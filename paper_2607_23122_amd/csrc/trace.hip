@@ -144,30 +144,6 @@ __device__ inline bool pair_receiver(const GBufView &g, int jx, int jy, int side
     return true;
 }
 
-// The G-buffer entries of receiver q of candidate j, loaded ahead of their
-// use so that one 64-wide round of densities overlaps the next round's loads.
-struct PairFetch {
-    int64_t k;
-    bool in;
-    uint32_t prim;
-    float x[3], n[3];
-};
-
-__device__ inline void pair_fetch(const GBufView &g, int jx, int jy, int side, float inv_side, int D, int q,
-                                  int npairs, PairFetch &f) {
-    const int qy = small_div(q, inv_side);
-    const int kx = jx + (q - qy * side) - D, ky = jy + qy - D;
-    f.in = q < npairs && kx >= 0 && kx < g.w && ky >= 0 && ky < g.h;
-    f.k = 0;
-    f.prim = OCR_HIT_MISS;
-    if (f.in) {
-        f.k = (int64_t)ky * g.w + kx;
-        f.prim = g.prim[f.k];
-        load3(g.pos, f.k, f.x);
-        load3(g.nrm, f.k, f.n);
-    }
-}
-
 // COUNT: the work-accounting instantiation (lane-masked walk, same bits),
 // which adds the segments' useful work to stats[0..4].  Bounded to 7 waves
 // per SIMD (72 registers, a few spilled): at its natural 88 registers (5
@@ -219,30 +195,27 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
         // (1) the receivers with positive density, compacted in q order
         for (int w = lane; w < words; w += 64) wbits[wave][w] = 0u;
         int count = 0;
-        PairFetch cur, nxt;
-        nxt.in = false;
-        pair_fetch(g, jx, jy, side, inv_side, D, lane, npairs, cur);
         for (int base = 0; base < npairs; base += 64) {
-            if (base + 64 < npairs) pair_fetch(g, jx, jy, side, inv_side, D, base + 64 + lane, npairs, nxt);
             const int q = base + lane;
             bool want = false;
-            if (cur.in && cur.prim != OCR_HIT_MISS && cur.k != j) {
-                float ok[3], w[3];
-                offset_point(cur.x, cur.n, ok);
+            int64_t k;
+            uint32_t primk;
+            float ok[3], nk[3];
+            if (q < npairs && pair_receiver(g, jx, jy, side, inv_side, D, q, k, primk, ok, nk) && k != j) {
+                float w[3];
                 rel_vec(oj, ok, dzj, w);
                 float p;
                 if (MODE == OCR_AO) {
-                    p = dens_ao(w, cur.n, nzj, R2);
+                    p = dens_ao(w, nk, nzj, R2);
                 } else {
                     RecvShadow rk = recv_shadow(ok, L);
-                    p = dens_shadow(w, cur.n, rk, nzj, L);
+                    p = dens_shadow(w, nk, rk, nzj, L);
                 }
                 want = p > 0.0f;
             }
             const unsigned long long m = __ballot(want);
             if (want) wq[wave][count + __popcll(m & below)] = (uint16_t)q;
             count += __popcll(m);
-            cur = nxt;
         }
         wave_sync();
         // (2) one walk per 64 listed segments

@@ -265,14 +265,18 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
                                          const bool (&want)[NR], bool (&blocked)[NR], uint32_t *wstack,
                                          WalkStats &st) {
     bool active[NR];
-    bool any = false;
+    // the active lanes of each segment set as a wave-uniform mask, kept in
+    // step with active[] (box-test ballots are masked with it)
+    unsigned long long amask[NR];
+    unsigned long long any = 0ull;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         active[q] = want[q];
         blocked[q] = false;
-        any |= active[q];
+        amask[q] = wave_ballot(active[q]);
+        any |= amask[q];
     }
-    if (__ballot(any) == 0ull) return;
+    if (any == 0ull) return;
     st.walks += 1;
     const float grow = 1.0f + 0x1p-20f;
     int sp = 0;
@@ -300,29 +304,34 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
                 hzs[i] = np[20 + i];
                 chs[i] = cp[24 + i];
             }
+            // all of the node's scalar loads issue together, ahead of the
+            // per-child branches (else each child waits for its own)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                asm volatile("" ::"s"(lxs[i]), "s"(hxs[i]), "s"(lys[i]), "s"(hys[i]), "s"(lzs[i]), "s"(hzs[i]),
+                             "s"(chs[i]));
             uint32_t next = kEmpty;
 #pragma unroll
             for (int i = 3; i >= 0; --i) {
                 if (chs[i] == kEmpty) continue;  // wave-uniform: skip the slot's tests
-                bool hit = false;
+                // every lane tests (no exec-mask branch); the active mask is
+                // applied to the ballot
+                unsigned long long hit = 0ull;
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
-                    if (active[q]) {
-                        const TRay &rq = r[q];
-                        float t0x = __fmaf_rn(lxs[i], rq.inv[0], rq.off_lo[0]);
-                        float t1x = __fmaf_rn(hxs[i], rq.inv[0], rq.off_hi[0]);
-                        float t0y = __fmaf_rn(lys[i], rq.inv[1], rq.off_lo[1]);
-                        float t1y = __fmaf_rn(hys[i], rq.inv[1], rq.off_hi[1]);
-                        float t0z = __fmaf_rn(lzs[i], rq.inv[2], rq.off_lo[2]);
-                        float t1z = __fmaf_rn(hzs[i], rq.inv[2], rq.off_hi[2]);
-                        float tnear =
-                            fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-                        float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
-                        tfar = fminf(tfar, tmax * grow);
-                        hit |= tnear <= tfar;
-                    }
+                    const TRay &rq = r[q];
+                    float t0x = __fmaf_rn(lxs[i], rq.inv[0], rq.off_lo[0]);
+                    float t1x = __fmaf_rn(hxs[i], rq.inv[0], rq.off_hi[0]);
+                    float t0y = __fmaf_rn(lys[i], rq.inv[1], rq.off_lo[1]);
+                    float t1y = __fmaf_rn(hys[i], rq.inv[1], rq.off_hi[1]);
+                    float t0z = __fmaf_rn(lzs[i], rq.inv[2], rq.off_lo[2]);
+                    float t1z = __fmaf_rn(hzs[i], rq.inv[2], rq.off_hi[2]);
+                    float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+                    float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
+                    tfar = fminf(tfar, tmax * grow);
+                    hit |= wave_ballot(tnear <= tfar) & amask[q];
                 }
-                if (chs[i] != kEmpty && __ballot(hit) != 0ull) {
+                if (chs[i] != kEmpty && hit != 0ull) {
                     // children pushed in reverse so that child 0 is visited first
                     if (next != kEmpty) {
                         wstack[sp] = next;
@@ -358,10 +367,13 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
                     }
                 }
             }
-            bool still = false;
+            unsigned long long still = 0ull;
 #pragma unroll
-            for (int q = 0; q < NR; ++q) still |= active[q];
-            if (__ballot(still) == 0ull) return;
+            for (int q = 0; q < NR; ++q) {
+                amask[q] = wave_ballot(active[q]);
+                still |= amask[q];
+            }
+            if (still == 0ull) return;
         }
         if (sp == 0) break;
         --sp;
