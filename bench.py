@@ -343,6 +343,8 @@ def run_frame(args):
     result["trace_roofline"] = alu_roofline(
         counted_trace(ocr, torch, bvh, dg, mode, R, light, cfg["sample_seed"], args.steps - 1), per["trace"],
         "trace_kernel")
+    if args.workload == "ao_1080p":
+        result["trace_roofline"]["traffic"] = measured_traffic("ocr::trace_kernel<0>")
     if args.cpu_baseline == "on":
         result["cpu_baseline"] = cpu_baseline(scene, gb, cfg, light, args.cpu_seconds)
     return result
