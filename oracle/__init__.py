@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
                 ("sample", ctypes.c_uint32), ("pad", ctypes.c_int32)]
 
 
-MODES = {"ao": 0, "shadow": 1}
+MODES = {"ao": 0, "shadow": 1, "shadow_sa": 2}
 ESTIMATORS = {"none": 0, "biased": 1, "unbiased": 2}
 PATTERNS = {"window": 0, "group": 1}
 
@@ -97,6 +97,11 @@ def _load():
     lib.orc_ao_quadrature.argtypes = [vp, vp, vp, f64, ctypes.c_uint32, i32]
     lib.orc_shadow_quadrature.restype = f64
     lib.orc_shadow_quadrature.argtypes = [vp, vp, vp, vp, ctypes.c_uint32, i32]
+    lib.orc_shadow_sa_quadrature.restype = f64
+    lib.orc_shadow_sa_quadrature.argtypes = [vp, vp, vp, vp, ctypes.c_uint32, i32]
+    lib.orc_solid_angles.argtypes = [vp, vp, vp, vp]
+    lib.orc_sa_factor.restype = f64
+    lib.orc_sa_factor.argtypes = [vp, vp, vp, vp]
     lib.orc_pcg4d_first.restype = ctypes.c_uint32
     lib.orc_pcg4d_first.argtypes = [ctypes.c_uint32] * 4 + [vp]
     lib.orc_num_threads.restype = i32
@@ -169,6 +174,12 @@ class Scene:
         n = np.ascontiguousarray(n, np.float64)
         la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
         return float(_load().orc_shadow_quadrature(self.h, _ptr(o), _ptr(n), _ptr(la), int(ign), int(ngrid)))
+
+    def shadow_sa_quadrature(self, o, n, light, ign=MISS, ngrid=512):
+        o = np.ascontiguousarray(o, np.float64)
+        n = np.ascontiguousarray(n, np.float64)
+        la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
+        return float(_load().orc_shadow_sa_quadrature(self.h, _ptr(o), _ptr(n), _ptr(la), int(ign), int(ngrid)))
 
 
 def _gb(gb):
@@ -276,3 +287,20 @@ def front_fraction(o, n, light) -> float:
     n = np.ascontiguousarray(n, np.float64)
     la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
     return float(_load().orc_front_fraction(_ptr(o), _ptr(n), _ptr(la)))
+
+
+def solid_angles(o, n, light):
+    """(Omega_A, Omega_front): the light's solid angle at o and its part in
+    front of the tangent plane of (o, n)."""
+    o = np.ascontiguousarray(o, np.float64)
+    n = np.ascontiguousarray(n, np.float64)
+    la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
+    out = np.zeros(2, np.float64)
+    _load().orc_solid_angles(_ptr(o), _ptr(n), _ptr(la), _ptr(out))
+    return float(out[0]), float(out[1])
+
+
+def sa_factor(o, n, z, light) -> float:
+    a = [np.ascontiguousarray(v, np.float64) for v in (o, n, z)]
+    la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
+    return float(_load().orc_sa_factor(*[_ptr(v) for v in a], _ptr(la)))

@@ -20,7 +20,12 @@
  *     and its biased form (Eqs. ao-biased-estimator, shadow-biased-estimator)
  *     with the dark-region guard of Sec. 4.4;
  *   - accumulation over samples (final line of both algorithms);
- *   - FP64 quadrature references of Eqs. ao-hemisphere and shadow-area.
+ *   - FP64 quadrature references of Eqs. ao-hemisphere and shadow-area;
+ *   - shadows under the solid-angle definition (App. on that definition:
+ *     Eq. reapp-shadow-definition-solid-angle, the MIS estimator of Eq.
+ *     reapp-shadow-solid-angle-estimator with the factor C_Omega of Eq.
+ *     reapp-shadow-solid-angle-mis-factor), with the emitter's solid angle
+ *     computed exactly, and its quadrature reference.
  *
  * Readings where the paper is silent (each listed in the design notes):
  * receiver point o = x + 2^-16 (1 + max|x|) n and the receiver's own
@@ -707,6 +712,103 @@ double orc_front_fraction(const double *o, const double *n, const double *light)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Solid-angle shadows.                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Solid angle of the triangle with vertices a, b, c (vectors from the
+ * viewpoint), by the formula of Van Oosterom and Strackee (IEEE Trans.
+ * Biomed. Eng. BME-30, 1983):
+ *   tan(Omega / 2) = |a . (b x c)| / (|a||b||c| + (a.b)|c| + (a.c)|b| + (b.c)|a|). */
+static double tri_solid_angle(const double a[3], const double b[3], const double c[3]) {
+    double bc[3];
+    cross3(b, c, bc);
+    double num = fabs(dot3(a, bc));
+    double la = len3(a), lb = len3(b), lc = len3(c);
+    double den = la * lb * lc + dot3(a, b) * lc + dot3(a, c) * lb + dot3(b, c) * la;
+    return 2.0 * atan2(num, den);
+}
+
+/* Solid angle at o of a convex planar polygon Q[0..m), as a fan of
+ * triangles from Q[0] (all of one orientation as seen from o). */
+static double polygon_solid_angle(const double o[3], double Q[][3], int m) {
+    double acc = 0.0;
+    for (int k = 1; k + 1 < m; ++k) {
+        double a[3], b[3], c[3];
+        sub3(Q[0], o, a);
+        sub3(Q[k], o, b);
+        sub3(Q[k + 1], o, c);
+        acc += tri_solid_angle(a, b, c);
+    }
+    return acc;
+}
+
+/* Omega_A(x), the solid angle the one-sided emitter subtends at o, and the
+ * part of it in front of the receiver's tangent plane (the rectangle
+ * clipped by <n, y - o> > 0); both 0 when o is not on the emitting side. */
+static void emitter_solid_angles(const double o[3], const double n[3], const double *L, double *all,
+                                 double *front, int *near_edge) {
+    double c[3], eu[3], ev[3], nl[3], area;
+    light_frame(L, c, eu, ev, nl, &area);
+    double oc[3];
+    sub3(o, c, oc);
+    double side = dot3(nl, oc);
+    if (near_edge) *near_edge = fabs(side) <= LIGHT_BAND * len3(oc);
+    *all = 0.0;
+    *front = 0.0;
+    if (!(side > 0.0)) return;
+    double P[4][3], Q[8][3];
+    const double su[4] = {-0.5, 0.5, 0.5, -0.5}, sv[4] = {-0.5, -0.5, 0.5, 0.5};
+    for (int k = 0; k < 4; ++k)
+        for (int a = 0; a < 3; ++a) P[k][a] = c[a] + su[k] * eu[a] + sv[k] * ev[a];
+    *all = polygon_solid_angle(o, P, 4);
+    int m = 0;
+    for (int k = 0; k < 4; ++k) {
+        const double *A = P[k], *B = P[(k + 1) % 4];
+        double da[3], db[3];
+        sub3(A, o, da);
+        sub3(B, o, db);
+        double fa = dot3(n, da), fb = dot3(n, db);
+        if (fa > 0.0) { memcpy(Q[m++], A, sizeof(double) * 3); }
+        if ((fa > 0.0) != (fb > 0.0)) {
+            double t = fa / (fa - fb);
+            for (int a = 0; a < 3; ++a) Q[m][a] = A[a] + t * (B[a] - A[a]);
+            ++m;
+        }
+    }
+    *front = m >= 3 ? polygon_solid_angle(o, Q, m) : 0.0;
+}
+
+/* C_Omega(x, z) = Area(A) / Omega_A(x) * <n_y', w_{y'->x}> / |x - y'|^2 at
+ * the light crossing y'(x, z) of the ray from x through z (Eq.
+ * reapp-shadow-solid-angle-mis-factor); 0 where that crossing does not
+ * exist (the ray runs away from or parallel to the light's plane). */
+static double sa_factor(const double o[3], const double z[3], const double *L, double omega_all) {
+    double c[3], eu[3], ev[3], nl[3], area;
+    light_frame(L, c, eu, ev, nl, &area);
+    if (!(omega_all > 0.0)) return 0.0;
+    double w[3], co[3];
+    sub3(z, o, w);
+    double nlw = dot3(nl, w);
+    if (!(nlw < 0.0)) return 0.0;
+    sub3(c, o, co);
+    double s = dot3(nl, co) / nlw; /* y' = o + s w */
+    double d = len3(w);
+    double cos_y = -nlw / d;          /* <n_y', w_{y'->x}> */
+    double r2 = s * s * d * d;        /* |x - y'|^2 */
+    return area / omega_all * cos_y / r2;
+}
+
+void orc_solid_angles(const double *o, const double *n, const double *light, double *out2) {
+    emitter_solid_angles(o, n, light, &out2[0], &out2[1], NULL);
+}
+
+double orc_sa_factor(const double *o, const double *n, const double *z, const double *light) {
+    double all, front;
+    emitter_solid_angles(o, n, light, &all, &front, NULL);
+    return sa_factor(o, z, light, all);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reuse sets (Eq. reuse-group).                                            */
 /* ------------------------------------------------------------------------ */
 static void group_dims(int32_t N, int *gw, int *gh) {
@@ -857,9 +959,11 @@ typedef struct {
 } target_buf;
 
 static double combine(const reuse_ctx *c, const target_buf *t, int ia, const int *amb_idx, int namb,
-                      unsigned mask, int use_fp64) {
+                      unsigned mask, int use_fp64, const double *cfac) {
     /* B_i = sum_j [p_i(j) > 0 and P_i(j) > 0] p_i(j) / P_i(j),
-     * P_i(j) = sum_{k in S(i)} p_k(j)   (App. D / App. H, step 3). */
+     * P_i(j) = sum_{k in S(i)} p_k(j)   (App. D / App. H, step 3);
+     * under the solid-angle definition each term carries the factor
+     * C_Omega(x_i, z_j) (cfac[j's index], Eq. reapp-shadow-solid-angle-estimator). */
     int m = t->m;
     double B = 0.0;
     for (int b = 0; b < m; ++b) {
@@ -877,7 +981,7 @@ static double combine(const reuse_ctx *c, const target_buf *t, int ia, const int
             Pj += v;
             if (a == ia) pij = v;
         }
-        if (pij > 0.0 && Pj > 0.0) B += pij / Pj;
+        if (pij > 0.0 && Pj > 0.0) B += (cfac ? cfac[b] : 1.0) * (pij / Pj);
     }
     return B;
 }
@@ -896,9 +1000,10 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
         *nvar = 1;
         return;
     }
-    if (p->estimator == 0) {
+    if (p->estimator == 0 && p->mode != 2) {
         /* Eqs. (ao-mc-estimator) and (shadow-mc-estimator), one sample:
-         * V = 1 when the ray or segment is free. */
+         * V = 1 when the ray or segment is free.  (Solid-angle shadows take
+         * the general path below with S(i) = {i}.) */
         *value = c->hit[i] == ORC_MISS ? 1.0 : 0.0;
         var[0] = *value;
         *nvar = 1;
@@ -928,6 +1033,7 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
             }
         }
     double F = 1.0;
+    double cfac[MAXSET], *cf = NULL;
     if (p->mode == 1) {
         double o[3], n[3], L[9];
         int near;
@@ -935,21 +1041,36 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
         for (int q = 0; q < 9; ++q) L[q] = p->light[q];
         F = front_fraction(o, n, L, &near);
         if (near) excluded = 1;
+    } else if (p->mode == 2) {
+        /* Solid-angle definition: the visible fraction of Omega_A(x_i) is
+         * F_Omega - B_i with F_Omega = Omega_front / Omega_A the part of the
+         * emitter's solid angle in front of the tangent plane (the analogue
+         * of F_i), and B_i weighted by C_Omega(x_i, z_j). */
+        double o[3], n[3], L[9], all, front;
+        int near;
+        receiver_point(c, i, o, n);
+        for (int q = 0; q < 9; ++q) L[q] = p->light[q];
+        emitter_solid_angles(o, n, L, &all, &front, &near);
+        if (near) excluded = 1;
+        F = all > 0.0 ? front / all : 0.0;
+        for (int b = 0; b < m; ++b)
+            cfac[b] = c->hit[t->S[b]] < ORC_SELF ? sa_factor(o, c->z + 3 * t->S[b], L, all) : 0.0;
+        cf = cfac;
     }
     /* Dark-region guard (Sec. 4.4, biased shadows): every sample of the set
      * blocked (an occluder hit, or no visible light sample at all). */
     int dark = 0;
-    if (p->mode == 1 && p->estimator == 1 && p->dark_guard) {
+    if (p->mode != 0 && p->estimator == 1 && p->dark_guard) {
         dark = 1;
         for (int a = 0; a < m; ++a)
             if (c->hit[t->S[a]] == ORC_MISS) dark = 0;
     }
-    double B = combine(c, t, ia, amb_idx, namb, 0u, 1);
+    double B = combine(c, t, ia, amb_idx, namb, 0u, 1, cf);
     *value = dark ? 0.0 : (p->mode == 0 ? 1.0 - B : F - B);
     if (excluded || namb > MAX_AMBIG) return;
     int nv = 1 << namb;
     for (int v = 0; v < nv; ++v) {
-        double Bv = combine(c, t, ia, amb_idx, namb, (unsigned)v, 0);
+        double Bv = combine(c, t, ia, amb_idx, namb, (unsigned)v, 0, cf);
         var[v] = dark ? 0.0 : (p->mode == 0 ? 1.0 - Bv : F - Bv);
     }
     *nvar = (uint8_t)nv;
@@ -1108,6 +1229,39 @@ double orc_shadow_quadrature(const orc_scene *s, const double *o, const double *
         free(cand.ids);
     }
     return vis / ((double)ngrid * ngrid);
+}
+
+/* Shadow_Omega(x) = (1/Omega_A) \int_{Omega_A} V dw (Eq.
+ * reapp-shadow-definition-solid-angle): the midpoint rule on an ngrid^2 grid
+ * over the rectangle with each cell weighted by its solid angle
+ * <n_y, w_{y->x}> dA / |x - y|^2, normalised by the sum of the weights; V = 0
+ * behind the tangent plane, and 0 for a receiver behind the one-sided light. */
+double orc_shadow_sa_quadrature(const orc_scene *s, const double *o, const double *n, const double *light,
+                                uint32_t ign, int32_t ngrid) {
+    double c[3], eu[3], ev[3], nl[3], area, oc[3];
+    light_frame(light, c, eu, ev, nl, &area);
+    sub3(o, c, oc);
+    if (!(dot3(nl, oc) > 0.0)) return 0.0;
+    double vis = 0.0, tot = 0.0;
+#pragma omp parallel reduction(+ : vis, tot)
+    {
+        idlist cand = {0, 0, 0};
+#pragma omp for schedule(dynamic, 4)
+        for (int32_t a = 0; a < ngrid; ++a)
+            for (int32_t b = 0; b < ngrid; ++b) {
+                double ua = (a + 0.5) / ngrid - 0.5, ub = (b + 0.5) / ngrid - 0.5, d[3];
+                for (int q = 0; q < 3; ++q) d[q] = c[q] + ua * eu[q] + ub * ev[q] - o[q];
+                double r2 = dot3(d, d);
+                double wgt = -dot3(nl, d) / sqrt(r2) / r2;
+                tot += wgt;
+                if (!(dot3(n, d) > 0.0)) continue;
+                uint8_t blocked, g;
+                any_one(s, &cand, o, d, 1.0, ign, ORC_MISS, &blocked, &g);
+                if (!blocked) vis += wgt;
+            }
+        free(cand.ids);
+    }
+    return vis / tot;
 }
 
 int32_t orc_num_threads(void) {

@@ -17,7 +17,8 @@
 #define ORC_SELF 0xFFFFFFFEu /* shadow sample below the tangent plane or receiver behind the light */
 
 typedef struct {
-    int32_t mode;       /* 0 ambient occlusion, 1 rectangular-light shadow */
+    int32_t mode;       /* 0 ambient occlusion, 1 rectangular-light shadow (area definition),
+                           2 rectangular-light shadow under the solid-angle definition */
     int32_t estimator;  /* 0 no reuse, 1 biased reuse, 2 unbiased reuse */
     int32_t pattern;    /* 0 sliding window of radius r, 1 fixed group of N pixels */
     int32_t radius;     /* window radius r */
@@ -78,6 +79,11 @@ double orc_density_shadow(const double *o, const double *n, const double *z, con
                           const double *light);
 /* Fraction of the light's area in front of the receiver's tangent plane. */
 double orc_front_fraction(const double *o, const double *n, const double *light);
+/* Solid angle of the whole one-sided light at o (out2[0]) and of its part in
+ * front of the tangent plane (out2[1]); 0 behind the light. */
+void orc_solid_angles(const double *o, const double *n, const double *light, double *out2);
+/* C_Omega(o, z) of the solid-angle MIS estimator. */
+double orc_sa_factor(const double *o, const double *n, const double *z, const double *light);
 
 /* FP64 quadrature references of the AO integral (Eq. ao-hemisphere) and the
  * normalised shadow integral (Eq. shadow-area) at one receiver. */
@@ -85,6 +91,9 @@ double orc_ao_quadrature(const orc_scene *s, const double *o, const double *n, d
                          int32_t nstrata);
 double orc_shadow_quadrature(const orc_scene *s, const double *o, const double *n, const double *light,
                              uint32_t ign, int32_t ngrid);
+/* ... and of the solid-angle shadow (Eq. reapp-shadow-definition-solid-angle). */
+double orc_shadow_sa_quadrature(const orc_scene *s, const double *o, const double *n, const double *light,
+                                uint32_t ign, int32_t ngrid);
 
 uint32_t orc_pcg4d_first(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t *out4);
 int32_t orc_num_threads(void);
