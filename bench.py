@@ -65,6 +65,11 @@ OPS_BOX, OPS_TRI = 26, 59
 # shadow: five dot products (15), a reciprocal, s, two FMAs (a, b), six
 # support compares and two abs, s^2 and the Jacobian ratio (3), a select = 31.
 OPS_DENS = {"ao": 6 + 17, "shadow": 6 + 31}
+OPS_DENS["shadow_sa"] = OPS_DENS["shadow"]
+# solid-angle shadows scatter p/P times g = cos / |x - y'|^2 per (target,
+# candidate) pair: the pair vector (6), two dot products (10), two
+# reciprocals, a reciprocal square root, s, s^2 |w|^2 (2) and three products = 24
+OPS_SA_G = 24
 
 
 def window_reuse_ops(r, mode):
@@ -72,12 +77,16 @@ def window_reuse_ops(r, mode):
     (4r+1)^2 pair densities, the (4r+1)(2r+1) row box sums and (2r+1)^2
     column box sums of 2r adds each, and a reciprocal and product per target."""
     side, tw = 4 * r + 1, 2 * r + 1
-    return side * side * OPS_DENS[mode] + side * tw * 2 * r + tw * tw * 2 * r + tw * tw * 2
+    g = tw * tw * OPS_SA_G if mode == "shadow_sa" else 0
+    return side * side * OPS_DENS[mode] + side * tw * 2 * r + tw * tw * 2 * r + tw * tw * 2 + g
 
 WORKLOADS = {
     "ao_1080p": dict(mode="ao", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2, sample_seed=1),
     "shadow_1080p": dict(mode="shadow", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2,
                          sample_seed=1),
+    # shadows under the solid-angle definition: same records and validation
+    "shadow_sa_1080p": dict(mode="shadow_sa", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2,
+                            sample_seed=1),
     "batched_16": dict(radius=2.0, window_r=3, sample_seed=1),
     "served": dict(radius=2.0, window_r=3, rate=400.0, budget_gib=4.0, slots=8),
 }
@@ -191,7 +200,8 @@ def run_frame(args):
     t0 = time.time()
     scene = w.terrain_scene(cfg["scene_seed"])
     gb = w.render_gbuffer(scene, w.terrain_camera(W, H))
-    light = w.terrain_light() if mode == "shadow" else None
+    light = w.terrain_light() if mode != "ao" else None
+    tmode = "shadow" if mode == "shadow_sa" else mode  # the mode records are traced (and validated) in
     log(f"[bench] inputs {time.time() - t0:.1f}s: {scene.ntris} tris, {W}x{H}, valid {gb.valid.mean():.3f}")
 
     dev = torch.device("cuda:0")
@@ -207,7 +217,7 @@ def run_frame(args):
     out_n = torch.empty((H, W), dtype=torch.float32, device=dev)
     out_b = torch.empty((H, W), dtype=torch.float32, device=dev)
     out_u = torch.empty((H, W), dtype=torch.float32, device=dev)
-    _, _, kind = ocr.sample_rays(dg, mode, light, cfg["sample_seed"], 0)
+    _, _, kind = ocr.sample_rays(dg, tmode, light, cfg["sample_seed"], 0)
     rays = int((kind == 0).sum().item())
     torch.cuda.synchronize()
     log(f"[bench] bvh {info.nnodes} nodes depth {info.depth} built in {info.build_ms:.0f} ms; {rays} traced rays/step")
@@ -219,7 +229,7 @@ def run_frame(args):
             if ev is not None:
                 ev[k].record(stream)
         mark(0)
-        ocr.trace_occluders(bvh, dg, mode, R, light, cfg["sample_seed"], s, occ)
+        ocr.trace_occluders(bvh, dg, tmode, R, light, cfg["sample_seed"], s, occ)
         mark(1)
         if mode == "ao":
             ocr.reuse_ao(None, dg, occ, R, p_none, out_n)
@@ -230,13 +240,14 @@ def run_frame(args):
             mark(4)
             ocr.reuse_ao(None, dg, occ, R, p_u, out_u, ws)
         else:
-            ocr.reuse_shadow(None, dg, occ, light, p_none, out_n)
+            reuse = ocr.reuse_shadow_solid_angle if mode == "shadow_sa" else ocr.reuse_shadow
+            reuse(None, dg, occ, light, p_none, out_n)
             mark(2)
-            ocr.reuse_shadow(None, dg, occ, light, p_b, out_b)
+            reuse(None, dg, occ, light, p_b, out_b)
             mark(3)
-            ocr.validate_pairs(bvh, dg, occ, mode, R, light, p_u, ws)
+            ocr.validate_pairs(bvh, dg, occ, tmode, R, light, p_u, ws)
             mark(4)
-            ocr.reuse_shadow(None, dg, occ, light, p_u, out_u, ws)
+            reuse(None, dg, occ, light, p_u, out_u, ws)
         mark(5)
 
     if args.calibration_copy_mib > 0:
@@ -272,8 +283,8 @@ def run_frame(args):
 
     # work counted by the validation walk for one sample (outside the timed region)
     stats = torch.zeros(5, dtype=torch.int64, device=dev)
-    ocr.trace_occluders(bvh, dg, mode, R, light, cfg["sample_seed"], args.steps - 1, occ)
-    ocr.validate_pairs(bvh, dg, occ, mode, R, light, p_u, ws, stats=stats)
+    ocr.trace_occluders(bvh, dg, tmode, R, light, cfg["sample_seed"], args.steps - 1, occ)
+    ocr.validate_pairs(bvh, dg, occ, tmode, R, light, p_u, ws, stats=stats)
     torch.cuda.synchronize()
     walks, nodes, box_tests, tri_tests, segments = [int(v) for v in stats.cpu().tolist()]
     valid_px = int(gb.valid.sum())
@@ -292,7 +303,7 @@ def run_frame(args):
     reuse_tops = hits * window_reuse_ops(r, mode) / (per["reuse_biased"] * 1e-3) / 1e12
     if dominant == "validate":
         # traversal and densities are VALU-bound: price the useful operations
-        kname = f"ocr::validate_window_kernel<{0 if mode == 'ao' else 1}, false>"
+        kname = f"ocr::validate_window_kernel<{0 if mode == 'ao' else 1}, false>"  # one validation per definition
         traffic = measured_traffic(kname) if args.workload == "ao_1080p" else None
         roof = dict(bound="alu", achieved=round(val_tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
                     frac=round(val_tops / VALU_PEAK_TOPS, 4), traffic=traffic, kernel=kname)
@@ -314,7 +325,8 @@ def run_frame(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: terrain 512x512 cells + 2000 icospheres ({scene.ntris} tris), "
-                               f"{W}x{H}, 1 spp, R={R} m, 7x7 window, no-reuse + biased + unbiased",
+                               f"{W}x{H}, 1 spp, R={R} m, 7x7 window, no-reuse + biased + unbiased"
+                               + (", shadows under the solid-angle definition" if mode == "shadow_sa" else ""),
                    "global_batch": 1, "seq_len": W * H, "parallelism": "single-gpu"},
         "kernels_ms": {k: round(v, 4) for k, v in per.items()},
         "kernels_ms_p50": {k: round(float(np.percentile(v, 50)), 4) for k, v in samples.items()},
@@ -327,7 +339,7 @@ def run_frame(args):
         "reuse_roofline": dict(bound="alu", achieved=round(reuse_tops, 3), peak=round(VALU_PEAK_TOPS, 1),
                                unit="TFLOP/s", frac=round(reuse_tops / VALU_PEAK_TOPS, 4),
                                hbm_gbs=round(reuse_gbs, 1), hbm_frac=round(reuse_gbs / HBM_PEAK_GBS, 4),
-                               kernel=f"ocr::reuse_window_kernel<{0 if mode == 'ao' else 1}, false>",
+                               kernel=f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2}[mode]}, false>",
                                ops_per_candidate=window_reuse_ops(r, mode)),
         "rays_per_step": rays,
         "occluder_hits": hits,
@@ -341,7 +353,7 @@ def run_frame(args):
     }
 
     result["trace_roofline"] = alu_roofline(
-        counted_trace(ocr, torch, bvh, dg, mode, R, light, cfg["sample_seed"], args.steps - 1), per["trace"],
+        counted_trace(ocr, torch, bvh, dg, tmode, R, light, cfg["sample_seed"], args.steps - 1), per["trace"],
         "trace_kernel")
     if args.workload == "ao_1080p":
         result["trace_roofline"]["traffic"] = measured_traffic("ocr::trace_kernel<0>")

@@ -238,6 +238,28 @@ ocr_status ocr_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const o
                             const ocr_rect_light *light, const ocr_reuse_params *params, void *workspace,
                             size_t workspace_bytes, float *out, void *stream);
 
+/* Shadow reuse under the solid-angle definition (the appendix deriving the
+ * occluder-domain form of Eq. reapp-shadow-definition-solid-angle): the
+ * visible fraction of the solid angle Omega_A(x_i) that the light subtends,
+ *   out[i] = F_Omega(x_i) - sum_j C_Omega(x_i, z_j) p_i(j) / P_i(j)
+ * (Eq. reapp-shadow-solid-angle-estimator), with p, P, the validation and
+ * the records exactly as for ocr_reuse_shadow (the light is still sampled
+ * uniformly on its area: trace with OCR_SHADOW), the factor
+ *   C_Omega(x, z) = Area / Omega_A(x) * <n_y', w_{y'->x}> / |x - y'|^2
+ * at the light crossing y' of the ray from x through z (Eq.
+ * reapp-shadow-solid-angle-mis-factor), and F_Omega = Omega_front /
+ * Omega_A, the part of the light's solid angle in front of the receiver's
+ * tangent plane (1 for a receiver facing the whole light; solid angles
+ * exact, by the formula of Van Oosterom and Strackee).  OCR_NOREUSE is the
+ * N = 1 case: F_Omega - C_Omega(x_i, z_i) for a hit.  Biased with dark_guard:
+ * 0 when no sample of S(i) is unblocked.  Background pixels and receivers
+ * not on the light's emitting side get 0.  A single term is clamped below
+ * 2^31 (reached only within ~1e-5 of the light).  Arguments, workspace and
+ * errors as ocr_reuse_shadow. */
+ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                        const ocr_rect_light *light, const ocr_reuse_params *params,
+                                        void *workspace, size_t workspace_bytes, float *out, void *stream);
+
 /* out[i] *= s for n floats (device); turns accumulated sums over M samples
  * into their mean (the final line of App. D / App. H). */
 ocr_status ocr_scale(float *out, int64_t n, float s, void *stream);

@@ -109,7 +109,8 @@ class ServerStats(ctypes.Structure):
 EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders",
            "ocr_trace_occluders_counted", "ocr_sample_rays",
            "ocr_workspace_bytes", "ocr_validate_pairs",
-           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_scale", "ocr_last_error", "ocr_version",
+           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_reuse_shadow_solid_angle", "ocr_scale", "ocr_last_error",
+           "ocr_version",
            "ocr_plan_create", "ocr_plan_launch", "ocr_plan_get_info", "ocr_plan_get_records", "ocr_plan_free",
            "ocr_server_create", "ocr_server_add_scene", "ocr_server_submit", "ocr_server_poll",
            "ocr_server_release", "ocr_server_drain", "ocr_server_get_stats", "ocr_server_now_ms",
@@ -155,6 +156,8 @@ def lib():
     L.ocr_reuse_shadow.restype = i32
     L.ocr_reuse_shadow.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), ctypes.POINTER(_Light),
                                    ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
+    L.ocr_reuse_shadow_solid_angle.restype = i32
+    L.ocr_reuse_shadow_solid_angle.argtypes = L.ocr_reuse_shadow.argtypes
     L.ocr_scale.restype = i32
     L.ocr_scale.argtypes = [vp, i64, ctypes.c_float, vp]
     P = ctypes.POINTER
@@ -409,6 +412,23 @@ def reuse_shadow(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluders, light, pa
     return out
 
 
+def reuse_shadow_solid_angle(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluders, light, params: ReuseParams,
+                             out=None, workspace=None, stream=None):
+    """Shadows under the solid-angle definition from OCR_SHADOW records
+    (ocr_reuse_shadow_solid_angle)."""
+    import torch
+    out = out if out is not None else torch.empty((gbuf.height, gbuf.width), dtype=torch.float32,
+                                                  device=gbuf.prim.device)
+    ws, nbytes = _workspace(gbuf, params, workspace)
+    g, o = gbuf.c(), occ.c()
+    ls = light_struct(light)
+    _check(lib().ocr_reuse_shadow_solid_angle(bvh.h if bvh is not None else None, ctypes.byref(g), ctypes.byref(o),
+                                              ctypes.byref(ls), ctypes.byref(params),
+                                              _dptr(ws) if ws is not None else None, nbytes, _dptr(out),
+                                              _stream(stream)))
+    return out
+
+
 def scale(out, s: float, stream=None):
     _check(lib().ocr_scale(_dptr(out), int(out.numel()), float(s), _stream(stream)))
     return out
@@ -417,7 +437,8 @@ def scale(out, s: float, stream=None):
 def render(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, light=None, seed=1, nsamples=1,
            first_sample=0, params: ReuseParams | None = None, stream=None):
     """Mean over `nsamples` samples of the per-sample estimate (trace, then
-    reuse accumulating into one buffer, then one scale)."""
+    reuse accumulating into one buffer, then one scale); mode "ao", "shadow"
+    or "shadow_sa" (shadows under the solid-angle definition)."""
     import torch
     params = params or reuse_params()
     occ = Occluders.empty(gbuf.height, gbuf.width, gbuf.prim.device)
@@ -426,12 +447,16 @@ def render(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, light=None, 
     need = workspace_bytes(gbuf.width, gbuf.height, params)
     if need:
         ws = torch.empty(need, dtype=torch.uint8, device=gbuf.prim.device)
+    solid_angle = mode == "shadow_sa"
     for s in range(nsamples):
-        trace_occluders(bvh, gbuf, mode, ao_radius, light, seed, first_sample + s, occ, stream)
+        trace_occluders(bvh, gbuf, "shadow" if solid_angle else mode, ao_radius, light, seed, first_sample + s, occ,
+                        stream)
         p = ReuseParams(params.pattern, params.radius, params.group_n, params.estimator, params.dark_guard,
                         0 if s == 0 else 1, 0)
         if mode in ("ao", OCR_AO):
             out = reuse_ao(bvh, gbuf, occ, ao_radius, p, out, ws, stream)
+        elif solid_angle:
+            out = reuse_shadow_solid_angle(bvh, gbuf, occ, light, p, out, ws, stream)
         else:
             out = reuse_shadow(bvh, gbuf, occ, light, p, out, ws, stream)
     if nsamples > 1:

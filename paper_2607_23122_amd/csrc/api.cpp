@@ -125,7 +125,9 @@ ocr_status reuse_common(const ocr_bvh *bvh, const ocr_gbuffer *g, const ocr_occl
     GBufView gv = view(g);
     hipError_t e;
     if (p->estimator == OCR_UNBIASED && !p->validated) {
-        e = launch_validate(bvh->dev, gv, ov, mode, R, L, *p, (uint32_t *)ws, nullptr, s);
+        // both shadow definitions validate the same pairs (same densities)
+        e = launch_validate(bvh->dev, gv, ov, mode == kShadowSA ? OCR_SHADOW : mode, R, L, *p, (uint32_t *)ws,
+                            nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "validation launch");
     }
     e = launch_reuse(gv, ov, mode, R, L, *p, (const uint32_t *)ws, out, s);
@@ -326,6 +328,15 @@ ocr_status ocr_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const o
     ocr_status st = make_light(light, L);
     if (st) return st;
     return reuse_common(bvh, gbuf, occ, OCR_SHADOW, 1.0f, L, params, workspace, workspace_bytes, out, stream);
+}
+
+ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                        const ocr_rect_light *light, const ocr_reuse_params *params,
+                                        void *workspace, size_t workspace_bytes, float *out, void *stream) {
+    LightF L;
+    ocr_status st = make_light(light, L);
+    if (st) return st;
+    return reuse_common(bvh, gbuf, occ, kShadowSA, 1.0f, L, params, workspace, workspace_bytes, out, stream);
 }
 
 ocr_status ocr_scale(float *out, int64_t n, float s, void *stream) {

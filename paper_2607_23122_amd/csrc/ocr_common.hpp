@@ -54,6 +54,10 @@ struct DeviceBVH {
 };
 
 // Light in the form the kernels use (FP32).
+// Internal mode of the reuse kernels: rectangular-light shadows under the
+// solid-angle definition (records, densities and validation as OCR_SHADOW).
+constexpr int kShadowSA = 2;
+
 struct LightF {
     float c[3], eu[3], ev[3];
     float nl[3];       // unit normal of the emitting side

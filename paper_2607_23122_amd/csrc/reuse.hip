@@ -1,7 +1,8 @@
 // Occluder-domain MIS reuse kernels (Sec. 4.2-4.4; steps 2-3 of App. D /
 // App. H): the sliding window (one 16x16 target tile per block; the tile
 // body is shared with the batched schedule), fixed groups, no reuse, and the
-// sample-mean scale.
+// sample-mean scale; each for AO, area-definition shadows and shadows under
+// the solid-angle definition (kShadowSA).
 //
 // Fixed groups (N = 1, 2, 4, 8): one lane per pixel; each receiver lane
 // evaluates its densities for the N candidates of its group into LDS and each
@@ -11,6 +12,7 @@
 #include "density.hpp"
 #include "ocr_common.hpp"
 #include "reuse_tile.hpp"
+#include "solid_angle.hpp"
 
 namespace ocr {
 
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
         }
     }
     RecvShadow rk = {0.f, 0.f, 0.f};
-    if (MODE == OCR_SHADOW && valid) rk = recv_shadow(o, L);
+    if (MODE != OCR_AO && valid) rk = recv_shadow(o, L);
     s_sh[0][tid] = rk.hk;
     s_sh[1][tid] = rk.ak;
     s_sh[2][tid] = rk.bk;
@@ -132,25 +134,65 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
             P += s_p[kt][m];
         }
         const float pij = s_p[tid][m];
-        if (pij > 0.0f && P > 0.0f) B += pij * __builtin_amdgcn_rcpf(P);
+        if (pij > 0.0f && P > 0.0f) {
+            float term = pij * __builtin_amdgcn_rcpf(P);
+            if (MODE == kShadowSA) {
+                // times g_ij of this target and candidate m
+                const float oj[3] = {s_o[0][jt], s_o[1][jt], s_o[2][jt]};
+                const float dzj[3] = {s_dz[0][jt], s_dz[1][jt], s_dz[2][jt]};
+                float w[3];
+                rel_vec(oj, o, dzj, w);
+                term *= sa_pair_g(w, rk.hk, L);
+            }
+            B += term;
+        }
     }
     float F = 1.0f;
     bool dark = false;
-    if (MODE == OCR_SHADOW && valid) {
-        F = front_fraction(o, n, L);
+    if (MODE != OCR_AO && valid) {
+        if (MODE == kShadowSA) {
+            F = sa_estimate(o, n, L, B);
+            B = 0.0f;
+        } else {
+            F = front_fraction(o, n, L);
+        }
         dark = dark_guard && misses == 0;
     }
     out[gi] = finish(MODE, valid, B, F, dark, accumulate ? out[gi] : 0.0f, accumulate);
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView occ, int accumulate, float *out) {
+__global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView occ, LightF L, int accumulate,
+                                                          float *out) {
     const int64_t gi = (int64_t)blockIdx.x * kRBlock + threadIdx.x;
     if (gi >= (int64_t)g.w * g.h) return;
     const bool valid = g.prim[gi] != OCR_HIT_MISS;
     float v;
-    if (MODE == OCR_AO) v = (!valid || occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
-    else v = (valid && occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
+    if (MODE == OCR_AO) {
+        v = (!valid || occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
+    } else if (MODE == OCR_SHADOW) {
+        v = (valid && occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
+    } else {
+        // solid-angle definition, S(i) = {i}: F_Omega - C_Omega(x_i, z_i) for
+        // a hit whose own density is positive (the ratio p/p is 1)
+        v = 0.0f;
+        if (valid) {
+            float x[3], n[3], o[3];
+            ld3(g.pos, gi, x);
+            ld3(g.nrm, gi, n);
+            offset_point(x, n, o);
+            float Bg = 0.0f;
+            const uint32_t hit = occ.hit[gi];
+            if (hit < OCR_HIT_SELF) {
+                float dz[3], nz[3];
+                ld3(occ.dz, gi, dz);
+                ld3(occ.nz, gi, nz);
+                const RecvShadow rk = recv_shadow(o, L);
+                if (dens_shadow(dz, n, rk, nz, L) > 0.0f) Bg = sa_pair_g(dz, rk.hk, L);
+            }
+            v = sa_estimate(o, n, L, Bg);
+        }
+    }
     out[gi] = accumulate ? out[gi] + v : v;
 }
 
@@ -208,25 +250,36 @@ hipError_t launch_reuse(const GBufView &g, const OccView &occ, int mode, float R
     if (p.estimator == OCR_NOREUSE) {
         int64_t n = (int64_t)g.w * g.h;
         dim3 grid((unsigned)((n + kRBlock - 1) / kRBlock)), block(kRBlock);
-        if (mode == OCR_AO) hipLaunchKernelGGL(noreuse_kernel<OCR_AO>, grid, block, 0, st, g, occ, q.accumulate, out);
-        else hipLaunchKernelGGL(noreuse_kernel<OCR_SHADOW>, grid, block, 0, st, g, occ, q.accumulate, out);
+        if (mode == OCR_AO)
+            hipLaunchKernelGGL(noreuse_kernel<OCR_AO>, grid, block, 0, st, g, occ, L, q.accumulate, out);
+        else if (mode == OCR_SHADOW)
+            hipLaunchKernelGGL(noreuse_kernel<OCR_SHADOW>, grid, block, 0, st, g, occ, L, q.accumulate, out);
+        else
+            hipLaunchKernelGGL(noreuse_kernel<kShadowSA>, grid, block, 0, st, g, occ, L, q.accumulate, out);
     } else if (p.pattern == OCR_WINDOW) {
         if (mode == OCR_AO) {
             hipError_t e = unb ? launch_win<OCR_AO, true>(g, occ, R2, L, bits, words, q, out, st)
                                : launch_win<OCR_AO, false>(g, occ, R2, L, bits, words, q, out, st);
             if (e != hipSuccess) return e;
-        } else {
+        } else if (mode == OCR_SHADOW) {
             hipError_t e = unb ? launch_win<OCR_SHADOW, true>(g, occ, R2, L, bits, words, q, out, st)
                                : launch_win<OCR_SHADOW, false>(g, occ, R2, L, bits, words, q, out, st);
+            if (e != hipSuccess) return e;
+        } else {
+            hipError_t e = unb ? launch_win<kShadowSA, true>(g, occ, R2, L, bits, words, q, out, st)
+                               : launch_win<kShadowSA, false>(g, occ, R2, L, bits, words, q, out, st);
             if (e != hipSuccess) return e;
         }
     } else {
         if (mode == OCR_AO) {
             if (unb) launch_grp<OCR_AO, true>(g, occ, R2, L, bits, words, q, out, st);
             else launch_grp<OCR_AO, false>(g, occ, R2, L, bits, words, q, out, st);
-        } else {
+        } else if (mode == OCR_SHADOW) {
             if (unb) launch_grp<OCR_SHADOW, true>(g, occ, R2, L, bits, words, q, out, st);
             else launch_grp<OCR_SHADOW, false>(g, occ, R2, L, bits, words, q, out, st);
+        } else {
+            if (unb) launch_grp<kShadowSA, true>(g, occ, R2, L, bits, words, q, out, st);
+            else launch_grp<kShadowSA, false>(g, occ, R2, L, bits, words, q, out, st);
         }
     }
     return hipGetLastError();

@@ -19,6 +19,7 @@
 #pragma once
 #include "density.hpp"
 #include "ocr_common.hpp"
+#include "solid_angle.hpp"
 
 namespace ocr {
 
@@ -65,13 +66,24 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     l.B_off = lds_take(off, sizeof(unsigned long long) * kWTX * kWTY);
     l.o_off = lds_take(off, sizeof(float) * 3 * l.cells);
     l.n_off = lds_take(off, sizeof(float) * 3 * l.cells);
-    l.sh_off = lds_take(off, mode == OCR_SHADOW ? sizeof(float) * 3 * l.cells : 0);
+    l.sh_off = lds_take(off, mode != OCR_AO ? sizeof(float) * 3 * l.cells : 0);
     l.valid_off = lds_take(off, l.cells);
     l.miss_off = lds_take(off, l.cells);
     l.list_off = lds_take(off, 4 * sizeof(int) + sizeof(uint16_t) * l.cells);
     l.wave_off = lds_take(off, sizeof(float) * (kRBlock / 64) * (l.dens + l.hsum));
     l.total = off;
     return l;
+}
+
+// The scattered term of target cell kc under the solid-angle definition:
+// p_i(j) / P_i(j) times g_ij, clamped below 2^31 so that the 32.32 fixed-point
+// sum cannot overflow (g reaches that size only within ~1e-5 of the light).
+__device__ inline float sa_term(float ratio, const float *s_o, const float *s_sh, int CELLS, int kc,
+                                const float oj[3], const float dzj[3], const LightF &L) {
+    const float oi[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
+    float w[3];
+    rel_vec(oj, oi, dzj, w);
+    return fminf(ratio * sa_pair_g(w, s_sh[kc], L), 0x1p31f);
 }
 
 // One kWTX x kWTY target tile (tx, ty) of the sliding-window estimator; every
@@ -122,7 +134,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
             s_o[a * CELLS + c] = o[a];
             s_n[a * CELLS + c] = n[a];
         }
-        if (MODE == OCR_SHADOW) {
+        if (MODE != OCR_AO) {
             RecvShadow rk = {0.f, 0.f, 0.f};
             if (valid) rk = recv_shadow(o, L);
             s_sh[c] = rk.hk;
@@ -163,7 +175,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         // runs every pass so that the count of positive densities is uniform.
         // Shadow candidates have a few positive densities at most (the light
         // subtends a narrow cone); AO candidates most often have dozens.
-        constexpr bool kSparsePath = MODE == OCR_SHADOW;
+        constexpr bool kSparsePath = MODE != OCR_AO;
         int npos = 0;
         int *e_code = reinterpret_cast<int *>(w_h);  // positive entries, q order
         float *e_p = w_h + kSparse;
@@ -238,9 +250,13 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                     if (abs(ym - my_y) <= R && abs(xm - my_x) <= R) h += pv;
                 }
                 P += h;
-                if (tgt)
+                if (tgt) {
+                    float term = my_p * __builtin_amdgcn_rcpf(P);
+                    if (MODE == kShadowSA)
+                        term = sa_term(term, s_o, s_sh, CELLS, __mul24(ky0 + my_y, RW) + (kx0 + my_x), oj, dzj, L);
                     atomicAdd(&s_B[(ky0 + my_y - R) * TX + (kx0 + my_x - R)],
-                              (unsigned long long)rintf((my_p * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
+                              (unsigned long long)rintf(term * 4294967296.0f));
+                }
             }
         } else {
             // (2) row box sums H[row][t] = sum_{e < 2R+1} p(row, t + e), t < ntx
@@ -262,9 +278,13 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
 #pragma unroll 4
                 for (int e = 0; e < TW; ++e) P += ph[__mul24(e, TW)];
                 const float pij = w_dens[__mul24(r2 + R, SIDE) + (t2 + R)];
-                if (pij > 0.0f && P > 0.0f)
+                if (pij > 0.0f && P > 0.0f) {
+                    float term = pij * __builtin_amdgcn_rcpf(P);
+                    if (MODE == kShadowSA)
+                        term = sa_term(term, s_o, s_sh, CELLS, __mul24(ty0 + r2, RW) + (tx0 + t2), oj, dzj, L);
                     atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],
-                              (unsigned long long)rintf((pij * __builtin_amdgcn_rcpf(P)) * 4294967296.0f));
+                              (unsigned long long)rintf(term * 4294967296.0f));
+                }
             }
         }
         wave_sync();
@@ -278,13 +298,20 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         if (px >= g.w || py >= g.h) continue;
         const int c = __mul24(iy + R, RW) + (ix + R);
         const bool valid = s_valid[c];
-        const float B = (float)((double)s_B[t] * 0x1p-32);
+        float B = (float)((double)s_B[t] * 0x1p-32);
         float F = 1.0f;
         bool dark = false;
-        if (MODE == OCR_SHADOW && valid) {
+        if (MODE != OCR_AO && valid) {
             float o[3] = {s_o[c], s_o[CELLS + c], s_o[2 * CELLS + c]};
             float n[3] = {s_n[c], s_n[CELLS + c], s_n[2 * CELLS + c]};
-            F = front_fraction(o, n, L);
+            if (MODE == kShadowSA) {
+                // F_Omega - (Area / Omega_A) B, as F - B below
+                const float v = sa_estimate(o, n, L, B);
+                F = v;
+                B = 0.0f;
+            } else {
+                F = front_fraction(o, n, L);
+            }
             if (dark_guard) {
                 int misses = 0;
                 for (int dy = -R; dy <= R; ++dy)
