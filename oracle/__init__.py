@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
 
 
 MODES = {"ao": 0, "shadow": 1, "shadow_sa": 2}
-ESTIMATORS = {"none": 0, "biased": 1, "unbiased": 2}
+ESTIMATORS = {"none": 0, "biased": 1, "unbiased": 2, "filter": 3, "light": 4}
 PATTERNS = {"window": 0, "group": 1}
 
 

@@ -21,6 +21,10 @@
  *     with the dark-region guard of Sec. 4.4;
  *   - accumulation over samples (final line of both algorithms);
  *   - FP64 quadrature references of Eqs. ao-hemisphere and shadow-area;
+ *   - the paper's simple reuse baselines of Sec. 6: final-value filtering
+ *     (Filter (N) for AO; for shadows light-sample reuse without validation,
+ *     Light (N), which the paper notes reduces to the same average) and
+ *     light-sample reuse with visibility re-evaluation (Light (NU));
  *   - shadows under the solid-angle definition (App. on that definition:
  *     Eq. reapp-shadow-definition-solid-angle, the MIS estimator of Eq.
  *     reapp-shadow-solid-angle-estimator with the factor C_Omega of Eq.
@@ -956,7 +960,74 @@ typedef struct {
     double *P;      /* m x m: P[a*m + b] = density of candidate S[b] at receiver S[a] */
     double *Ppass;
     int *amb;
+    idlist cand;    /* tracer scratch (light-sample reuse) */
 } target_buf;
+
+/* Final-value filtering (Sec. 6, Filter (N); for shadows also Light (N),
+ * light-sample reuse without visibility validation, which reduces to the
+ * same average): the mean over the valid pixels j of S(i) of their
+ * one-sample no-reuse estimates [the ray or segment of j is free]. */
+static double eval_filter(const reuse_ctx *c, target_buf *t, int ix, int iy) {
+    t->m = reuse_set(c->p, c->W, c->H, c->prim, ix, iy, t->S);
+    double acc = 0.0;
+    for (int a = 0; a < t->m; ++a) acc += c->hit[t->S[a]] == ORC_MISS ? 1.0 : 0.0;
+    return acc / t->m;
+}
+
+/* Light-sample reuse with visibility re-evaluation (Sec. 6, Light (NU)):
+ * target i re-traces the light sample y_j of every pixel j of S(i),
+ *   Shadow_i = (1/|S(i)|) sum_j V(x_i, y_j),
+ * unbiased because every y_j is uniform on the light independently of x_i.
+ * V = 0 for a y_j behind the tangent plane of x_i or an x_i behind the
+ * light (the FP32 tests of the sample specification, so that both sides
+ * decide them identically), else 1 when the segment o_i -> y_j is free over
+ * t in (0, 1), ignoring x_i's own triangle.  Grazing traces make the pair
+ * ambiguous: up to three are enumerated, more make the target not
+ * comparable. */
+static void eval_light_reuse(const reuse_ctx *c, target_buf *t, int ix, int iy, double *value, uint8_t *nvar,
+                             double *var) {
+    const orc_params *p = c->p;
+    int64_t i = (int64_t)iy * c->W + ix;
+    t->m = reuse_set(p, c->W, c->H, c->prim, ix, iy, t->S);
+    float o[3];
+    const float *n = c->nrm + 3 * i, *L = p->light;
+    offset_point(c->pos + 3 * i, n, o);
+    uint32_t sd = seed32(p->seed);
+    float nl[3] = {L[4] * L[8] - L[5] * L[7], L[5] * L[6] - L[3] * L[8], L[3] * L[7] - L[4] * L[6]};
+    float lit = fmaf(nl[2], o[2] - L[2], fmaf(nl[1], o[1] - L[1], nl[0] * (o[0] - L[0])));
+    int vis = 0, namb = 0, amb_vis[MAX_AMBIG];
+    for (int a = 0; a < t->m; ++a) {
+        int64_t j = t->S[a];
+        float y[3], dir[3];
+        light_point((uint32_t)(j % c->W), (uint32_t)(j / c->W), p->sample, sd, L, y);
+        for (int q = 0; q < 3; ++q) dir[q] = y[q] - o[q];
+        float front = fmaf(n[2], dir[2], fmaf(n[1], dir[1], n[0] * dir[0]));
+        if (!(front > 0.0f) || !(lit > 0.0f)) continue;
+        double od[3], dd[3];
+        f2d(o, od);
+        f2d(dir, dd);
+        uint8_t blocked, g;
+        any_one(c->s, &t->cand, od, dd, 1.0, c->prim[i], ORC_MISS, &blocked, &g);
+        if (!blocked) ++vis;
+        if (g) {
+            if (namb < MAX_AMBIG) amb_vis[namb] = !blocked;
+            ++namb;
+        }
+    }
+    *value = (double)vis / t->m;
+    if (namb > MAX_AMBIG) {
+        *nvar = 0;
+        return;
+    }
+    int nv = 1 << namb;
+    for (int v = 0; v < nv; ++v) {
+        int vv = vis;
+        for (int q = 0; q < namb; ++q)
+            if ((v >> q) & 1) vv += amb_vis[q] ? -1 : 1;
+        var[v] = (double)vv / t->m;
+    }
+    *nvar = (uint8_t)nv;
+}
 
 static double combine(const reuse_ctx *c, const target_buf *t, int ia, const int *amb_idx, int namb,
                       unsigned mask, int use_fp64, const double *cfac) {
@@ -998,6 +1069,16 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
         *value = p->mode == 0 ? 1.0 : 0.0;
         var[0] = *value;
         *nvar = 1;
+        return;
+    }
+    if (p->estimator == 3) {
+        *value = eval_filter(c, t, ix, iy);
+        var[0] = *value;
+        *nvar = 1;
+        return;
+    }
+    if (p->estimator == 4) {
+        eval_light_reuse(c, t, ix, iy, value, nvar, var);
         return;
     }
     if (p->estimator == 0 && p->mode != 2) {
@@ -1118,6 +1199,9 @@ void orc_reuse(const orc_scene *s, int32_t W, int32_t H, const float *pos, const
         t.P = (double *)malloc(sizeof(double) * MAXSET * MAXSET);
         t.Ppass = (double *)malloc(sizeof(double) * MAXSET * MAXSET);
         t.amb = (int *)malloc(sizeof(int) * MAXSET * MAXSET);
+        t.cand.ids = NULL;
+        t.cand.n = 0;
+        t.cand.cap = 0;
 #pragma omp for schedule(dynamic, 32)
         for (int64_t q = 0; q < n; ++q) {
             int ix = x0 + (int)(q % w), iy = y0 + (int)(q / w);
@@ -1127,6 +1211,7 @@ void orc_reuse(const orc_scene *s, int32_t W, int32_t H, const float *pos, const
         free(t.P);
         free(t.Ppass);
         free(t.amb);
+        free(t.cand.ids);
     }
     free(c.occ);
 }

@@ -19,7 +19,8 @@
 typedef struct {
     int32_t mode;       /* 0 ambient occlusion, 1 rectangular-light shadow (area definition),
                            2 rectangular-light shadow under the solid-angle definition */
-    int32_t estimator;  /* 0 no reuse, 1 biased reuse, 2 unbiased reuse */
+    int32_t estimator;  /* 0 no reuse, 1 biased reuse, 2 unbiased reuse, 3 final-value filtering
+                           (Filter (N) / Light (N)), 4 light-sample reuse re-traced (Light (NU), shadows) */
     int32_t pattern;    /* 0 sliding window of radius r, 1 fixed group of N pixels */
     int32_t radius;     /* window radius r */
     int32_t group_n;    /* group size N in {1,2,4,8} */
