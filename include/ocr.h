@@ -260,6 +260,35 @@ ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *g
                                         const ocr_rect_light *light, const ocr_reuse_params *params,
                                         void *workspace, size_t workspace_bytes, float *out, void *stream);
 
+/* The paper's simple reuse baselines (Sec. 6), for quality comparisons.
+ *
+ * Final-value filtering (Filter (N) for AO; for shadows also Light (N),
+ * light-sample reuse without visibility validation, which reduces to the same
+ * average): out[i] = the mean of in[j] over the valid pixels j of S(i), the
+ * window of radius params->radius or the group of params->group_n
+ * (params->pattern; the estimator field is checked but unused); background
+ * pixels keep in[i].  in: device float[h][w], typically the OCR_NOREUSE
+ * estimate of ocr_reuse_ao / ocr_reuse_shadow; out: device float[h][w],
+ * must not alias in (params->accumulate: out += the value).  Async on
+ * `stream`.  Errors: OCR_ERR_INVALID_ARG (bad G-buffer or params, NULL or
+ * aliased buffers), OCR_ERR_HIP. */
+ocr_status ocr_filter_values(const ocr_gbuffer *gbuf, const ocr_reuse_params *params, const float *in, float *out,
+                             void *stream);
+
+/* Light-sample reuse with visibility re-evaluation (Light (NU), Sec. 6):
+ * target i re-traces the light sample y_j (the sample of ocr_trace_occluders
+ * with this seed and sample index) of every valid pixel j of S(i):
+ *   out[i] = (1/|S(i)|) sum_j V(x_i, y_j),
+ * unbiased because every y_j is uniform on the light.  V = 0 for a y_j behind
+ * the tangent plane of x_i or an x_i behind the light (the sampler's FP32
+ * tests), else 1 when the segment o_i -> y_j is free over t in (0, 1).  Costs
+ * |S(i)| segments per pixel.  Background pixels get 0 (accumulate: += ).
+ * Async on `stream`.  Errors: OCR_ERR_INVALID_ARG (NULL bvh or out, bad
+ * G-buffer, params or light), OCR_ERR_HIP. */
+ocr_status ocr_light_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_rect_light *light,
+                                  uint64_t seed, uint32_t sample, const ocr_reuse_params *params, float *out,
+                                  void *stream);
+
 /* out[i] *= s for n floats (device); turns accumulated sums over M samples
  * into their mean (the final line of App. D / App. H). */
 ocr_status ocr_scale(float *out, int64_t n, float s, void *stream);

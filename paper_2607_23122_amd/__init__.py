@@ -109,7 +109,8 @@ class ServerStats(ctypes.Structure):
 EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders",
            "ocr_trace_occluders_counted", "ocr_sample_rays",
            "ocr_workspace_bytes", "ocr_validate_pairs",
-           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_reuse_shadow_solid_angle", "ocr_scale", "ocr_last_error",
+           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_reuse_shadow_solid_angle", "ocr_filter_values",
+           "ocr_light_reuse_shadow", "ocr_scale", "ocr_last_error",
            "ocr_version",
            "ocr_plan_create", "ocr_plan_launch", "ocr_plan_get_info", "ocr_plan_get_records", "ocr_plan_free",
            "ocr_server_create", "ocr_server_add_scene", "ocr_server_submit", "ocr_server_poll",
@@ -158,6 +159,11 @@ def lib():
                                    ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
     L.ocr_reuse_shadow_solid_angle.restype = i32
     L.ocr_reuse_shadow_solid_angle.argtypes = L.ocr_reuse_shadow.argtypes
+    L.ocr_filter_values.restype = i32
+    L.ocr_filter_values.argtypes = [ctypes.POINTER(_GBuffer), ctypes.POINTER(ReuseParams), vp, vp, vp]
+    L.ocr_light_reuse_shadow.restype = i32
+    L.ocr_light_reuse_shadow.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Light), ctypes.c_uint64,
+                                         ctypes.c_uint32, ctypes.POINTER(ReuseParams), vp, vp]
     L.ocr_scale.restype = i32
     L.ocr_scale.argtypes = [vp, i64, ctypes.c_float, vp]
     P = ctypes.POINTER
@@ -426,6 +432,31 @@ def reuse_shadow_solid_angle(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluder
                                               ctypes.byref(ls), ctypes.byref(params),
                                               _dptr(ws) if ws is not None else None, nbytes, _dptr(out),
                                               _stream(stream)))
+    return out
+
+
+def filter_values(gbuf: DeviceGBuffer, params: ReuseParams, inp, out=None, stream=None):
+    """Final-value filtering (the paper's Filter (N) / Light (N) baseline):
+    the mean of `inp` over each target's set (ocr_filter_values)."""
+    import torch
+    out = out if out is not None else torch.empty_like(inp)
+    g = gbuf.c()
+    _check(lib().ocr_filter_values(ctypes.byref(g), ctypes.byref(params), _dptr(inp), _dptr(out),
+                                   _stream(stream)))
+    return out
+
+
+def light_reuse_shadow(bvh: BVH, gbuf: DeviceGBuffer, light, seed: int, sample: int, params: ReuseParams, out=None,
+                       stream=None):
+    """Light-sample reuse with visibility re-evaluation (the paper's Light (NU)
+    baseline, ocr_light_reuse_shadow)."""
+    import torch
+    out = out if out is not None else torch.empty((gbuf.height, gbuf.width), dtype=torch.float32,
+                                                  device=gbuf.prim.device)
+    g = gbuf.c()
+    ls = light_struct(light)
+    _check(lib().ocr_light_reuse_shadow(bvh.h, ctypes.byref(g), ctypes.byref(ls), int(seed), int(sample),
+                                        ctypes.byref(params), _dptr(out), _stream(stream)))
     return out
 
 

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libocr.so")
-SOURCES = ["api.cpp", "bvh_build.cpp", "trace.hip", "reuse.hip", "batch.hip", "plan.cpp", "server.cpp"]
+SOURCES = ["api.cpp", "bvh_build.cpp", "trace.hip", "reuse.hip", "baselines.hip", "batch.hip", "plan.cpp",
+           "server.cpp"]
 ARCH = "gfx950"
 
 

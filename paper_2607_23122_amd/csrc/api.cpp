@@ -339,6 +339,32 @@ ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *g
     return reuse_common(bvh, gbuf, occ, kShadowSA, 1.0f, L, params, workspace, workspace_bytes, out, stream);
 }
 
+ocr_status ocr_filter_values(const ocr_gbuffer *gbuf, const ocr_reuse_params *params, const float *in, float *out,
+                             void *stream) {
+    ocr_status st = check_gbuf(gbuf);
+    if (st) return st;
+    if ((st = check_params(params))) return st;
+    if (!in || !out) return fail(OCR_ERR_INVALID_ARG, "in or out is NULL");
+    if (in == out) return fail(OCR_ERR_INVALID_ARG, "out must not alias in");
+    hipError_t e = launch_filter(view(gbuf), *params, in, out, (hipStream_t)stream);
+    return e == hipSuccess ? OCR_OK : hip_fail(e, "filter launch");
+}
+
+ocr_status ocr_light_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_rect_light *light,
+                                  uint64_t seed, uint32_t sample, const ocr_reuse_params *params, float *out,
+                                  void *stream) {
+    ocr_status st = check_gbuf(gbuf);
+    if (st) return st;
+    if ((st = check_params(params))) return st;
+    if (!bvh) return fail(OCR_ERR_INVALID_ARG, "bvh is NULL");
+    if (!out) return fail(OCR_ERR_INVALID_ARG, "out is NULL");
+    LightF L;
+    if ((st = make_light(light, L))) return st;
+    hipError_t e = launch_light_reuse(bvh->dev, view(gbuf), L, fold_seed(seed), sample, *params, out,
+                                      (hipStream_t)stream);
+    return e == hipSuccess ? OCR_OK : hip_fail(e, "light-sample reuse launch");
+}
+
 ocr_status ocr_scale(float *out, int64_t n, float s, void *stream) {
     if (!out || n < 0) return fail(OCR_ERR_INVALID_ARG, "bad scale arguments");
     if (n == 0) return OCR_OK;

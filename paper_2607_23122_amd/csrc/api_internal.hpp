@@ -28,4 +28,9 @@ ocr_status check_effect(int32_t mode, float ao_radius, const ocr_rect_light *lig
 
 inline GBufView view(const ocr_gbuffer *g) { return GBufView{g->pos, g->nrm, g->prim, g->width, g->height}; }
 
+// The simple reuse baselines (baselines.hip).
+hipError_t launch_filter(const GBufView &g, const ocr_reuse_params &p, const float *in, float *out, hipStream_t st);
+hipError_t launch_light_reuse(const DeviceBVH &bvh, const GBufView &g, const LightF &L, uint32_t seed32,
+                              uint32_t sample, const ocr_reuse_params &p, float *out, hipStream_t st);
+
 }  // namespace ocr

@@ -1,0 +1,137 @@
+"""GPU parity of the paper's simple reuse baselines (Sec. 6) against the
+oracle: final-value filtering (Filter (N) / Light (N)) and light-sample reuse
+with visibility re-evaluation (Light (NU)), through the C-ABI.
+
+Filtering consumes the GPU's own no-reuse estimate, so it is compared where
+the oracle's traces agree with the GPU's (targets whose set holds a
+differing grazing trace are counted, not compared); light-sample reuse makes
+its own traces and is compared to within 1e-4 of an admissible oracle value
+(grazing segments enumerated)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from gpu_util import compare_values, log, mismatch_reach, tiles, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ocr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2607_23122_amd as ocr
+    ocr.lib()
+    return ocr
+
+
+class Case:
+    def __init__(self, ocr, name, scene, gb, R, light):
+        log(f"[case] {name}: {gb.width}x{gb.height}, {scene.ntris} tris")
+        self.scene, self.gb, self.R, self.light = scene, gb, R, light
+        self.bvh = ocr.build_bvh(scene.V, scene.F)
+        self.dg = ocr.DeviceGBuffer.from_host(gb)
+        self.osc = oracle.Scene(scene.V, scene.F)
+
+
+@pytest.fixture(scope="module")
+def boxes(ocr):
+    s = w.boxes_scene(1)
+    return Case(ocr, "boxes_256", s, w.render_gbuffer(s, w.boxes_camera()), 1.0, w.terrain_light())
+
+
+@pytest.fixture(scope="module")
+def terrain_small(ocr):
+    s = w.terrain_scene(2)
+    return Case(ocr, "terrain_480x270", s, w.render_gbuffer(s, w.terrain_camera(480, 270)), 2.0, w.terrain_light())
+
+
+def _noreuse(ocr, case, mode, seed):
+    occ = ocr.trace_occluders(case.bvh, case.dg, mode, case.R, case.light if mode == "shadow" else None, seed, 0)
+    p = ocr.reuse_params("window", 0, 0, "none")
+    if mode == "ao":
+        out = ocr.reuse_ao(None, case.dg, occ, case.R, p)
+    else:
+        out = ocr.reuse_shadow(None, case.dg, occ, case.light, p)
+    return occ, out
+
+
+@pytest.mark.parametrize("mode", ["ao", "shadow"])
+@pytest.mark.parametrize("pattern,size", [("window", 2), ("window", 3), ("group", 8), ("group", 2)])
+def test_filter_matches_oracle(ocr, boxes, terrain_small, mode, pattern, size):
+    case = boxes if mode == "ao" else terrain_small
+    log(f"[filter] {mode} {pattern} {size}")
+    occ, nr = _noreuse(ocr, case, mode, seed=4)
+    gpu = to_np(ocr.filter_values(case.dg, ocr.reuse_params(pattern, size, size, "biased"), nr))
+    torch.cuda.synchronize()
+    p = oracle.params(mode, "filter", pattern, radius=size, group_n=size, ao_radius=case.R,
+                      light=case.light if mode == "shadow" else None, seed=4)
+    rec, res = oracle.frame(case.osc, case.gb, p)
+    st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
+    log(f"    {st}")
+    assert st["excluded"] <= 2e-3 * st["targets"]
+
+
+@pytest.mark.parametrize("pattern,size", [("window", 1), ("group", 8), ("group", 1)])
+def test_light_reuse_matches_oracle(ocr, terrain_small, pattern, size):
+    case = terrain_small
+    log(f"[light reuse] {pattern} {size}")
+    params = ocr.reuse_params(pattern, size, size, "unbiased")
+    gpu = to_np(ocr.light_reuse_shadow(case.bvh, case.dg, case.light, 5, 2, params))
+    torch.cuda.synchronize()
+    p = oracle.params("shadow", "light", pattern, radius=size, group_n=size, light=case.light, seed=5, sample=2)
+    _, res = oracle.frame(case.osc, case.gb, p)
+    st = compare_values(gpu, res)
+    log(f"    {st}")
+    assert st["excluded"] <= 1e-3 * st["targets"]
+    if pattern == "group" and size == 1:
+        # Light (1U) is the no-reuse estimator
+        occ = ocr.trace_occluders(case.bvh, case.dg, "shadow", case.R, case.light, 5, 2)
+        nr = to_np(ocr.reuse_shadow(None, case.dg, occ, case.light, ocr.reuse_params("window", 0, 0, "none")))
+        torch.cuda.synchronize()
+        assert (gpu == nr).mean() > 0.9999
+
+
+def test_light_reuse_window3_tiles(ocr, terrain_small):
+    case = terrain_small
+    params = ocr.reuse_params("window", 3, 0, "unbiased")
+    gpu = to_np(ocr.light_reuse_shadow(case.bvh, case.dg, case.light, 1, 0, params))
+    torch.cuda.synchronize()
+    p = oracle.params("shadow", "light", "window", radius=3, light=case.light, seed=1)
+    for t in tiles(case.gb.width, case.gb.height, 4, 32, seed=3):
+        res = oracle.reuse(case.osc, case.gb, p, oracle.Records(case.gb.height, case.gb.width), t)
+        st = compare_values(gpu, res, region=t)
+        log(f"    tile {t}: {st}")
+
+
+def test_light_reuse_1080p_tiles(ocr):
+    s = w.terrain_scene(2)
+    case = Case(ocr, "terrain_1080p", s, w.render_gbuffer(s, w.terrain_camera()), 2.0, w.terrain_light())
+    params = ocr.reuse_params("group", 0, 8, "unbiased")
+    gpu = to_np(ocr.light_reuse_shadow(case.bvh, case.dg, case.light, 1, 0, params))
+    torch.cuda.synchronize()
+    assert np.isfinite(gpu).all() and (gpu >= 0).all() and (gpu <= 1).all()
+    assert (gpu[~case.gb.valid] == 0.0).all()
+    p = oracle.params("shadow", "light", "group", group_n=8, light=case.light, seed=1)
+    for t in tiles(case.gb.width, case.gb.height, 6, 32, seed=21):
+        res = oracle.reuse(case.osc, case.gb, p, oracle.Records(case.gb.height, case.gb.width), t)
+        st = compare_values(gpu, res, region=t)
+        log(f"    tile {t}: {st}")
+
+
+def test_accumulate_and_errors(ocr, boxes):
+    _, nr = _noreuse(ocr, boxes, "ao", seed=2)
+    p = ocr.reuse_params("window", 2, 0, "biased")
+    a = ocr.filter_values(boxes.dg, p, nr)
+    b = a.clone()
+    pa = ocr.reuse_params("window", 2, 0, "biased", accumulate=True)
+    ocr.filter_values(boxes.dg, pa, nr, out=b)
+    torch.cuda.synchronize()
+    assert torch.equal(b, 2 * a)
+    with pytest.raises(ocr.OcrError):
+        ocr.filter_values(boxes.dg, p, nr, out=nr)  # aliasing refused
+    with pytest.raises(ocr.OcrError):
+        ocr.filter_values(boxes.dg, ocr.reuse_params("window", 9, 0, "biased"), nr)
