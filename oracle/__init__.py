@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
                 ("sample", ctypes.c_uint32), ("pad", ctypes.c_int32)]
 
 
-MODES = {"ao": 0, "shadow": 1, "shadow_sa": 2}
+MODES = {"ao": 0, "shadow": 1, "shadow_sa": 2, "di": 3}
 ESTIMATORS = {"none": 0, "biased": 1, "unbiased": 2, "filter": 3, "light": 4}
 PATTERNS = {"window": 0, "group": 1}
 
@@ -100,6 +100,12 @@ def _load():
     lib.orc_shadow_sa_quadrature.restype = f64
     lib.orc_shadow_sa_quadrature.argtypes = [vp, vp, vp, vp, ctypes.c_uint32, i32]
     lib.orc_solid_angles.argtypes = [vp, vp, vp, vp]
+    lib.orc_emitter_irradiance.restype = f64
+    lib.orc_emitter_irradiance.argtypes = [vp, vp, vp]
+    lib.orc_di_factor.restype = f64
+    lib.orc_di_factor.argtypes = [vp, vp, vp, vp]
+    lib.orc_di_quadrature.restype = f64
+    lib.orc_di_quadrature.argtypes = [vp, vp, vp, vp, ctypes.c_uint32, i32]
     lib.orc_sa_factor.restype = f64
     lib.orc_sa_factor.argtypes = [vp, vp, vp, vp]
     lib.orc_pcg4d_first.restype = ctypes.c_uint32
@@ -174,6 +180,14 @@ class Scene:
         n = np.ascontiguousarray(n, np.float64)
         la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
         return float(_load().orc_shadow_quadrature(self.h, _ptr(o), _ptr(n), _ptr(la), int(ign), int(ngrid)))
+
+    def di_quadrature(self, o, n, light, ign=MISS, ngrid=512):
+        """Visible irradiance of the unit-radiance light (direct illumination
+        in units of rho L_e / pi)."""
+        o = np.ascontiguousarray(o, np.float64)
+        n = np.ascontiguousarray(n, np.float64)
+        la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
+        return float(_load().orc_di_quadrature(self.h, _ptr(o), _ptr(n), _ptr(la), int(ign), int(ngrid)))
 
     def shadow_sa_quadrature(self, o, n, light, ign=MISS, ngrid=512):
         o = np.ascontiguousarray(o, np.float64)
@@ -304,3 +318,15 @@ def sa_factor(o, n, z, light) -> float:
     a = [np.ascontiguousarray(v, np.float64) for v in (o, n, z)]
     la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
     return float(_load().orc_sa_factor(*[_ptr(v) for v in a], _ptr(la)))
+
+
+def emitter_irradiance(o, n, light) -> float:
+    a = [np.ascontiguousarray(v, np.float64) for v in (o, n)]
+    la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
+    return float(_load().orc_emitter_irradiance(*[_ptr(v) for v in a], _ptr(la)))
+
+
+def di_factor(o, n, z, light) -> float:
+    a = [np.ascontiguousarray(v, np.float64) for v in (o, n, z)]
+    la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
+    return float(_load().orc_di_factor(*[_ptr(v) for v in a], _ptr(la)))

@@ -25,6 +25,12 @@
  *     (Filter (N) for AO; for shadows light-sample reuse without validation,
  *     Light (N), which the paper notes reduces to the same average) and
  *     light-sample reuse with visibility re-evaluation (Light (NU));
+ *   - occluder-domain direct illumination (App. on it: Eq.
+ *     reapp-di-occluder-domain-compact with the MIS estimator of Eq.
+ *     reapp-di-general-mis-estimator and factor of Eq.
+ *     reapp-di-general-mis-factor) for a Lambertian receiver under a
+ *     uniform one-sided emitter, its unshadowed term from Lambert's polygon
+ *     formula, and its quadrature reference;
  *   - shadows under the solid-angle definition (App. on that definition:
  *     Eq. reapp-shadow-definition-solid-angle, the MIS estimator of Eq.
  *     reapp-shadow-solid-angle-estimator with the factor C_Omega of Eq.
@@ -802,6 +808,92 @@ static double sa_factor(const double o[3], const double z[3], const double *L, d
     return area / omega_all * cos_y / r2;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Direct illumination (mode 3), in units of rho L_e / pi: for a Lambertian  */
+/* receiver of albedo rho under a one-sided emitter of radiance L_e,         */
+/* g(x, y) = (rho / pi) L_e cos+(n_x, w_{x->y}) <n_y, w_{y->x}> / |x - y|^2,   */
+/* so the oracle's quantity is the visible irradiance of a unit-radiance     */
+/* emitter, E_vis(x) = \int_A V cos+_x cos_y / |x - y|^2 dA.                  */
+/* ------------------------------------------------------------------------ */
+
+/* Irradiance at o (normal n) of a unit-radiance convex polygon Q[0..m) lying
+ * in front of the tangent plane, by Lambert's formula:
+ *   E = 1/2 |sum_k theta_k <n, (q_k x q_{k+1}) / |q_k x q_{k+1}|>|,
+ * q_k = Q_k - o, theta_k the angle between q_k and q_{k+1}. */
+static double lambert_polygon(const double o[3], const double n[3], double Q[][3], int m) {
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) {
+        double a[3], b[3], c[3];
+        sub3(Q[k], o, a);
+        sub3(Q[(k + 1) % m], o, b);
+        cross3(a, b, c);
+        double lc = len3(c);
+        if (lc == 0.0) continue;
+        double th = atan2(lc, dot3(a, b));
+        acc += th * dot3(n, c) / lc;
+    }
+    return 0.5 * fabs(acc);
+}
+
+/* U / (rho L_e / pi): the unshadowed term of Eq. reapp-di-unshadowed-term,
+ * the irradiance of the part of the light in front of the tangent plane (0
+ * for a receiver not on the emitting side). */
+static double emitter_irradiance(const double o[3], const double n[3], const double *L, int *near_edge) {
+    double c[3], eu[3], ev[3], nl[3], area;
+    light_frame(L, c, eu, ev, nl, &area);
+    double oc[3];
+    sub3(o, c, oc);
+    double side = dot3(nl, oc);
+    if (near_edge) *near_edge = fabs(side) <= LIGHT_BAND * len3(oc);
+    if (!(side > 0.0)) return 0.0;
+    double P[4][3], Q[8][3];
+    const double su[4] = {-0.5, 0.5, 0.5, -0.5}, sv[4] = {-0.5, -0.5, 0.5, 0.5};
+    for (int k = 0; k < 4; ++k)
+        for (int a = 0; a < 3; ++a) P[k][a] = c[a] + su[k] * eu[a] + sv[k] * ev[a];
+    int m = 0;
+    for (int k = 0; k < 4; ++k) {
+        const double *A = P[k], *B = P[(k + 1) % 4];
+        double da[3], db[3];
+        sub3(A, o, da);
+        sub3(B, o, db);
+        double fa = dot3(n, da), fb = dot3(n, db);
+        if (fa > 0.0) { memcpy(Q[m++], A, sizeof(double) * 3); }
+        if ((fa > 0.0) != (fb > 0.0)) {
+            double t = fa / (fa - fb);
+            for (int a = 0; a < 3; ++a) Q[m][a] = A[a] + t * (B[a] - A[a]);
+            ++m;
+        }
+    }
+    return m >= 3 ? lambert_polygon(o, n, Q, m) : 0.0;
+}
+
+/* C_DI(x, z) / (rho L_e / pi) = Area cos+_x <n_y', w_{y'->x}> / |x - y'|^2 at
+ * the light crossing y' (Eq. reapp-di-general-mis-factor with p_A = 1/Area);
+ * 0 where the crossing does not exist. */
+static double di_factor(const double o[3], const double n[3], const double z[3], const double *L) {
+    double c[3], eu[3], ev[3], nl[3], area;
+    light_frame(L, c, eu, ev, nl, &area);
+    double w[3], co[3];
+    sub3(z, o, w);
+    double nlw = dot3(nl, w);
+    if (!(nlw < 0.0)) return 0.0;
+    sub3(c, o, co);
+    double s = dot3(nl, co) / nlw;
+    double d = len3(w);
+    double cos_x = dot3(n, w) / d;
+    if (!(cos_x > 0.0)) return 0.0;
+    double cos_y = -nlw / d;
+    return area * cos_x * cos_y / (s * s * d * d);
+}
+
+double orc_emitter_irradiance(const double *o, const double *n, const double *light) {
+    return emitter_irradiance(o, n, light, NULL);
+}
+
+double orc_di_factor(const double *o, const double *n, const double *z, const double *light) {
+    return di_factor(o, n, z, light);
+}
+
 void orc_solid_angles(const double *o, const double *n, const double *light, double *out2) {
     emitter_solid_angles(o, n, light, &out2[0], &out2[1], NULL);
 }
@@ -1081,7 +1173,7 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
         eval_light_reuse(c, t, ix, iy, value, nvar, var);
         return;
     }
-    if (p->estimator == 0 && p->mode != 2) {
+    if (p->estimator == 0 && p->mode < 2) {
         /* Eqs. (ao-mc-estimator) and (shadow-mc-estimator), one sample:
          * V = 1 when the ray or segment is free.  (Solid-angle shadows take
          * the general path below with S(i) = {i}.) */
@@ -1136,6 +1228,18 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
         F = all > 0.0 ? front / all : 0.0;
         for (int b = 0; b < m; ++b)
             cfac[b] = c->hit[t->S[b]] < ORC_SELF ? sa_factor(o, c->z + 3 * t->S[b], L, all) : 0.0;
+        cf = cfac;
+    } else if (p->mode == 3) {
+        /* Direct illumination (Eq. reapp-di-general-mis-estimator), in units
+         * of rho L_e / pi: U - sum_j C_DI(x_i, z_j) p_i(j) / P_i(j). */
+        double o[3], n[3], L[9];
+        int near;
+        receiver_point(c, i, o, n);
+        for (int q = 0; q < 9; ++q) L[q] = p->light[q];
+        F = emitter_irradiance(o, n, L, &near);
+        if (near) excluded = 1;
+        for (int b = 0; b < m; ++b)
+            cfac[b] = c->hit[t->S[b]] < ORC_SELF ? di_factor(o, n, c->z + 3 * t->S[b], L) : 0.0;
         cf = cfac;
     }
     /* Dark-region guard (Sec. 4.4, biased shadows): every sample of the set
@@ -1314,6 +1418,38 @@ double orc_shadow_quadrature(const orc_scene *s, const double *o, const double *
         free(cand.ids);
     }
     return vis / ((double)ngrid * ngrid);
+}
+
+/* E_vis(x) = \int_A V cos+_x cos_y / |x - y|^2 dA (Eq. reapp-di-area-compact
+ * in units of rho L_e / pi): midpoint rule on an ngrid^2 grid over the
+ * rectangle; 0 for a receiver behind the one-sided light. */
+double orc_di_quadrature(const orc_scene *s, const double *o, const double *n, const double *light, uint32_t ign,
+                         int32_t ngrid) {
+    double c[3], eu[3], ev[3], nl[3], area, oc[3];
+    light_frame(light, c, eu, ev, nl, &area);
+    sub3(o, c, oc);
+    if (!(dot3(nl, oc) > 0.0)) return 0.0;
+    double vis = 0.0;
+    double dA = area / ((double)ngrid * ngrid);
+#pragma omp parallel reduction(+ : vis)
+    {
+        idlist cand = {0, 0, 0};
+#pragma omp for schedule(dynamic, 4)
+        for (int32_t a = 0; a < ngrid; ++a)
+            for (int32_t b = 0; b < ngrid; ++b) {
+                double ua = (a + 0.5) / ngrid - 0.5, ub = (b + 0.5) / ngrid - 0.5, d[3];
+                for (int q = 0; q < 3; ++q) d[q] = c[q] + ua * eu[q] + ub * ev[q] - o[q];
+                double cx = dot3(n, d);
+                if (!(cx > 0.0)) continue;
+                uint8_t blocked, g;
+                any_one(s, &cand, o, d, 1.0, ign, ORC_MISS, &blocked, &g);
+                if (blocked) continue;
+                double r2 = dot3(d, d);
+                vis += cx * -dot3(nl, d) / (r2 * r2) * dA;
+            }
+        free(cand.ids);
+    }
+    return vis;
 }
 
 /* Shadow_Omega(x) = (1/Omega_A) \int_{Omega_A} V dw (Eq.

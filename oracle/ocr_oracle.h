@@ -18,7 +18,9 @@
 
 typedef struct {
     int32_t mode;       /* 0 ambient occlusion, 1 rectangular-light shadow (area definition),
-                           2 rectangular-light shadow under the solid-angle definition */
+                           2 rectangular-light shadow under the solid-angle definition,
+                           3 direct illumination of a Lambertian receiver, in units of
+                             rho L_e / pi (the visible irradiance of a unit-radiance light) */
     int32_t estimator;  /* 0 no reuse, 1 biased reuse, 2 unbiased reuse, 3 final-value filtering
                            (Filter (N) / Light (N)), 4 light-sample reuse re-traced (Light (NU), shadows) */
     int32_t pattern;    /* 0 sliding window of radius r, 1 fixed group of N pixels */
@@ -85,6 +87,14 @@ double orc_front_fraction(const double *o, const double *n, const double *light)
 void orc_solid_angles(const double *o, const double *n, const double *light, double *out2);
 /* C_Omega(o, z) of the solid-angle MIS estimator. */
 double orc_sa_factor(const double *o, const double *n, const double *z, const double *light);
+/* Irradiance of the unit-radiance light's part in front of the tangent plane
+ * (the unshadowed direct-illumination term in units of rho L_e / pi). */
+double orc_emitter_irradiance(const double *o, const double *n, const double *light);
+/* C_DI(o, z) / (rho L_e / pi) of the direct-illumination MIS estimator. */
+double orc_di_factor(const double *o, const double *n, const double *z, const double *light);
+/* FP64 quadrature of the visible irradiance (direct illumination in units of rho L_e / pi). */
+double orc_di_quadrature(const orc_scene *s, const double *o, const double *n, const double *light, uint32_t ign,
+                         int32_t ngrid);
 
 /* FP64 quadrature references of the AO integral (Eq. ao-hemisphere) and the
  * normalised shadow integral (Eq. shadow-area) at one receiver. */
