@@ -70,6 +70,10 @@ OPS_DENS["shadow_sa"] = OPS_DENS["shadow"]
 # candidate) pair: the pair vector (6), two dot products (10), two
 # reciprocals, a reciprocal square root, s, s^2 |w|^2 (2) and three products = 24
 OPS_SA_G = 24
+# direct illumination adds the receiver cosine: a dot product, a reciprocal
+# square root and two products
+OPS_DI_G = OPS_SA_G + 8
+OPS_DENS["di"] = OPS_DENS["shadow"]
 
 
 def window_reuse_ops(r, mode):
@@ -77,7 +81,7 @@ def window_reuse_ops(r, mode):
     (4r+1)^2 pair densities, the (4r+1)(2r+1) row box sums and (2r+1)^2
     column box sums of 2r adds each, and a reciprocal and product per target."""
     side, tw = 4 * r + 1, 2 * r + 1
-    g = tw * tw * OPS_SA_G if mode == "shadow_sa" else 0
+    g = tw * tw * {"shadow_sa": OPS_SA_G, "di": OPS_DI_G}.get(mode, 0)
     return side * side * OPS_DENS[mode] + side * tw * 2 * r + tw * tw * 2 * r + tw * tw * 2 + g
 
 WORKLOADS = {
@@ -87,6 +91,9 @@ WORKLOADS = {
     # shadows under the solid-angle definition: same records and validation
     "shadow_sa_1080p": dict(mode="shadow_sa", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2,
                             sample_seed=1),
+    # occluder-domain direct illumination (Lambertian receivers, albedo 0.8,
+    # the light at radiance 100): same records and validation
+    "di_1080p": dict(mode="di", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2, sample_seed=1),
     "batched_16": dict(radius=2.0, window_r=3, sample_seed=1),
     "served": dict(radius=2.0, window_r=3, rate=400.0, budget_gib=4.0, slots=8),
 }
@@ -201,7 +208,7 @@ def run_frame(args):
     scene = w.terrain_scene(cfg["scene_seed"])
     gb = w.render_gbuffer(scene, w.terrain_camera(W, H))
     light = w.terrain_light() if mode != "ao" else None
-    tmode = "shadow" if mode == "shadow_sa" else mode  # the mode records are traced (and validated) in
+    tmode = "shadow" if mode in ("shadow_sa", "di") else mode  # the mode records are traced (and validated) in
     log(f"[bench] inputs {time.time() - t0:.1f}s: {scene.ntris} tris, {W}x{H}, valid {gb.valid.mean():.3f}")
 
     dev = torch.device("cuda:0")
@@ -240,7 +247,12 @@ def run_frame(args):
             mark(4)
             ocr.reuse_ao(None, dg, occ, R, p_u, out_u, ws)
         else:
-            reuse = ocr.reuse_shadow_solid_angle if mode == "shadow_sa" else ocr.reuse_shadow
+            if mode == "di":
+                def reuse(b, d, o, lt, p, out, ws=None):
+                    return ocr.reuse_direct_illumination(b, d, o, lt, p, radiance=100.0, albedo=0.8, out=out,
+                                                         workspace=ws)
+            else:
+                reuse = ocr.reuse_shadow_solid_angle if mode == "shadow_sa" else ocr.reuse_shadow
             reuse(None, dg, occ, light, p_none, out_n)
             mark(2)
             reuse(None, dg, occ, light, p_b, out_b)
@@ -326,7 +338,8 @@ def run_frame(args):
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: terrain 512x512 cells + 2000 icospheres ({scene.ntris} tris), "
                                f"{W}x{H}, 1 spp, R={R} m, 7x7 window, no-reuse + biased + unbiased"
-                               + (", shadows under the solid-angle definition" if mode == "shadow_sa" else ""),
+                               + {"shadow_sa": ", shadows under the solid-angle definition",
+                                  "di": ", occluder-domain direct illumination"}.get(mode, ""),
                    "global_batch": 1, "seq_len": W * H, "parallelism": "single-gpu"},
         "kernels_ms": {k: round(v, 4) for k, v in per.items()},
         "kernels_ms_p50": {k: round(float(np.percentile(v, 50)), 4) for k, v in samples.items()},
@@ -339,7 +352,7 @@ def run_frame(args):
         "reuse_roofline": dict(bound="alu", achieved=round(reuse_tops, 3), peak=round(VALU_PEAK_TOPS, 1),
                                unit="TFLOP/s", frac=round(reuse_tops / VALU_PEAK_TOPS, 4),
                                hbm_gbs=round(reuse_gbs, 1), hbm_frac=round(reuse_gbs / HBM_PEAK_GBS, 4),
-                               kernel=f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2}[mode]}, false>",
+                               kernel=f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2, 'di': 3}[mode]}, false>",
                                ops_per_candidate=window_reuse_ops(r, mode)),
         "rays_per_step": rays,
         "occluder_hits": hits,

@@ -260,6 +260,28 @@ ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *g
                                         const ocr_rect_light *light, const ocr_reuse_params *params,
                                         void *workspace, size_t workspace_bytes, float *out, void *stream);
 
+/* Occluder-domain direct illumination (the appendix deriving Eq.
+ * reapp-di-occluder-domain-compact) of a Lambertian receiver of albedo
+ * `albedo` (rho) under the one-sided light emitting radiance `radiance`
+ * (L_e) uniformly:
+ *   out[i] = U(x_i) - sum_j C_DI(x_i, z_j) p_i(j) / P_i(j)
+ * (Eq. reapp-di-general-mis-estimator) with p, P, the validation and the
+ * records exactly as for ocr_reuse_shadow (trace with OCR_SHADOW: the light
+ * is sampled uniformly on its area), C_DI(x, z) = Area g(x, y') and
+ * g(x, y) = (rho / pi) L_e cos+(n_x, w_{x->y}) <n_y, w_{y->x}> / |x - y|^2
+ * (Eq. reapp-di-general-mis-factor with p_A = 1 / Area), and U the unshadowed
+ * term of Eq. reapp-di-unshadowed-term, computed exactly by Lambert's polygon
+ * formula over the light clipped by the receiver's tangent plane.
+ * OCR_NOREUSE is the N = 1 case: U - C_DI(x_i, z_i) for a hit.  Biased with
+ * dark_guard: 0 when no sample of S(i) is unblocked.  Background pixels and
+ * receivers not on the light's emitting side get 0.  Errors as
+ * ocr_reuse_shadow, and OCR_ERR_INVALID_ARG for a negative or non-finite
+ * radiance or albedo. */
+ocr_status ocr_reuse_direct_illumination(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                         const ocr_rect_light *light, float radiance, float albedo,
+                                         const ocr_reuse_params *params, void *workspace, size_t workspace_bytes,
+                                         float *out, void *stream);
+
 /* The paper's simple reuse baselines (Sec. 6), for quality comparisons.
  *
  * Final-value filtering (Filter (N) for AO; for shadows also Light (N),

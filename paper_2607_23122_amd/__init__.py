@@ -109,7 +109,8 @@ class ServerStats(ctypes.Structure):
 EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders",
            "ocr_trace_occluders_counted", "ocr_sample_rays",
            "ocr_workspace_bytes", "ocr_validate_pairs",
-           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_reuse_shadow_solid_angle", "ocr_filter_values",
+           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_reuse_shadow_solid_angle", "ocr_reuse_direct_illumination",
+           "ocr_filter_values",
            "ocr_light_reuse_shadow", "ocr_scale", "ocr_last_error",
            "ocr_version",
            "ocr_plan_create", "ocr_plan_launch", "ocr_plan_get_info", "ocr_plan_get_records", "ocr_plan_free",
@@ -159,6 +160,10 @@ def lib():
                                    ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
     L.ocr_reuse_shadow_solid_angle.restype = i32
     L.ocr_reuse_shadow_solid_angle.argtypes = L.ocr_reuse_shadow.argtypes
+    L.ocr_reuse_direct_illumination.restype = i32
+    L.ocr_reuse_direct_illumination.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ),
+                                                ctypes.POINTER(_Light), ctypes.c_float, ctypes.c_float,
+                                                ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
     L.ocr_filter_values.restype = i32
     L.ocr_filter_values.argtypes = [ctypes.POINTER(_GBuffer), ctypes.POINTER(ReuseParams), vp, vp, vp]
     L.ocr_light_reuse_shadow.restype = i32
@@ -432,6 +437,23 @@ def reuse_shadow_solid_angle(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluder
                                               ctypes.byref(ls), ctypes.byref(params),
                                               _dptr(ws) if ws is not None else None, nbytes, _dptr(out),
                                               _stream(stream)))
+    return out
+
+
+def reuse_direct_illumination(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluders, light, params: ReuseParams,
+                              radiance=1.0, albedo=1.0, out=None, workspace=None, stream=None):
+    """Occluder-domain direct illumination of a Lambertian receiver from
+    OCR_SHADOW records (ocr_reuse_direct_illumination)."""
+    import torch
+    out = out if out is not None else torch.empty((gbuf.height, gbuf.width), dtype=torch.float32,
+                                                  device=gbuf.prim.device)
+    ws, nbytes = _workspace(gbuf, params, workspace)
+    g, o = gbuf.c(), occ.c()
+    ls = light_struct(light)
+    _check(lib().ocr_reuse_direct_illumination(bvh.h if bvh is not None else None, ctypes.byref(g), ctypes.byref(o),
+                                               ctypes.byref(ls), float(radiance), float(albedo),
+                                               ctypes.byref(params), _dptr(ws) if ws is not None else None, nbytes,
+                                               _dptr(out), _stream(stream)))
     return out
 
 

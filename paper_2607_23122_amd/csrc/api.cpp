@@ -109,7 +109,7 @@ namespace {
 
 ocr_status reuse_common(const ocr_bvh *bvh, const ocr_gbuffer *g, const ocr_occluders *occ, int mode, float R,
                         const LightF &L, const ocr_reuse_params *p, void *ws, size_t ws_bytes, float *out,
-                        void *stream) {
+                        void *stream, float scale = 1.0f) {
     ocr_status st = check_gbuf(g);
     if (st) return st;
     if ((st = check_params(p))) return st;
@@ -125,12 +125,12 @@ ocr_status reuse_common(const ocr_bvh *bvh, const ocr_gbuffer *g, const ocr_occl
     GBufView gv = view(g);
     hipError_t e;
     if (p->estimator == OCR_UNBIASED && !p->validated) {
-        // both shadow definitions validate the same pairs (same densities)
-        e = launch_validate(bvh->dev, gv, ov, mode == kShadowSA ? OCR_SHADOW : mode, R, L, *p, (uint32_t *)ws,
+        // the light modes validate the same pairs (same densities)
+        e = launch_validate(bvh->dev, gv, ov, mode == OCR_AO ? OCR_AO : OCR_SHADOW, R, L, *p, (uint32_t *)ws,
                             nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "validation launch");
     }
-    e = launch_reuse(gv, ov, mode, R, L, *p, (const uint32_t *)ws, out, s);
+    e = launch_reuse(gv, ov, mode, R, L, *p, (const uint32_t *)ws, out, s, scale);
     if (e != hipSuccess) return hip_fail(e, "reuse launch");
     return OCR_OK;
 }
@@ -337,6 +337,20 @@ ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *g
     ocr_status st = make_light(light, L);
     if (st) return st;
     return reuse_common(bvh, gbuf, occ, kShadowSA, 1.0f, L, params, workspace, workspace_bytes, out, stream);
+}
+
+ocr_status ocr_reuse_direct_illumination(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                         const ocr_rect_light *light, float radiance, float albedo,
+                                         const ocr_reuse_params *params, void *workspace, size_t workspace_bytes,
+                                         float *out, void *stream) {
+    if (!(std::isfinite(radiance) && radiance >= 0.0f) || !(std::isfinite(albedo) && albedo >= 0.0f))
+        return fail(OCR_ERR_INVALID_ARG, "radiance %g and albedo %g must be finite and >= 0", (double)radiance,
+                    (double)albedo);
+    LightF L;
+    ocr_status st = make_light(light, L);
+    if (st) return st;
+    const float scale = (float)((double)albedo * (double)radiance / 3.14159265358979323846);
+    return reuse_common(bvh, gbuf, occ, kDI, 1.0f, L, params, workspace, workspace_bytes, out, stream, scale);
 }
 
 ocr_status ocr_filter_values(const ocr_gbuffer *gbuf, const ocr_reuse_params *params, const float *in, float *out,

@@ -54,9 +54,11 @@ struct DeviceBVH {
 };
 
 // Light in the form the kernels use (FP32).
-// Internal mode of the reuse kernels: rectangular-light shadows under the
-// solid-angle definition (records, densities and validation as OCR_SHADOW).
+// Internal modes of the reuse kernels, with the records, densities and
+// validation of OCR_SHADOW: rectangular-light shadows under the solid-angle
+// definition, and occluder-domain direct illumination.
 constexpr int kShadowSA = 2;
+constexpr int kDI = 3;
 
 struct LightF {
     float c[3], eu[3], ev[3];
@@ -198,8 +200,10 @@ hipError_t launch_trace_count(const DeviceBVH &bvh, const GBufView &g, int mode,
 hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, int mode, float R,
                            const LightF &L, const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats,
                            hipStream_t st);
+// scale: rho L_e / pi for direct illumination (kDI), unused otherwise
 hipError_t launch_reuse(const GBufView &g, const OccView &occ, int mode, float R, const LightF &L,
-                        const ocr_reuse_params &p, const uint32_t *bits, float *out, hipStream_t st);
+                        const ocr_reuse_params &p, const uint32_t *bits, float *out, hipStream_t st,
+                        float scale = 1.0f);
 hipError_t launch_scale(float *out, int64_t n, float s, hipStream_t st);
 hipError_t launch_samples(const GBufView &g, int mode, const LightF &L, uint32_t seed32, uint32_t sample, float *o,
                           float *d, uint8_t *kind, hipStream_t st);

@@ -29,12 +29,12 @@ template <int MODE, bool UNB>
 __global__ __launch_bounds__(kRBlock) void reuse_window_kernel(GBufView g, OccView occ, float R2, LightF L,
                                                                const uint32_t *__restrict__ bits, int words, int R,
                                                                int dark_guard, int accumulate, float *out,
-                                                               int tiles_x, int ntiles) {
+                                                               int tiles_x, int ntiles, float scale) {
     extern __shared__ __align__(16) unsigned char smem[];
     int tx, ty;
     r_tile_of_block(tiles_x, ntiles, tx, ty);
     if (ty * tiles_x + tx >= ntiles) return;
-    reuse_window_tile<MODE, UNB>(smem, g, occ, R2, L, bits, words, R, dark_guard, accumulate, out, tx, ty);
+    reuse_window_tile<MODE, UNB>(smem, g, occ, R2, L, bits, words, R, dark_guard, accumulate, out, tx, ty, scale);
 }
 
 // Fixed groups.  Block = 32 x 8 pixels; the group shapes (1x1, 2x1, 2x2,
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
                                                               const uint32_t *__restrict__ bits, int words, int N,
                                                               int gw, int gh, int D, int dark_guard,
                                                               int accumulate, float *out, int tiles_x,
-                                                              int ntiles) {
+                                                              int ntiles, float scale) {
     __shared__ float s_o[3][kRBlock], s_n[3][kRBlock], s_dz[3][kRBlock], s_nz[3][kRBlock];
     __shared__ float s_sh[3][kRBlock];
     __shared__ uint32_t s_hit[kRBlock];
@@ -136,13 +136,14 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
         const float pij = s_p[tid][m];
         if (pij > 0.0f && P > 0.0f) {
             float term = pij * __builtin_amdgcn_rcpf(P);
-            if (MODE == kShadowSA) {
-                // times g_ij of this target and candidate m
+            if (MODE >= kShadowSA) {
+                // times g_ij (solid angle) or gd_ij (direct illumination) of
+                // this target and candidate m
                 const float oj[3] = {s_o[0][jt], s_o[1][jt], s_o[2][jt]};
                 const float dzj[3] = {s_dz[0][jt], s_dz[1][jt], s_dz[2][jt]};
                 float w[3];
                 rel_vec(oj, o, dzj, w);
-                term *= sa_pair_g(w, rk.hk, L);
+                term *= MODE == kDI ? di_pair_g(w, n, rk.hk, L) : sa_pair_g(w, rk.hk, L);
             }
             B += term;
         }
@@ -152,6 +153,9 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     if (MODE != OCR_AO && valid) {
         if (MODE == kShadowSA) {
             F = sa_estimate(o, n, L, B);
+            B = 0.0f;
+        } else if (MODE == kDI) {
+            F = di_estimate(o, n, L, B, scale);
             B = 0.0f;
         } else {
             F = front_fraction(o, n, L);
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
 
 template <int MODE>
 __global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView occ, LightF L, int accumulate,
-                                                          float *out) {
+                                                          float *out, float scale) {
     const int64_t gi = (int64_t)blockIdx.x * kRBlock + threadIdx.x;
     if (gi >= (int64_t)g.w * g.h) return;
     const bool valid = g.prim[gi] != OCR_HIT_MISS;
@@ -173,8 +177,9 @@ __global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView oc
     } else if (MODE == OCR_SHADOW) {
         v = (valid && occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
     } else {
-        // solid-angle definition, S(i) = {i}: F_Omega - C_Omega(x_i, z_i) for
-        // a hit whose own density is positive (the ratio p/p is 1)
+        // solid-angle definition / direct illumination, S(i) = {i}: the
+        // unshadowed term minus C(x_i, z_i) for a hit whose own density is
+        // positive (the ratio p/p is 1)
         v = 0.0f;
         if (valid) {
             float x[3], n[3], o[3];
@@ -188,9 +193,10 @@ __global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView oc
                 ld3(occ.dz, gi, dz);
                 ld3(occ.nz, gi, nz);
                 const RecvShadow rk = recv_shadow(o, L);
-                if (dens_shadow(dz, n, rk, nz, L) > 0.0f) Bg = sa_pair_g(dz, rk.hk, L);
+                if (dens_shadow(dz, n, rk, nz, L) > 0.0f)
+                    Bg = MODE == kDI ? di_pair_g(dz, n, rk.hk, L) : sa_pair_g(dz, rk.hk, L);
             }
-            v = sa_estimate(o, n, L, Bg);
+            v = MODE == kDI ? di_estimate(o, n, L, Bg, scale) : sa_estimate(o, n, L, Bg);
         }
     }
     out[gi] = accumulate ? out[gi] + v : v;
@@ -206,7 +212,7 @@ __global__ void scale_kernel(float *out, int64_t n, float s) {
 // ---------------------------------------------------------------------------
 template <int MODE, bool UNB>
 static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, const LightF &L, const uint32_t *bits,
-                             int words, const ocr_reuse_params &p, float *out, hipStream_t st) {
+                             int words, const ocr_reuse_params &p, float *out, float scale, hipStream_t st) {
     int tiles_x = (g.w + kWTX - 1) / kWTX, tiles_y = (g.h + kWTY - 1) / kWTY;
     int nt = tiles_x * tiles_y;
     WinLayout lay = win_layout(p.radius, MODE, UNB, words);
@@ -223,65 +229,56 @@ static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, co
     }
     dim3 grid(((nt + 7) / 8) * 8), block(kRBlock);
     hipLaunchKernelGGL((reuse_window_kernel<MODE, UNB>), grid, block, lay.total, st, g, occ, R2, L, bits, words,
-                       p.radius, p.dark_guard, p.accumulate, out, tiles_x, nt);
+                       p.radius, p.dark_guard, p.accumulate, out, tiles_x, nt, scale);
     return hipSuccess;
 }
 
 template <int MODE, bool UNB>
 static void launch_grp(const GBufView &g, const OccView &occ, float R2, const LightF &L, const uint32_t *bits,
-                       int words, const ocr_reuse_params &p, float *out, hipStream_t st) {
+                       int words, const ocr_reuse_params &p, float *out, float scale, hipStream_t st) {
     int gw, gh;
     group_dims(p.group_n, gw, gh);
     int tiles_x = (g.w + 31) / 32, tiles_y = (g.h + 7) / 8;
     int nt = tiles_x * tiles_y;
     dim3 grid(((nt + 7) / 8) * 8), block(kRBlock);
     hipLaunchKernelGGL((reuse_group_kernel<MODE, UNB>), grid, block, 0, st, g, occ, R2, L, bits, words, p.group_n,
-                       gw, gh, pair_extent(p), p.dark_guard, p.accumulate, out, tiles_x, nt);
+                       gw, gh, pair_extent(p), p.dark_guard, p.accumulate, out, tiles_x, nt, scale);
+}
+
+template <int MODE>
+static hipError_t launch_mode(const GBufView &g, const OccView &occ, float R2, const LightF &L, const uint32_t *bits,
+                              int words, const ocr_reuse_params &q, bool unb, float *out, float scale,
+                              hipStream_t st) {
+    if (q.estimator == OCR_NOREUSE) {
+        int64_t n = (int64_t)g.w * g.h;
+        dim3 grid((unsigned)((n + kRBlock - 1) / kRBlock)), block(kRBlock);
+        hipLaunchKernelGGL(noreuse_kernel<MODE>, grid, block, 0, st, g, occ, L, q.accumulate, out, scale);
+        return hipSuccess;
+    }
+    if (q.pattern == OCR_WINDOW)
+        return unb ? launch_win<MODE, true>(g, occ, R2, L, bits, words, q, out, scale, st)
+                   : launch_win<MODE, false>(g, occ, R2, L, bits, words, q, out, scale, st);
+    if (unb) launch_grp<MODE, true>(g, occ, R2, L, bits, words, q, out, scale, st);
+    else launch_grp<MODE, false>(g, occ, R2, L, bits, words, q, out, scale, st);
+    return hipSuccess;
 }
 
 hipError_t launch_reuse(const GBufView &g, const OccView &occ, int mode, float R, const LightF &L,
-                        const ocr_reuse_params &p, const uint32_t *bits, float *out, hipStream_t st) {
+                        const ocr_reuse_params &p, const uint32_t *bits, float *out, hipStream_t st, float scale) {
     const float R2 = R * R;
     const int words = pair_words(p);
     const bool unb = p.estimator == OCR_UNBIASED;
-    // the dark-region guard belongs to the biased shadow estimator only
+    // the dark-region guard belongs to the biased estimators of the light modes only
     ocr_reuse_params q = p;
     q.dark_guard = (p.estimator == OCR_BIASED && p.dark_guard) ? 1 : 0;
-    if (p.estimator == OCR_NOREUSE) {
-        int64_t n = (int64_t)g.w * g.h;
-        dim3 grid((unsigned)((n + kRBlock - 1) / kRBlock)), block(kRBlock);
-        if (mode == OCR_AO)
-            hipLaunchKernelGGL(noreuse_kernel<OCR_AO>, grid, block, 0, st, g, occ, L, q.accumulate, out);
-        else if (mode == OCR_SHADOW)
-            hipLaunchKernelGGL(noreuse_kernel<OCR_SHADOW>, grid, block, 0, st, g, occ, L, q.accumulate, out);
-        else
-            hipLaunchKernelGGL(noreuse_kernel<kShadowSA>, grid, block, 0, st, g, occ, L, q.accumulate, out);
-    } else if (p.pattern == OCR_WINDOW) {
-        if (mode == OCR_AO) {
-            hipError_t e = unb ? launch_win<OCR_AO, true>(g, occ, R2, L, bits, words, q, out, st)
-                               : launch_win<OCR_AO, false>(g, occ, R2, L, bits, words, q, out, st);
-            if (e != hipSuccess) return e;
-        } else if (mode == OCR_SHADOW) {
-            hipError_t e = unb ? launch_win<OCR_SHADOW, true>(g, occ, R2, L, bits, words, q, out, st)
-                               : launch_win<OCR_SHADOW, false>(g, occ, R2, L, bits, words, q, out, st);
-            if (e != hipSuccess) return e;
-        } else {
-            hipError_t e = unb ? launch_win<kShadowSA, true>(g, occ, R2, L, bits, words, q, out, st)
-                               : launch_win<kShadowSA, false>(g, occ, R2, L, bits, words, q, out, st);
-            if (e != hipSuccess) return e;
-        }
-    } else {
-        if (mode == OCR_AO) {
-            if (unb) launch_grp<OCR_AO, true>(g, occ, R2, L, bits, words, q, out, st);
-            else launch_grp<OCR_AO, false>(g, occ, R2, L, bits, words, q, out, st);
-        } else if (mode == OCR_SHADOW) {
-            if (unb) launch_grp<OCR_SHADOW, true>(g, occ, R2, L, bits, words, q, out, st);
-            else launch_grp<OCR_SHADOW, false>(g, occ, R2, L, bits, words, q, out, st);
-        } else {
-            if (unb) launch_grp<kShadowSA, true>(g, occ, R2, L, bits, words, q, out, st);
-            else launch_grp<kShadowSA, false>(g, occ, R2, L, bits, words, q, out, st);
-        }
+    hipError_t e;
+    switch (mode) {
+        case OCR_AO: e = launch_mode<OCR_AO>(g, occ, R2, L, bits, words, q, unb, out, scale, st); break;
+        case OCR_SHADOW: e = launch_mode<OCR_SHADOW>(g, occ, R2, L, bits, words, q, unb, out, scale, st); break;
+        case kShadowSA: e = launch_mode<kShadowSA>(g, occ, R2, L, bits, words, q, unb, out, scale, st); break;
+        default: e = launch_mode<kDI>(g, occ, R2, L, bits, words, q, unb, out, scale, st); break;
     }
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

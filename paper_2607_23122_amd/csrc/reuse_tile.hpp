@@ -75,15 +75,25 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     return l;
 }
 
-// The scattered term of target cell kc under the solid-angle definition:
-// p_i(j) / P_i(j) times g_ij, clamped below 2^31 so that the 32.32 fixed-point
-// sum cannot overflow (g reaches that size only within ~1e-5 of the light).
-__device__ inline float sa_term(float ratio, const float *s_o, const float *s_sh, int CELLS, int kc,
-                                const float oj[3], const float dzj[3], const LightF &L) {
+// The scattered term of target cell kc under the solid-angle definition
+// (MODE kShadowSA: p_i(j) / P_i(j) times g_ij) or for direct illumination
+// (kDI: times gd_ij), clamped below 2^31 so that the 32.32 fixed-point sum
+// cannot overflow (the factor reaches that size only within ~1e-5 of the
+// light).
+template <int MODE>
+__device__ inline float weighted_term(float ratio, const float *s_o, const float *s_n, const float *s_sh, int CELLS,
+                                      int kc, const float oj[3], const float dzj[3], const LightF &L) {
     const float oi[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
     float w[3];
     rel_vec(oj, oi, dzj, w);
-    return fminf(ratio * sa_pair_g(w, s_sh[kc], L), 0x1p31f);
+    float gf;
+    if (MODE == kDI) {
+        const float ni[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
+        gf = di_pair_g(w, ni, s_sh[kc], L);
+    } else {
+        gf = sa_pair_g(w, s_sh[kc], L);
+    }
+    return fminf(ratio * gf, 0x1p31f);
 }
 
 // One kWTX x kWTY target tile (tx, ty) of the sliding-window estimator; every
@@ -91,7 +101,8 @@ __device__ inline float sa_term(float ratio, const float *s_o, const float *s_sh
 template <int MODE, bool UNB>
 __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g, const OccView &occ, float R2,
                                          const LightF &L, const uint32_t *__restrict__ bits, int words, int R,
-                                         int dark_guard, int accumulate, float *out, int tx, int ty) {
+                                         int dark_guard, int accumulate, float *out, int tx, int ty,
+                                         float scale = 1.0f) {
     const WinLayout lay = win_layout(R, MODE, UNB, words);
     const int TX = kWTX, TY = kWTY, RW = lay.RWX, CELLS = lay.cells, D = 2 * R, SIDE = lay.side, TW = 2 * R + 1;
     const float inv_rw = 1.0f / (float)RW;
@@ -252,8 +263,9 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                 P += h;
                 if (tgt) {
                     float term = my_p * __builtin_amdgcn_rcpf(P);
-                    if (MODE == kShadowSA)
-                        term = sa_term(term, s_o, s_sh, CELLS, __mul24(ky0 + my_y, RW) + (kx0 + my_x), oj, dzj, L);
+                    if (MODE >= kShadowSA)
+                        term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ky0 + my_y, RW) + (kx0 + my_x),
+                                                   oj, dzj, L);
                     atomicAdd(&s_B[(ky0 + my_y - R) * TX + (kx0 + my_x - R)],
                               (unsigned long long)rintf(term * 4294967296.0f));
                 }
@@ -280,8 +292,9 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                 const float pij = w_dens[__mul24(r2 + R, SIDE) + (t2 + R)];
                 if (pij > 0.0f && P > 0.0f) {
                     float term = pij * __builtin_amdgcn_rcpf(P);
-                    if (MODE == kShadowSA)
-                        term = sa_term(term, s_o, s_sh, CELLS, __mul24(ty0 + r2, RW) + (tx0 + t2), oj, dzj, L);
+                    if (MODE >= kShadowSA)
+                        term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ty0 + r2, RW) + (tx0 + t2), oj,
+                                                   dzj, L);
                     atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],
                               (unsigned long long)rintf(term * 4294967296.0f));
                 }
@@ -306,8 +319,11 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
             float n[3] = {s_n[c], s_n[CELLS + c], s_n[2 * CELLS + c]};
             if (MODE == kShadowSA) {
                 // F_Omega - (Area / Omega_A) B, as F - B below
-                const float v = sa_estimate(o, n, L, B);
-                F = v;
+                F = sa_estimate(o, n, L, B);
+                B = 0.0f;
+            } else if (MODE == kDI) {
+                // (rho L_e / pi) (E - Area B), as F - B below
+                F = di_estimate(o, n, L, B, scale);
                 B = 0.0f;
             } else {
                 F = front_fraction(o, n, L);

@@ -1,3 +1,6 @@
+// Shadows under the solid-angle definition and direct illumination in the
+// occluder domain.
+//
 // Shadows under the solid-angle definition (the appendix deriving the
 // occluder-domain form of Eq. reapp-shadow-definition-solid-angle): the
 // target is the visible part of the solid angle Omega_A(x) that the light
@@ -116,6 +119,104 @@ __device__ inline float sa_estimate(const float o[3], const float n[3], const Li
     if (!(all > 0.0f)) return 0.0f;
     const float area = sqrtf(dot3f(L.nlu, L.nlu));
     return front / all - (area / all) * Bg;
+}
+
+// ---------------------------------------------------------------------------
+// Occluder-domain direct illumination (the appendix deriving Eq.
+// reapp-di-occluder-domain-compact) for a Lambertian receiver of albedo rho
+// under the one-sided emitter of radiance L_e:
+//   L_DI(x_i) = (rho L_e / pi) (E(x_i) - Area sum_j gd_ij p_i(j) / P_i(j)),
+// gd_ij = cos+_x <n_y', w_{y'->x_i}> / |x_i - y'|^2 (the factor C_DI of Eq.
+// reapp-di-general-mis-factor for uniform light sampling, without its
+// per-target part) and E the irradiance of the unit-radiance light's part in
+// front of the tangent plane (the unshadowed term, Lambert's polygon formula).
+// ---------------------------------------------------------------------------
+
+// gd for the pair vector w = z_j - o_i, the receiver normal n and hk.
+__device__ inline float di_pair_g(const float w[3], const float n[3], float hk, const LightF &L) {
+    const float nw = dot3f(n, w);
+    if (!(nw > 0.0f)) return 0.0f;
+    return nw * __builtin_amdgcn_rsqf(dot3f(w, w)) * sa_pair_g(w, hk, L);
+}
+
+// Streaming Lambert polygon formula, E = 1/2 |sum_k theta_k <n, c_k / |c_k|>|,
+// c_k = q_k x q_{k+1}, over vertices arriving in order as light coordinates.
+// The cross product of the two long vertex vectors is taken as
+// co x (short edge) + (a_k b_{k+1} - b_k a_{k+1}) (e_u x e_v), co = c - o,
+// which avoids their cancellation.
+struct LambertFan {
+    float a0, b0, v0[3];
+    float ap, bp, vp[3];
+    float acc;
+    int m;
+};
+
+__device__ inline void lambert_edge(float &acc, float a1, float b1, const float v1[3], float a2, float b2,
+                                    const float v2[3], const float co[3], const float n[3], const LightF &L) {
+    float e[3], c[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = (a2 - a1) * L.eu[k] + (b2 - b1) * L.ev[k];
+    const float t = a1 * b2 - b1 * a2;
+    c[0] = __fmaf_rn(t, L.nlu[0], co[1] * e[2] - co[2] * e[1]);
+    c[1] = __fmaf_rn(t, L.nlu[1], co[2] * e[0] - co[0] * e[2]);
+    c[2] = __fmaf_rn(t, L.nlu[2], co[0] * e[1] - co[1] * e[0]);
+    const float lc = sqrtf(dot3f(c, c));
+    if (!(lc > 0.0f)) return;
+    acc += atan2f(lc, dot3f(v1, v2)) * dot3f(n, c) / lc;
+}
+
+__device__ inline void lfan_add(LambertFan &f, float va, float vb, const float co[3], const float n[3],
+                                const LightF &L) {
+    float v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = __fmaf_rn(vb, L.ev[k], __fmaf_rn(va, L.eu[k], co[k]));
+    if (f.m == 0) {
+        f.a0 = va;
+        f.b0 = vb;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f.v0[k] = v[k];
+    } else {
+        lambert_edge(f.acc, f.ap, f.bp, f.vp, va, vb, v, co, n, L);
+    }
+    f.ap = va;
+    f.bp = vb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f.vp[k] = v[k];
+    ++f.m;
+}
+
+// E(o): the irradiance of the unit-radiance light's part with <n, y - o> > 0
+// (0 when o is not on the emitting side).
+__device__ inline float emitter_irradiance(const float o[3], const float n[3], const LightF &L) {
+    const float co[3] = {L.c[0] - o[0], L.c[1] - o[1], L.c[2] - o[2]};
+    if (!(dot3f(L.nl, co) < 0.0f)) return 0.0f;
+    const float ca[4] = {-0.5f, 0.5f, 0.5f, -0.5f};
+    const float cb[4] = {-0.5f, -0.5f, 0.5f, 0.5f};
+    const float f0 = dot3f(n, co), fu = dot3f(n, L.eu), fv = dot3f(n, L.ev);
+    LambertFan f;
+    f.acc = 0.0f;
+    f.m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int k1 = (k + 1) & 3;
+        const float ga = f0 + ca[k] * fu + cb[k] * fv;
+        const float gb = f0 + ca[k1] * fu + cb[k1] * fv;
+        if (ga > 0.0f) lfan_add(f, ca[k], cb[k], co, n, L);
+        if ((ga > 0.0f) != (gb > 0.0f)) {
+            const float t = ga / (ga - gb);
+            lfan_add(f, ca[k] + t * (ca[k1] - ca[k]), cb[k] + t * (cb[k1] - cb[k]), co, n, L);
+        }
+    }
+    if (f.m < 3) return 0.0f;
+    lambert_edge(f.acc, f.ap, f.bp, f.vp, f.a0, f.b0, f.v0, co, n, L);  // closing edge
+    return 0.5f * fabsf(f.acc);
+}
+
+// Estimate of one target from its accumulated sum_j gd_ij p_i(j) / P_i(j);
+// scale = rho L_e / pi.
+__device__ inline float di_estimate(const float o[3], const float n[3], const LightF &L, float Bg, float scale) {
+    const float area = sqrtf(dot3f(L.nlu, L.nlu));
+    return scale * (emitter_irradiance(o, n, L) - area * Bg);
 }
 
 }  // namespace ocr

@@ -54,19 +54,27 @@ def terrain_1080(ocr):
 
 
 def _trace(ocr, case, mode, seed=1, sample=0):
-    # both shadow definitions trace the same records (uniform light samples)
-    tmode = "shadow" if mode == "shadow_sa" else mode
+    # the light modes trace the same records (uniform light samples)
+    tmode = "shadow" if mode in ("shadow_sa", "di") else mode
     occ = ocr.trace_occluders(case.bvh, case.dg, tmode, case.R, case.light if tmode == "shadow" else None, seed,
                               sample)
     torch.cuda.synchronize()
     return occ
 
 
-def _reuse(ocr, case, mode, occ, params):
+# direct illumination: albedo pi, so that the GPU's value is the oracle's
+# (in units of rho L_e / pi) times the radiance
+DI_ALBEDO = float(np.pi)
+
+
+def _reuse(ocr, case, mode, occ, params, radiance=1.0):
     if mode == "ao":
         out = ocr.reuse_ao(case.bvh, case.dg, occ, case.R, params)
     elif mode == "shadow_sa":
         out = ocr.reuse_shadow_solid_angle(case.bvh, case.dg, occ, case.light, params)
+    elif mode == "di":
+        out = ocr.reuse_direct_illumination(case.bvh, case.dg, occ, case.light, params, radiance=radiance,
+                                            albedo=DI_ALBEDO)
     else:
         out = ocr.reuse_shadow(case.bvh, case.dg, occ, case.light, params)
     torch.cuda.synchronize()
@@ -195,6 +203,52 @@ def test_reuse_shadow_solid_angle_near_light(ocr, est, pattern, size):
     assert (f < 0.999).mean() > 0.5  # the case does exercise F_Omega < 1 and blocked terms
 
 
+def _scaled(res, k):
+    res.value = res.value * k
+    res.var = res.var * k
+    return res
+
+
+@pytest.mark.parametrize("pattern,size,est,guard", [("window", 3, "biased", True), ("window", 2, "unbiased", True),
+                                                   ("window", 3, "unbiased", True), ("group", 8, "biased", True),
+                                                   ("group", 4, "unbiased", True), ("window", 3, "none", True)])
+def test_reuse_direct_illumination_terrain_small(ocr, terrain_small, pattern, size, est, guard):
+    # f4: occluder-domain direct illumination from the shadow records; a
+    # radiance of 100 puts the values (a 1 m^2 light 8-12 m away) near 1
+    case = terrain_small
+    log(f"[reuse di 480x270] {pattern} {size} {est} guard={guard}")
+    occ = _trace(ocr, case, "di", seed=3)
+    gpu = _reuse(ocr, case, "di", occ, ocr.reuse_params(pattern, size, size, est, dark_guard=guard), radiance=100.0)
+    p = _oparams(case, "di", est, pattern, size, seed=3, guard=guard)
+    rec, res = oracle.frame(case.osc, case.gb, p)
+    st = compare_values(gpu, _scaled(res, 100.0), exclude=mismatch_reach(occ.hit_u32(), rec, p))
+    log(f"    {st}")
+    assert st["excluded"] <= 2e-3 * st["targets"]
+
+
+@pytest.mark.parametrize("est,pattern,size", [("none", "window", 0), ("biased", "window", 2),
+                                              ("unbiased", "window", 2), ("unbiased", "group", 8)])
+def test_reuse_direct_illumination_near_light(ocr, est, pattern, size):
+    # a light 2 m above tilted receivers: the tangent planes clip the light
+    import scenes
+    s = scenes.build([scenes.FLOOR, scenes.plate_y(1.0, -0.5, 0.02, -3, 3), scenes.plate_y(0.1, -0.12, -0.06, -3, 3)])
+    gb = scenes.floor_grid(96, 64, 0.01, x0=-0.5, z0=-0.3)
+    th = np.arctan2(1.0, -0.1)
+    gb.nrm[:] = np.array([np.sin(th), np.cos(th), 0.0], np.float32)
+    light = w.RectLight(np.array([0, 2.0, 0], np.float32), np.array([1.0, 0, 0], np.float32),
+                        np.array([0, 0, 1.0], np.float32))
+    case = Case(ocr, "tilted_near_light", s, gb, "di", 1.0, light)
+    log(f"[reuse di near light] {pattern} {size} {est}")
+    occ = _trace(ocr, case, "di", seed=6)
+    gpu = _reuse(ocr, case, "di", occ, ocr.reuse_params(pattern, size, size, est), radiance=4.0)
+    p = _oparams(case, "di", est, pattern, size, seed=6)
+    rec, res = oracle.frame(case.osc, gb, p)
+    st = compare_values(gpu, _scaled(res, 4.0), exclude=mismatch_reach(occ.hit_u32(), rec, p))
+    log(f"    {st}")
+    # plate edges on pixel columns graze more segments (see the solid-angle case)
+    assert st["excluded"] <= 1e-2 * st["targets"]
+
+
 def test_reuse_ao_terrain_small_unbiased_r3(ocr, terrain_small):
     case = terrain_small
     log("[reuse ao 480x270] window 3 unbiased")
@@ -211,7 +265,7 @@ def test_reuse_ao_terrain_small_unbiased_r3(ocr, terrain_small):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("mode,est,ntiles", [("ao", "biased", 12), ("ao", "unbiased", 4), ("shadow", "biased", 12),
                                              ("shadow", "unbiased", 4), ("shadow_sa", "biased", 6),
-                                             ("shadow_sa", "unbiased", 3)])
+                                             ("shadow_sa", "unbiased", 3), ("di", "biased", 6), ("di", "unbiased", 3)])
 def test_reuse_1080p_tiles(ocr, terrain_1080, mode, est, ntiles):
     case = terrain_1080
     log(f"[reuse 1080p] {mode} window 3 {est}")
@@ -219,10 +273,16 @@ def test_reuse_1080p_tiles(ocr, terrain_1080, mode, est, ntiles):
     gpu = _reuse(ocr, case, mode, occ, ocr.reuse_params("window", 3, 0, est))
     p = _oparams(case, mode, est, "window", 3, seed=1)
     gh = occ.hit_u32()
-    for t in tiles(case.gb.width, case.gb.height, ntiles, 32, seed={"ao": 11, "shadow": 12, "shadow_sa": 13}[mode]):
+    k = 100.0 if mode == "di" else 1.0  # radiance of the direct-illumination case (values near 1)
+    if mode == "di":
+        gpu = to_np(ocr.reuse_direct_illumination(case.bvh, case.dg, occ, case.light,
+                                                  ocr.reuse_params("window", 3, 0, est), radiance=k,
+                                                  albedo=DI_ALBEDO))
+    for t in tiles(case.gb.width, case.gb.height, ntiles, 32,
+                   seed={"ao": 11, "shadow": 12, "shadow_sa": 13, "di": 14}[mode]):
         hr = oracle.halo_region(p, case.gb.width, case.gb.height, t)
         rec = oracle.records(case.osc, case.gb, p, hr)
-        res = oracle.reuse(case.osc, case.gb, p, rec, t)
+        res = _scaled(oracle.reuse(case.osc, case.gb, p, rec, t), k)
         inside = np.zeros_like(case.gb.valid)
         inside[hr[1]:hr[3], hr[0]:hr[2]] = True
         st = compare_values(gpu, res, region=t, exclude=mismatch_reach(np.where(inside, gh, rec.hit), rec, p))
