@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("estimator", ctypes.c_int32), ("pattern", ctypes.c_int32),
                 ("radius", ctypes.c_int32), ("group_n", ctypes.c_int32), ("dark_guard", ctypes.c_int32),
                 ("ao_radius", ctypes.c_double), ("light", ctypes.c_float * 9), ("seed", ctypes.c_uint64),
-                ("sample", ctypes.c_uint32), ("pad", ctypes.c_int32)]
+                ("sample", ctypes.c_uint32), ("pad", ctypes.c_int32), ("nlights", ctypes.c_int32),
+                ("more_lights", ctypes.c_float * 27)]
 
 
 MODES = {"ao": 0, "shadow": 1, "shadow_sa": 2, "di": 3}
@@ -55,9 +56,18 @@ def params(mode="ao", estimator="biased", pattern="window", radius=2, group_n=8,
     p.dark_guard = 1 if dark_guard else 0
     p.ao_radius = float(ao_radius)
     if light is not None:
-        la = light.as_array() if hasattr(light, "as_array") else np.asarray(light, np.float32)
-        for i in range(9):
-            p.light[i] = float(la[i])
+        # one light, or a list of up to 4 (shadows of several lights)
+        lights = list(light) if isinstance(light, (list, tuple)) else [light]
+        if not 1 <= len(lights) <= 4:
+            raise ValueError("1 to 4 lights")
+        for k, lt in enumerate(lights):
+            la = lt.as_array() if hasattr(lt, "as_array") else np.asarray(lt, np.float32)
+            for i in range(9):
+                if k == 0:
+                    p.light[i] = float(la[i])
+                else:
+                    p.more_lights[9 * (k - 1) + i] = float(la[i])
+        p.nlights = len(lights)
     p.seed = int(seed)
     p.sample = int(sample)
     return p

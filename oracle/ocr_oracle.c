@@ -25,6 +25,10 @@
  *     (Filter (N) for AO; for shadows light-sample reuse without validation,
  *     Light (N), which the paper notes reduces to the same average) and
  *     light-sample reuse with visibility re-evaluation (Light (NU));
+ *   - shadows of several rectangular lights (the paper shows two lights
+ *     but gives no formulation; reading: the visible fraction of the total
+ *     emitting area, a light chosen per sample with probability A_l / A_tot
+ *     and the induced density summed over the lights);
  *   - occluder-domain direct illumination (App. on it: Eq.
  *     reapp-di-occluder-domain-compact with the MIS estimator of Eq.
  *     reapp-di-general-mis-estimator and factor of Eq.
@@ -169,6 +173,50 @@ static void light_point(uint32_t px, uint32_t py, uint32_t s, uint32_t sd, const
     for (int c = 0; c < 3; ++c) y[c] = fmaf(b, L[6 + c], fmaf(a, L[3 + c], L[c]));
 }
 
+/* Light k of the parameters (k < max(nlights, 1)). */
+static const float *light_k(const orc_params *p, int k) { return k == 0 ? p->light : p->more_lights + 9 * (k - 1); }
+static int num_lights(const orc_params *p) { return p->nlights > 1 ? p->nlights : 1; }
+
+/* FP32 area |e_u x e_v| of a light, as the sample specification computes it. */
+static float light_area32(const float *L) {
+    float nl0 = L[4] * L[8] - L[5] * L[7], nl1 = L[5] * L[6] - L[3] * L[8], nl2 = L[3] * L[7] - L[4] * L[6];
+    return sqrtf(fmaf(nl2, nl2, fmaf(nl1, nl1, nl0 * nl0)));
+}
+
+/* Several lights: the light of a sample is chosen with probability
+ * A_l / A_tot, so that the point is uniform over the union of the lights:
+ * with u2 = unit24(h[2]) of the same hash, the first l whose running FP32 sum
+ * C_l = A_0 + ... + A_l exceeds u2 * A_tot (the last light if rounding leaves
+ * none); the point on it then uses h[0], h[1] exactly as for one light.  For
+ * one light this is light_point. */
+static int light_point_multi(uint32_t px, uint32_t py, uint32_t s, uint32_t sd, const orc_params *p, float y[3]) {
+    int K = num_lights(p);
+    uint32_t h[4] = {px, py, s, sd};
+    pcg4d(h);
+    int l = 0;
+    if (K > 1) {
+        float A[4], tot = 0.0f;
+        for (int k = 0; k < K; ++k) {
+            A[k] = light_area32(light_k(p, k));
+            tot = tot + A[k];
+        }
+        float u = unit24(h[2]) * tot, C = 0.0f;
+        l = K - 1;
+        for (int k = 0; k < K; ++k) {
+            C = C + A[k];
+            if (u < C) {
+                l = k;
+                break;
+            }
+        }
+    }
+    const float *L = light_k(p, l);
+    float a = unit24(h[0]) - 0.5f;
+    float b = unit24(h[1]) - 0.5f;
+    for (int c = 0; c < 3; ++c) y[c] = fmaf(b, L[6 + c], fmaf(a, L[3 + c], L[c]));
+    return l;
+}
+
 /* kind: 0 traced, 1 no trace (below the tangent plane, or receiver on the
  * back side of the one-sided light), 2 background pixel. */
 static int make_sample(int32_t W, const float *pos, const float *nrm, const uint32_t *prim, const orc_params *p,
@@ -182,9 +230,8 @@ static int make_sample(int32_t W, const float *pos, const float *nrm, const uint
         ao_direction((uint32_t)px, (uint32_t)py, p->sample, sd, n, dir);
         return 0;
     }
-    const float *L = p->light;
     float y[3];
-    light_point((uint32_t)px, (uint32_t)py, p->sample, sd, L, y);
+    const float *L = light_k(p, light_point_multi((uint32_t)px, (uint32_t)py, p->sample, sd, p, y));
     for (int c = 0; c < 3; ++c) dir[c] = y[c] - o[c];
     float front = fmaf(n[2], dir[2], fmaf(n[1], dir[1], n[0] * dir[0]));
     float nl[3] = {L[4] * L[8] - L[5] * L[7], L[5] * L[6] - L[3] * L[8], L[3] * L[7] - L[4] * L[6]};
@@ -978,13 +1025,39 @@ static void receiver_point(const reuse_ctx *c, int64_t k, double o[3], double n[
     f2d(c->nrm + 3 * k, n);
 }
 
+/* The light-frame area of light k (FP64). */
+static double light_area64(const orc_params *p, int k) {
+    double L[9], cc[3], eu[3], ev[3], nl[3], area;
+    for (int q = 0; q < 9; ++q) L[q] = light_k(p, k)[q];
+    light_frame(L, cc, eu, ev, nl, &area);
+    return area;
+}
+
 static dens_t pair_density(const reuse_ctx *c, int64_t k, int64_t j) {
     double o[3], n[3];
     receiver_point(c, k, o, n);
     if (c->p->mode == 0) return density_ao(o, n, c->z + 3 * j, c->nz + 3 * j, c->p->ao_radius);
-    double L[9];
-    for (int q = 0; q < 9; ++q) L[q] = c->p->light[q];
-    return density_shadow(o, n, c->z + 3 * j, c->nz + 3 * j, L);
+    int K = num_lights(c->p);
+    if (K == 1) {
+        double L[9];
+        for (int q = 0; q < 9; ++q) L[q] = c->p->light[q];
+        return density_shadow(o, n, c->z + 3 * j, c->nz + 3 * j, L);
+    }
+    /* several lights: the density of z over the union of the lights is the
+     * area-weighted sum of the per-light densities, sum_l (A_l / A_tot) p_l */
+    double A[4], tot = 0.0;
+    for (int l = 0; l < K; ++l) tot += (A[l] = light_area64(c->p, l));
+    dens_t r = {0.0, 0.0, 0, 0};
+    for (int l = 0; l < K; ++l) {
+        double L[9];
+        for (int q = 0; q < 9; ++q) L[q] = light_k(c->p, l)[q];
+        dens_t d = density_shadow(o, n, c->z + 3 * j, c->nz + 3 * j, L);
+        r.p += A[l] / tot * d.p;
+        r.ppass += A[l] / tot * d.ppass;
+        r.amb |= d.amb;
+        r.excl |= d.excl;
+    }
+    return r;
 }
 
 static uint8_t *occ_slot(const reuse_ctx *c, int64_t j, int64_t k) {
@@ -1208,12 +1281,22 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
     double F = 1.0;
     double cfac[MAXSET], *cf = NULL;
     if (p->mode == 1) {
-        double o[3], n[3], L[9];
-        int near;
+        /* F_i; for several lights the area-weighted sum of the per-light
+         * fractions (the front part of the union) */
+        double o[3], n[3];
         receiver_point(c, i, o, n);
-        for (int q = 0; q < 9; ++q) L[q] = p->light[q];
-        F = front_fraction(o, n, L, &near);
-        if (near) excluded = 1;
+        int K = num_lights(p);
+        double tot = 0.0, A[4];
+        for (int l = 0; l < K; ++l) tot += (A[l] = light_area64(p, l));
+        F = 0.0;
+        for (int l = 0; l < K; ++l) {
+            double L[9];
+            int near;
+            for (int q = 0; q < 9; ++q) L[q] = light_k(p, l)[q];
+            double Fl = front_fraction(o, n, L, &near);
+            if (near) excluded = 1;
+            F += K == 1 ? Fl : A[l] / tot * Fl;
+        }
     } else if (p->mode == 2) {
         /* Solid-angle definition: the visible fraction of Omega_A(x_i) is
          * F_Omega - B_i with F_Omega = Omega_front / Omega_A the part of the

@@ -32,6 +32,8 @@ typedef struct {
     uint64_t seed;
     uint32_t sample;    /* sample index s */
     int32_t pad;
+    int32_t nlights;    /* shadows: number of rectangular lights (0 or 1: light[] only; up to 4) */
+    float more_lights[3 * 9]; /* lights 1..nlights-1, as light[] */
 } orc_params;
 
 typedef struct orc_scene orc_scene;
