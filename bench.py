@@ -74,6 +74,7 @@ OPS_SA_G = 24
 # square root and two products
 OPS_DI_G = OPS_SA_G + 8
 OPS_DENS["di"] = OPS_DENS["shadow"]
+OPS_DENS["shadow2"] = 2 * OPS_DENS["shadow"]  # the density summed over two lights
 
 
 def window_reuse_ops(r, mode):
@@ -93,6 +94,9 @@ WORKLOADS = {
                             sample_seed=1),
     # occluder-domain direct illumination (Lambertian receivers, albedo 0.8,
     # the light at radiance 100): same records and validation
+    # shadows of two rectangular lights (the 1 m light and a tilted 2 m x 1 m one)
+    "shadow2_1080p": dict(mode="shadow2", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2,
+                          sample_seed=1),
     "di_1080p": dict(mode="di", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2, sample_seed=1),
     "batched_16": dict(radius=2.0, window_r=3, sample_seed=1),
     "served": dict(radius=2.0, window_r=3, rate=400.0, budget_gib=4.0, slots=8),
@@ -208,7 +212,9 @@ def run_frame(args):
     scene = w.terrain_scene(cfg["scene_seed"])
     gb = w.render_gbuffer(scene, w.terrain_camera(W, H))
     light = w.terrain_light() if mode != "ao" else None
-    tmode = "shadow" if mode in ("shadow_sa", "di") else mode  # the mode records are traced (and validated) in
+    if mode == "shadow2":
+        light = w.two_lights()
+    tmode = "shadow" if mode in ("shadow_sa", "di", "shadow2") else mode  # the mode records are traced in
     log(f"[bench] inputs {time.time() - t0:.1f}s: {scene.ntris} tris, {W}x{H}, valid {gb.valid.mean():.3f}")
 
     dev = torch.device("cuda:0")
@@ -224,8 +230,13 @@ def run_frame(args):
     out_n = torch.empty((H, W), dtype=torch.float32, device=dev)
     out_b = torch.empty((H, W), dtype=torch.float32, device=dev)
     out_u = torch.empty((H, W), dtype=torch.float32, device=dev)
-    _, _, kind = ocr.sample_rays(dg, tmode, light, cfg["sample_seed"], 0)
-    rays = int((kind == 0).sum().item())
+    if mode == "shadow2":
+        # (the sampler entry point takes one light: count the traced samples of a trace)
+        ocr.trace_occluders(bvh, dg, tmode, R, light, cfg["sample_seed"], 0, occ)
+        rays = int(((occ.hit_u32() != ocr.HIT_SELF) & gb.valid).sum())
+    else:
+        _, _, kind = ocr.sample_rays(dg, tmode, light, cfg["sample_seed"], 0)
+        rays = int((kind == 0).sum().item())
     torch.cuda.synchronize()
     log(f"[bench] bvh {info.nnodes} nodes depth {info.depth} built in {info.build_ms:.0f} ms; {rays} traced rays/step")
 
@@ -338,7 +349,8 @@ def run_frame(args):
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: terrain 512x512 cells + 2000 icospheres ({scene.ntris} tris), "
                                f"{W}x{H}, 1 spp, R={R} m, 7x7 window, no-reuse + biased + unbiased"
-                               + {"shadow_sa": ", shadows under the solid-angle definition",
+                               + {"shadow2": ", shadows of two rectangular lights",
+                                  "shadow_sa": ", shadows under the solid-angle definition",
                                   "di": ", occluder-domain direct illumination"}.get(mode, ""),
                    "global_batch": 1, "seq_len": W * H, "parallelism": "single-gpu"},
         "kernels_ms": {k: round(v, 4) for k, v in per.items()},
@@ -352,7 +364,7 @@ def run_frame(args):
         "reuse_roofline": dict(bound="alu", achieved=round(reuse_tops, 3), peak=round(VALU_PEAK_TOPS, 1),
                                unit="TFLOP/s", frac=round(reuse_tops / VALU_PEAK_TOPS, 4),
                                hbm_gbs=round(reuse_gbs, 1), hbm_frac=round(reuse_gbs / HBM_PEAK_GBS, 4),
-                               kernel=f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2, 'di': 3}[mode]}, false>",
+                               kernel=f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2, 'di': 3, 'shadow2': 1}[mode]}, false>",
                                ops_per_candidate=window_reuse_ops(r, mode)),
         "rays_per_step": rays,
         "occluder_hits": hits,
@@ -365,7 +377,8 @@ def run_frame(args):
         "roofline": roof,
     }
 
-    result["trace_roofline"] = alu_roofline(
+    # (the counting trace takes one light)
+    result["trace_roofline"] = None if mode == "shadow2" else alu_roofline(
         counted_trace(ocr, torch, bvh, dg, tmode, R, light, cfg["sample_seed"], args.steps - 1), per["trace"],
         "trace_kernel")
     if args.workload == "ao_1080p":
@@ -639,6 +652,7 @@ def cpu_baseline(scene, gb, cfg, light, budget_s):
     sc = oracle.Scene(scene.V, scene.F)
     W, H, r = gb.width, gb.height, cfg["window_r"]
     mode, R = cfg["mode"], cfg["radius"]
+    mode = "shadow" if mode == "shadow2" else mode  # (the oracle takes the list of lights)
     rng = np.random.default_rng(7)
     done_px, ntiles = 0, 0
     t0 = time.perf_counter()

@@ -260,6 +260,34 @@ ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *g
                                         const ocr_rect_light *light, const ocr_reuse_params *params,
                                         void *workspace, size_t workspace_bytes, float *out, void *stream);
 
+/* Shadows of several rectangular lights (up to 4).  The paper shows a
+ * two-light result without giving its formulation; the quantity estimated
+ * here is the visible fraction of the lights' total emitting area,
+ *   sum_l (A_l / A_tot) Shadow_l(x_i),  A_l = |e_u x e_v| of light l.
+ * ocr_trace_occluders_lights: as ocr_trace_occluders(OCR_SHADOW), except
+ * that each sample first picks light l with probability A_l / A_tot (the
+ * first l whose FP32 running sum A_0 + ... + A_l exceeds u2 A_tot, u2 the
+ * third word of the sample's hash mapped as u0 and u1 are; the last light if
+ * rounding leaves none), so that its point is uniform over the union of the
+ * lights; one light gives exactly ocr_trace_occluders' samples and records.
+ * ocr_reuse_shadow_lights: as ocr_reuse_shadow with the induced density of
+ * an occluder summed over the lights (the area-weighted sum of the per-light
+ * densities of Eq. shadow-pdf) and F_i the area-weighted front fraction.
+ * lights: host array of nlights light descriptions (each checked as for one
+ * light).  Errors as the single-light calls, and OCR_ERR_INVALID_ARG for a
+ * NULL array or nlights outside [1, 4]. */
+ocr_status ocr_trace_occluders_lights(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_rect_light *lights,
+                                      int32_t nlights, uint64_t seed, uint32_t sample, ocr_occluders *out,
+                                      void *stream);
+ocr_status ocr_reuse_shadow_lights(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                   const ocr_rect_light *lights, int32_t nlights, const ocr_reuse_params *params,
+                                   void *workspace, size_t workspace_bytes, float *out, void *stream);
+/* ocr_validate_pairs for several lights (the pairs whose summed density is
+ * positive); arguments, workspace, stats and errors as ocr_validate_pairs. */
+ocr_status ocr_validate_pairs_lights(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                     const ocr_rect_light *lights, int32_t nlights, const ocr_reuse_params *params,
+                                     void *workspace, size_t workspace_bytes, uint64_t *stats, void *stream);
+
 /* Occluder-domain direct illumination (the appendix deriving Eq.
  * reapp-di-occluder-domain-compact) of a Lambertian receiver of albedo
  * `albedo` (rho) under the one-sided light emitting radiance `radiance`

@@ -110,6 +110,7 @@ EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occlu
            "ocr_trace_occluders_counted", "ocr_sample_rays",
            "ocr_workspace_bytes", "ocr_validate_pairs",
            "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_reuse_shadow_solid_angle", "ocr_reuse_direct_illumination",
+           "ocr_trace_occluders_lights", "ocr_reuse_shadow_lights", "ocr_validate_pairs_lights",
            "ocr_filter_values",
            "ocr_light_reuse_shadow", "ocr_scale", "ocr_last_error",
            "ocr_version",
@@ -164,6 +165,16 @@ def lib():
     L.ocr_reuse_direct_illumination.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ),
                                                 ctypes.POINTER(_Light), ctypes.c_float, ctypes.c_float,
                                                 ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
+    L.ocr_trace_occluders_lights.restype = i32
+    L.ocr_trace_occluders_lights.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Light), i32,
+                                             ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(_Occ), vp]
+    L.ocr_reuse_shadow_lights.restype = i32
+    L.ocr_reuse_shadow_lights.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), ctypes.POINTER(_Light),
+                                          i32, ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
+    L.ocr_validate_pairs_lights.restype = i32
+    L.ocr_validate_pairs_lights.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ),
+                                            ctypes.POINTER(_Light), i32, ctypes.POINTER(ReuseParams), vp,
+                                            ctypes.c_size_t, vp, vp]
     L.ocr_filter_values.restype = i32
     L.ocr_filter_values.argtypes = [ctypes.POINTER(_GBuffer), ctypes.POINTER(ReuseParams), vp, vp, vp]
     L.ocr_light_reuse_shadow.restype = i32
@@ -265,6 +276,18 @@ def light_struct(light) -> _Light:
     return s
 
 
+def _is_light_list(light) -> bool:
+    return isinstance(light, (list, tuple))
+
+
+def light_array(lights):
+    """A C array of light descriptions (shadows of several lights)."""
+    arr = (_Light * len(lights))()
+    for k, lt in enumerate(lights):
+        arr[k] = light_struct(lt)
+    return arr
+
+
 @dataclass
 class Occluders:
     dz: object   # torch.float32 [H,W,3]
@@ -331,6 +354,14 @@ def trace_occluders(bvh: BVH, gbuf: DeviceGBuffer, mode="ao", ao_radius=1.0, lig
     out = out or Occluders.empty(gbuf.height, gbuf.width, gbuf.prim.device)
     g = gbuf.c()
     o = out.c()
+    if _is_light_list(light):
+        # shadows of several lights (ocr_trace_occluders_lights)
+        if m != OCR_SHADOW:
+            raise ValueError("a list of lights needs mode 'shadow'")
+        arr = light_array(light)
+        _check(lib().ocr_trace_occluders_lights(bvh.h, ctypes.byref(g), arr, len(light), int(seed), int(sample),
+                                                ctypes.byref(o), _stream(stream)))
+        return out
     lp = ctypes.byref(light_struct(light)) if light is not None else None
     _check(lib().ocr_trace_occluders(bvh.h, ctypes.byref(g), m, float(ao_radius), lp, int(seed), int(sample),
                                      ctypes.byref(o), _stream(stream)))
@@ -389,6 +420,12 @@ def validate_pairs(bvh: BVH, gbuf: DeviceGBuffer, occ: Occluders, mode="ao", ao_
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     ws, nbytes = _workspace(gbuf, params, workspace)
     g, o = gbuf.c(), occ.c()
+    if _is_light_list(light):
+        arr = light_array(light)
+        _check(lib().ocr_validate_pairs_lights(bvh.h, ctypes.byref(g), ctypes.byref(o), arr, len(light),
+                                               ctypes.byref(params), _dptr(ws), nbytes,
+                                               _dptr(stats) if stats is not None else None, _stream(stream)))
+        return ws
     lp = ctypes.byref(light_struct(light)) if light is not None else None
     _check(lib().ocr_validate_pairs(bvh.h, ctypes.byref(g), ctypes.byref(o), m, float(ao_radius), lp,
                                     ctypes.byref(params), _dptr(ws), nbytes,
@@ -416,6 +453,14 @@ def reuse_shadow(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluders, light, pa
                                                   device=gbuf.prim.device)
     ws, nbytes = _workspace(gbuf, params, workspace)
     g, o = gbuf.c(), occ.c()
+    if _is_light_list(light):
+        # shadows of several lights (ocr_reuse_shadow_lights)
+        arr = light_array(light)
+        _check(lib().ocr_reuse_shadow_lights(bvh.h if bvh is not None else None, ctypes.byref(g), ctypes.byref(o),
+                                             arr, len(light), ctypes.byref(params),
+                                             _dptr(ws) if ws is not None else None, nbytes, _dptr(out),
+                                             _stream(stream)))
+        return out
     ls = light_struct(light)
     _check(lib().ocr_reuse_shadow(bvh.h if bvh is not None else None, ctypes.byref(g), ctypes.byref(o),
                                   ctypes.byref(ls), ctypes.byref(params), _dptr(ws) if ws is not None else None,

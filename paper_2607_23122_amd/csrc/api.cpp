@@ -12,6 +12,7 @@
 
 #include "api_internal.hpp"
 #include "bvh_build.hpp"
+#include "lights.hpp"
 
 using namespace ocr;
 
@@ -46,6 +47,8 @@ ocr_status check_gbuf(const ocr_gbuffer *g) {
 }
 
 ocr_status make_light(const ocr_rect_light *l, LightF &L) {
+    // e_u x e_v below in FP32 exactly as the sampler specifies it: no contraction
+#pragma clang fp contract(off)
     std::memset(&L, 0, sizeof L);
     if (!l) return fail(OCR_ERR_INVALID_ARG, "light is NULL");
     if (!finite3(l->center) || !finite3(l->edge_u) || !finite3(l->edge_v))
@@ -88,6 +91,18 @@ ocr_status check_params(const ocr_reuse_params *p) {
             return fail(OCR_ERR_INVALID_ARG, "group size %d not in {1,2,4,8}", p->group_n);
     } else {
         return fail(OCR_ERR_INVALID_ARG, "pattern %d out of range", p->pattern);
+    }
+    return OCR_OK;
+}
+
+ocr_status make_lights(const ocr_rect_light *lights, int32_t n, LightSetF &S) {
+    std::memset(&S, 0, sizeof S);
+    if (!lights) return fail(OCR_ERR_INVALID_ARG, "lights is NULL");
+    if (n < 1 || n > kMaxLights) return fail(OCR_ERR_INVALID_ARG, "%d lights not in [1,%d]", n, kMaxLights);
+    S.n = n;
+    for (int k = 0; k < n; ++k) {
+        ocr_status st = make_light(&lights[k], S.l[k]);
+        if (st) return st;
     }
     return OCR_OK;
 }
@@ -337,6 +352,66 @@ ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *g
     ocr_status st = make_light(light, L);
     if (st) return st;
     return reuse_common(bvh, gbuf, occ, kShadowSA, 1.0f, L, params, workspace, workspace_bytes, out, stream);
+}
+
+ocr_status ocr_trace_occluders_lights(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_rect_light *lights,
+                                      int32_t nlights, uint64_t seed, uint32_t sample, ocr_occluders *out,
+                                      void *stream) {
+    if (!bvh) return fail(OCR_ERR_INVALID_ARG, "bvh is NULL");
+    ocr_status st = check_gbuf(gbuf);
+    if (st) return st;
+    if (!out || !out->dz || !out->nz || !out->hit) return fail(OCR_ERR_INVALID_ARG, "occluder records incomplete");
+    LightSetF S;
+    if ((st = make_lights(lights, nlights, S))) return st;
+    hipError_t e = launch_trace_lights(bvh->dev, view(gbuf), S, fold_seed(seed), sample,
+                                       OccView{out->dz, out->nz, out->hit}, (hipStream_t)stream);
+    return e == hipSuccess ? OCR_OK : hip_fail(e, "trace launch");
+}
+
+ocr_status ocr_reuse_shadow_lights(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                   const ocr_rect_light *lights, int32_t nlights, const ocr_reuse_params *params,
+                                   void *workspace, size_t workspace_bytes, float *out, void *stream) {
+    ocr_status st = check_gbuf(gbuf);
+    if (st) return st;
+    if ((st = check_params(params))) return st;
+    if (!occ || !occ->dz || !occ->nz || !occ->hit) return fail(OCR_ERR_INVALID_ARG, "occluder records incomplete");
+    if (!out) return fail(OCR_ERR_INVALID_ARG, "out is NULL");
+    LightSetF S;
+    if ((st = make_lights(lights, nlights, S))) return st;
+    size_t need = ocr_workspace_bytes(gbuf->width, gbuf->height, params);
+    if (need > 0 && (!workspace || workspace_bytes < need))
+        return fail(OCR_ERR_INVALID_ARG, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    if (params->estimator == OCR_UNBIASED && !params->validated && !bvh)
+        return fail(OCR_ERR_INVALID_ARG, "unbiased reuse needs the BVH");
+    hipStream_t s = (hipStream_t)stream;
+    OccView ov{occ->dz, occ->nz, occ->hit};
+    GBufView gv = view(gbuf);
+    hipError_t e;
+    if (params->estimator == OCR_UNBIASED && !params->validated) {
+        e = launch_validate_lights(bvh->dev, gv, ov, S, *params, (uint32_t *)workspace, nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "validation launch");
+    }
+    e = launch_reuse_lights(gv, ov, S, *params, (const uint32_t *)workspace, out, s);
+    return e == hipSuccess ? OCR_OK : hip_fail(e, "reuse launch");
+}
+
+ocr_status ocr_validate_pairs_lights(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                     const ocr_rect_light *lights, int32_t nlights, const ocr_reuse_params *params,
+                                     void *workspace, size_t workspace_bytes, uint64_t *stats, void *stream) {
+    if (!bvh) return fail(OCR_ERR_INVALID_ARG, "bvh is NULL");
+    ocr_status st = check_gbuf(gbuf);
+    if (st) return st;
+    if ((st = check_params(params))) return st;
+    if (params->estimator != OCR_UNBIASED) return fail(OCR_ERR_INVALID_ARG, "validation is for OCR_UNBIASED");
+    if (!occ || !occ->dz || !occ->nz || !occ->hit) return fail(OCR_ERR_INVALID_ARG, "occluder records incomplete");
+    LightSetF S;
+    if ((st = make_lights(lights, nlights, S))) return st;
+    size_t need = ocr_workspace_bytes(gbuf->width, gbuf->height, params);
+    if (!workspace || workspace_bytes < need)
+        return fail(OCR_ERR_INVALID_ARG, "workspace of %zu bytes needed, %zu given", need, workspace_bytes);
+    hipError_t e = launch_validate_lights(bvh->dev, view(gbuf), OccView{occ->dz, occ->nz, occ->hit}, S, *params,
+                                          (uint32_t *)workspace, stats, (hipStream_t)stream);
+    return e == hipSuccess ? OCR_OK : hip_fail(e, "validation launch");
 }
 
 ocr_status ocr_reuse_direct_illumination(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,

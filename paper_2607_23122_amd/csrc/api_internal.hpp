@@ -28,6 +28,17 @@ ocr_status check_effect(int32_t mode, float ao_radius, const ocr_rect_light *lig
 
 inline GBufView view(const ocr_gbuffer *g) { return GBufView{g->pos, g->nrm, g->prim, g->width, g->height}; }
 
+// Several rectangular lights (lights.hpp): validated set, and the shadow
+// launchers that take it (trace.hip, reuse.hip).
+struct LightSetF;
+ocr_status make_lights(const ocr_rect_light *lights, int32_t n, LightSetF &S);
+hipError_t launch_trace_lights(const DeviceBVH &bvh, const GBufView &g, const LightSetF &L, uint32_t seed32,
+                               uint32_t sample, const OccView &out, hipStream_t st);
+hipError_t launch_validate_lights(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, const LightSetF &L,
+                                  const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats, hipStream_t st);
+hipError_t launch_reuse_lights(const GBufView &g, const OccView &occ, const LightSetF &L, const ocr_reuse_params &p,
+                               const uint32_t *bits, float *out, hipStream_t st);
+
 // The simple reuse baselines (baselines.hip).
 hipError_t launch_filter(const GBufView &g, const ocr_reuse_params &p, const float *in, float *out, hipStream_t st);
 hipError_t launch_light_reuse(const DeviceBVH &bvh, const GBufView &g, const LightF &L, uint32_t seed32,

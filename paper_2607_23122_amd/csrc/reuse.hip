@@ -10,6 +10,7 @@
 #include <atomic>
 
 #include "density.hpp"
+#include "lights.hpp"
 #include "ocr_common.hpp"
 #include "reuse_tile.hpp"
 #include "solid_angle.hpp"
@@ -25,8 +26,8 @@ __device__ inline void r_tile_of_block(int tiles_x, int ntiles, int &tx, int &ty
     ty = t / tiles_x;
 }
 
-template <int MODE, bool UNB>
-__global__ __launch_bounds__(kRBlock) void reuse_window_kernel(GBufView g, OccView occ, float R2, LightF L,
+template <int MODE, bool UNB, class LT = LightF>
+__global__ __launch_bounds__(kRBlock) void reuse_window_kernel(GBufView g, OccView occ, float R2, LT L,
                                                                const uint32_t *__restrict__ bits, int words, int R,
                                                                int dark_guard, int accumulate, float *out,
                                                                int tiles_x, int ntiles, float scale) {
@@ -34,19 +35,18 @@ __global__ __launch_bounds__(kRBlock) void reuse_window_kernel(GBufView g, OccVi
     int tx, ty;
     r_tile_of_block(tiles_x, ntiles, tx, ty);
     if (ty * tiles_x + tx >= ntiles) return;
-    reuse_window_tile<MODE, UNB>(smem, g, occ, R2, L, bits, words, R, dark_guard, accumulate, out, tx, ty, scale);
+    reuse_window_tile<MODE, UNB, LT>(smem, g, occ, R2, L, bits, words, R, dark_guard, accumulate, out, tx, ty, scale);
 }
 
 // Fixed groups.  Block = 32 x 8 pixels; the group shapes (1x1, 2x1, 2x2,
 // 4x2) tile it exactly.
-template <int MODE, bool UNB>
-__global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccView occ, float R2, LightF L,
+template <int MODE, bool UNB, class LT = LightF>
+__global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccView occ, float R2, LT L,
                                                               const uint32_t *__restrict__ bits, int words, int N,
                                                               int gw, int gh, int D, int dark_guard,
                                                               int accumulate, float *out, int tiles_x,
                                                               int ntiles, float scale) {
     __shared__ float s_o[3][kRBlock], s_n[3][kRBlock], s_dz[3][kRBlock], s_nz[3][kRBlock];
-    __shared__ float s_sh[3][kRBlock];
     __shared__ uint32_t s_hit[kRBlock];
     __shared__ uint8_t s_val[kRBlock];
     __shared__ uint32_t s_bits[kRBlock][2];
@@ -83,11 +83,8 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
             s_nz[a][tid] = nz[a];
         }
     }
-    RecvShadow rk = {0.f, 0.f, 0.f};
-    if (MODE != OCR_AO && valid) rk = recv_shadow(o, L);
-    s_sh[0][tid] = rk.hk;
-    s_sh[1][tid] = rk.ak;
-    s_sh[2][tid] = rk.bk;
+    // this lane's light terms as a receiver (its point, for several lights)
+    const auto rk = recv_of(o, L);
     s_hit[tid] = valid ? hit : OCR_HIT_MISS;
     s_val[tid] = valid;
     if (UNB) {
@@ -109,7 +106,7 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
             float nzj[3] = {s_nz[0][jt], s_nz[1][jt], s_nz[2][jt]};
             float w[3];
             rel_vec(oj, o, dzj, w);
-            p = MODE == OCR_AO ? dens_ao(w, n, nzj, R2) : dens_shadow(w, n, rk, nzj, L);
+            p = MODE == OCR_AO ? dens_ao(w, n, nzj, R2) : dens_light(w, n, rk, nzj, L);
             if (UNB && p > 0.0f) {
                 const int bidx = (ly - my + D) * SIDE + (lx - mx + D);
                 if (!((s_bits[jt][bidx >> 5] >> (bidx & 31)) & 1u)) p = 0.0f;
@@ -136,7 +133,7 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
         const float pij = s_p[tid][m];
         if (pij > 0.0f && P > 0.0f) {
             float term = pij * __builtin_amdgcn_rcpf(P);
-            if (MODE >= kShadowSA) {
+            if constexpr (MODE >= kShadowSA) {
                 // times g_ij (solid angle) or gd_ij (direct illumination) of
                 // this target and candidate m
                 const float oj[3] = {s_o[0][jt], s_o[1][jt], s_o[2][jt]};
@@ -151,30 +148,30 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     float F = 1.0f;
     bool dark = false;
     if (MODE != OCR_AO && valid) {
-        if (MODE == kShadowSA) {
+        if constexpr (MODE == kShadowSA) {
             F = sa_estimate(o, n, L, B);
             B = 0.0f;
-        } else if (MODE == kDI) {
+        } else if constexpr (MODE == kDI) {
             F = di_estimate(o, n, L, B, scale);
             B = 0.0f;
         } else {
-            F = front_fraction(o, n, L);
+            F = front_light(o, n, L);
         }
         dark = dark_guard && misses == 0;
     }
     out[gi] = finish(MODE, valid, B, F, dark, accumulate ? out[gi] : 0.0f, accumulate);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView occ, LightF L, int accumulate,
+template <int MODE, class LT = LightF>
+__global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView occ, LT L, int accumulate,
                                                           float *out, float scale) {
     const int64_t gi = (int64_t)blockIdx.x * kRBlock + threadIdx.x;
     if (gi >= (int64_t)g.w * g.h) return;
     const bool valid = g.prim[gi] != OCR_HIT_MISS;
     float v;
-    if (MODE == OCR_AO) {
+    if constexpr (MODE == OCR_AO) {
         v = (!valid || occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
-    } else if (MODE == OCR_SHADOW) {
+    } else if constexpr (MODE == OCR_SHADOW) {
         v = (valid && occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
     } else {
         // solid-angle definition / direct illumination, S(i) = {i}: the
@@ -210,8 +207,8 @@ __global__ void scale_kernel(float *out, int64_t n, float s) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int MODE, bool UNB>
-static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, const LightF &L, const uint32_t *bits,
+template <int MODE, bool UNB, class LT>
+static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, const LT &L, const uint32_t *bits,
                              int words, const ocr_reuse_params &p, float *out, float scale, hipStream_t st) {
     int tiles_x = (g.w + kWTX - 1) / kWTX, tiles_y = (g.h + kWTY - 1) / kWTY;
     int nt = tiles_x * tiles_y;
@@ -220,7 +217,7 @@ static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, co
     // threads may launch at once
     static std::atomic<size_t> attr_bytes{64 * 1024};
     if (lay.total > attr_bytes.load()) {
-        hipError_t e = hipFuncSetAttribute((const void *)reuse_window_kernel<MODE, UNB>,
+        hipError_t e = hipFuncSetAttribute((const void *)reuse_window_kernel<MODE, UNB, LT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.total);
         if (e != hipSuccess) return e;
         size_t cur = attr_bytes.load();
@@ -228,38 +225,38 @@ static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, co
         }
     }
     dim3 grid(((nt + 7) / 8) * 8), block(kRBlock);
-    hipLaunchKernelGGL((reuse_window_kernel<MODE, UNB>), grid, block, lay.total, st, g, occ, R2, L, bits, words,
+    hipLaunchKernelGGL((reuse_window_kernel<MODE, UNB, LT>), grid, block, lay.total, st, g, occ, R2, L, bits, words,
                        p.radius, p.dark_guard, p.accumulate, out, tiles_x, nt, scale);
     return hipSuccess;
 }
 
-template <int MODE, bool UNB>
-static void launch_grp(const GBufView &g, const OccView &occ, float R2, const LightF &L, const uint32_t *bits,
+template <int MODE, bool UNB, class LT>
+static void launch_grp(const GBufView &g, const OccView &occ, float R2, const LT &L, const uint32_t *bits,
                        int words, const ocr_reuse_params &p, float *out, float scale, hipStream_t st) {
     int gw, gh;
     group_dims(p.group_n, gw, gh);
     int tiles_x = (g.w + 31) / 32, tiles_y = (g.h + 7) / 8;
     int nt = tiles_x * tiles_y;
     dim3 grid(((nt + 7) / 8) * 8), block(kRBlock);
-    hipLaunchKernelGGL((reuse_group_kernel<MODE, UNB>), grid, block, 0, st, g, occ, R2, L, bits, words, p.group_n,
+    hipLaunchKernelGGL((reuse_group_kernel<MODE, UNB, LT>), grid, block, 0, st, g, occ, R2, L, bits, words, p.group_n,
                        gw, gh, pair_extent(p), p.dark_guard, p.accumulate, out, tiles_x, nt, scale);
 }
 
-template <int MODE>
-static hipError_t launch_mode(const GBufView &g, const OccView &occ, float R2, const LightF &L, const uint32_t *bits,
+template <int MODE, class LT = LightF>
+static hipError_t launch_mode(const GBufView &g, const OccView &occ, float R2, const LT &L, const uint32_t *bits,
                               int words, const ocr_reuse_params &q, bool unb, float *out, float scale,
                               hipStream_t st) {
     if (q.estimator == OCR_NOREUSE) {
         int64_t n = (int64_t)g.w * g.h;
         dim3 grid((unsigned)((n + kRBlock - 1) / kRBlock)), block(kRBlock);
-        hipLaunchKernelGGL(noreuse_kernel<MODE>, grid, block, 0, st, g, occ, L, q.accumulate, out, scale);
+        hipLaunchKernelGGL((noreuse_kernel<MODE, LT>), grid, block, 0, st, g, occ, L, q.accumulate, out, scale);
         return hipSuccess;
     }
     if (q.pattern == OCR_WINDOW)
-        return unb ? launch_win<MODE, true>(g, occ, R2, L, bits, words, q, out, scale, st)
-                   : launch_win<MODE, false>(g, occ, R2, L, bits, words, q, out, scale, st);
-    if (unb) launch_grp<MODE, true>(g, occ, R2, L, bits, words, q, out, scale, st);
-    else launch_grp<MODE, false>(g, occ, R2, L, bits, words, q, out, scale, st);
+        return unb ? launch_win<MODE, true, LT>(g, occ, R2, L, bits, words, q, out, scale, st)
+                   : launch_win<MODE, false, LT>(g, occ, R2, L, bits, words, q, out, scale, st);
+    if (unb) launch_grp<MODE, true, LT>(g, occ, R2, L, bits, words, q, out, scale, st);
+    else launch_grp<MODE, false, LT>(g, occ, R2, L, bits, words, q, out, scale, st);
     return hipSuccess;
 }
 
@@ -278,6 +275,17 @@ hipError_t launch_reuse(const GBufView &g, const OccView &occ, int mode, float R
         case kShadowSA: e = launch_mode<kShadowSA>(g, occ, R2, L, bits, words, q, unb, out, scale, st); break;
         default: e = launch_mode<kDI>(g, occ, R2, L, bits, words, q, unb, out, scale, st); break;
     }
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+// several lights (shadows only)
+hipError_t launch_reuse_lights(const GBufView &g, const OccView &occ, const LightSetF &L, const ocr_reuse_params &p,
+                               const uint32_t *bits, float *out, hipStream_t st) {
+    ocr_reuse_params q = p;
+    q.dark_guard = (p.estimator == OCR_BIASED && p.dark_guard) ? 1 : 0;
+    hipError_t e = launch_mode<OCR_SHADOW, LightSetF>(g, occ, 1.0f, L, bits, pair_words(p), q,
+                                                      p.estimator == OCR_UNBIASED, out, 1.0f, st);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }

@@ -18,6 +18,7 @@
 // arrive (bitwise reproducible) at ~2^-33 absolute error per term.
 #pragma once
 #include "density.hpp"
+#include "lights.hpp"
 #include "ocr_common.hpp"
 #include "solid_angle.hpp"
 
@@ -98,9 +99,9 @@ __device__ inline float weighted_term(float ratio, const float *s_o, const float
 
 // One kWTX x kWTY target tile (tx, ty) of the sliding-window estimator; every
 // thread of the block calls it.  `smem` holds win_layout(R, ...).total bytes.
-template <int MODE, bool UNB>
+template <int MODE, bool UNB, class LT = LightF>
 __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g, const OccView &occ, float R2,
-                                         const LightF &L, const uint32_t *__restrict__ bits, int words, int R,
+                                         const LT &L, const uint32_t *__restrict__ bits, int words, int R,
                                          int dark_guard, int accumulate, float *out, int tx, int ty,
                                          float scale = 1.0f) {
     const WinLayout lay = win_layout(R, MODE, UNB, words);
@@ -146,11 +147,12 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
             s_n[a * CELLS + c] = n[a];
         }
         if (MODE != OCR_AO) {
-            RecvShadow rk = {0.f, 0.f, 0.f};
-            if (valid) rk = recv_shadow(o, L);
-            s_sh[c] = rk.hk;
-            s_sh[CELLS + c] = rk.ak;
-            s_sh[2 * CELLS + c] = rk.bk;
+            // the receiver's light terms (its point, for several lights)
+            float v[3] = {0.f, 0.f, 0.f};
+            if (valid) recv_store(recv_of(o, L), v);
+            s_sh[c] = v[0];
+            s_sh[CELLS + c] = v[1];
+            s_sh[2 * CELLS + c] = v[2];
         }
         s_valid[c] = valid;
         s_miss[c] = valid && hit == OCR_HIT_MISS;
@@ -207,8 +209,8 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                 if (MODE == OCR_AO) {
                     p = dens_ao(w, nk, nzj, R2);
                 } else {
-                    RecvShadow rk = {s_sh[kc], s_sh[CELLS + kc], s_sh[2 * CELLS + kc]};
-                    p = dens_shadow(w, nk, rk, nzj, L);
+                    const float v[3] = {s_sh[kc], s_sh[CELLS + kc], s_sh[2 * CELLS + kc]};
+                    p = dens_light(w, nk, recv_load(v, L), nzj, L);
                 }
                 if (UNB && p > 0.0f) {
                     // candidate j's validation bit for the receiver at offset k - j
@@ -263,7 +265,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                 P += h;
                 if (tgt) {
                     float term = my_p * __builtin_amdgcn_rcpf(P);
-                    if (MODE >= kShadowSA)
+                    if constexpr (MODE >= kShadowSA)
                         term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ky0 + my_y, RW) + (kx0 + my_x),
                                                    oj, dzj, L);
                     atomicAdd(&s_B[(ky0 + my_y - R) * TX + (kx0 + my_x - R)],
@@ -292,7 +294,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                 const float pij = w_dens[__mul24(r2 + R, SIDE) + (t2 + R)];
                 if (pij > 0.0f && P > 0.0f) {
                     float term = pij * __builtin_amdgcn_rcpf(P);
-                    if (MODE >= kShadowSA)
+                    if constexpr (MODE >= kShadowSA)
                         term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ty0 + r2, RW) + (tx0 + t2), oj,
                                                    dzj, L);
                     atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],
@@ -317,16 +319,16 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         if (MODE != OCR_AO && valid) {
             float o[3] = {s_o[c], s_o[CELLS + c], s_o[2 * CELLS + c]};
             float n[3] = {s_n[c], s_n[CELLS + c], s_n[2 * CELLS + c]};
-            if (MODE == kShadowSA) {
+            if constexpr (MODE == kShadowSA) {
                 // F_Omega - (Area / Omega_A) B, as F - B below
                 F = sa_estimate(o, n, L, B);
                 B = 0.0f;
-            } else if (MODE == kDI) {
+            } else if constexpr (MODE == kDI) {
                 // (rho L_e / pi) (E - Area B), as F - B below
                 F = di_estimate(o, n, L, B, scale);
                 B = 0.0f;
             } else {
-                F = front_fraction(o, n, L);
+                F = front_light(o, n, L);
             }
             if (dark_guard) {
                 int misses = 0;

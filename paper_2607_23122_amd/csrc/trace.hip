@@ -29,8 +29,8 @@ __device__ inline void pixel_of_thread(int tx, int ty, int &px, int &py) {
     py = ty * kTile + (wv >> 1) * 8 + (ln >> 3);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g, float R, LightF L, uint32_t sd,
+template <int MODE, class LT = LightF>
+__global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g, float R, LT L, uint32_t sd,
                                                        uint32_t sample, OccView out, int tiles_x, int ntiles) {
     __shared__ uint32_t stack[kStackLds * kBlock];
     int tx, ty;
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g
     int px, py;
     pixel_of_thread(tx, ty, px, py);
     if (px >= g.w || py >= g.h) return;
-    trace_pixel<MODE>(bvh, g, R, L, sd, sample, out, px, py, stack + threadIdx.x, kBlock);
+    trace_pixel<MODE, false, LT>(bvh, g, R, L, sd, sample, out, px, py, stack + threadIdx.x, kBlock);
 }
 
 // The trace with its walk work counted (walks, node visits, box and
@@ -148,9 +148,9 @@ __device__ inline bool pair_receiver(const GBufView &g, int jx, int jy, int side
 // which adds the segments' useful work to stats[0..4].  Bounded to 7 waves
 // per SIMD (72 registers, a few spilled): at its natural 88 registers (5
 // waves) the walk ran 12% slower; 8 waves spilled more and lost on shadows.
-template <int MODE, bool COUNT>
+template <int MODE, bool COUNT, class LT = LightF>
 __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
-                                                                 LightF L, int D, int words, uint32_t *bits,
+                                                                 LT L, int D, int words, uint32_t *bits,
                                                                  const uint32_t *lists, uint32_t per_xcd,
                                                                  uint64_t *stats) {
     __shared__ uint32_t wnode[kBlock / 64][kStackTotal];
@@ -208,8 +208,7 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
                 if (MODE == OCR_AO) {
                     p = dens_ao(w, nk, nzj, R2);
                 } else {
-                    RecvShadow rk = recv_shadow(ok, L);
-                    p = dens_shadow(w, nk, rk, nzj, L);
+                    p = dens_light(w, nk, recv_of(ok, L), nzj, L);
                 }
                 want = p > 0.0f;
             }
@@ -265,9 +264,9 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
 // First-hit validation for fixed groups: one lane per (candidate m, receiver
 // k) pair of a group; block = 32 x 8 pixels, which the group shapes tile.
 // Bit (ky - my + D)(2D+1) + (kx - mx + D) of m's words, D = the group extent.
-template <int MODE>
+template <int MODE, class LT = LightF>
 __global__ __launch_bounds__(kBlock) void validate_group_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
-                                                                LightF L, int N, int gw, int gh, int D, int words,
+                                                                LT L, int N, int gw, int gh, int D, int words,
                                                                 uint32_t *bits, int tiles_x, int ntiles) {
     __shared__ uint32_t stack[kStackLds * kBlock];
     __shared__ uint32_t s_words[kBlock * 2];
@@ -308,8 +307,7 @@ __global__ __launch_bounds__(kBlock) void validate_group_kernel(DeviceBVH bvh, G
             if (MODE == OCR_AO) {
                 p = dens_ao(w, nk, nzj, R2);
             } else {
-                RecvShadow rk = recv_shadow(ok, L);
-                p = dens_shadow(w, nk, rk, nzj, L);
+                p = dens_light(w, nk, recv_of(ok, L), nzj, L);
             }
             if (p > 0.0f) {
                 TRay r;
@@ -408,9 +406,10 @@ hipError_t launch_trace_count(const DeviceBVH &bvh, const GBufView &g, int mode,
     return hipGetLastError();
 }
 
-hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, int mode, float R,
-                           const LightF &L, const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats,
-                           hipStream_t st) {
+template <class LT>
+static hipError_t launch_validate_t(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, int mode, float R,
+                                    const LT &L, const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats,
+                                    hipStream_t st) {
     const int D = pair_extent(p), words = pair_words(p);
     if (p.pattern == OCR_WINDOW) {
         int tiles_x;
@@ -425,8 +424,8 @@ hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccVie
         // persistent grid: a multiple of 8 blocks (one share per XCD), ~32 per CU
         dim3 grid(8192), block(kBlock);
 #define OCR_VAL(M, C)                                                                                        \
-    hipLaunchKernelGGL((validate_window_kernel<M, C>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, \
-                       lists, per_xcd, stats)
+    hipLaunchKernelGGL((validate_window_kernel<M, C, LT>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, \
+                       bits, lists, per_xcd, stats)
         if (mode == OCR_AO) {
             if (stats) OCR_VAL(OCR_AO, true);
             else OCR_VAL(OCR_AO, false);
@@ -441,12 +440,34 @@ hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccVie
         int tiles_x = (g.w + 31) / 32, tiles_y = (g.h + 7) / 8, nt = tiles_x * tiles_y;
         dim3 grid(grid_for(nt)), block(kBlock);
         if (mode == OCR_AO)
-            hipLaunchKernelGGL(validate_group_kernel<OCR_AO>, grid, block, 0, st, bvh, g, occ, R * R, L, p.group_n,
-                               gw, gh, D, words, bits, tiles_x, nt);
+            hipLaunchKernelGGL((validate_group_kernel<OCR_AO, LT>), grid, block, 0, st, bvh, g, occ, R * R, L,
+                               p.group_n, gw, gh, D, words, bits, tiles_x, nt);
         else
-            hipLaunchKernelGGL(validate_group_kernel<OCR_SHADOW>, grid, block, 0, st, bvh, g, occ, R * R, L,
+            hipLaunchKernelGGL((validate_group_kernel<OCR_SHADOW, LT>), grid, block, 0, st, bvh, g, occ, R * R, L,
                                p.group_n, gw, gh, D, words, bits, tiles_x, nt);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, int mode, float R,
+                           const LightF &L, const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats,
+                           hipStream_t st) {
+    return launch_validate_t(bvh, g, occ, mode, R, L, p, bits, stats, st);
+}
+
+// several lights (shadows only)
+hipError_t launch_validate_lights(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, const LightSetF &L,
+                                  const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats, hipStream_t st) {
+    return launch_validate_t(bvh, g, occ, OCR_SHADOW, 1.0f, L, p, bits, stats, st);
+}
+
+hipError_t launch_trace_lights(const DeviceBVH &bvh, const GBufView &g, const LightSetF &L, uint32_t seed32,
+                               uint32_t sample, const OccView &out, hipStream_t st) {
+    int tiles_x;
+    int nt = ntiles_for(g, tiles_x);
+    dim3 grid(grid_for(nt)), block(kBlock);
+    hipLaunchKernelGGL((trace_kernel<OCR_SHADOW, LightSetF>), grid, block, 0, st, bvh, g, 1.0f, L, seed32, sample,
+                       out, tiles_x, nt);
     return hipGetLastError();
 }
 

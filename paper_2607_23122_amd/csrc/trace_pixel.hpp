@@ -1,6 +1,7 @@
 // Per-pixel first-hit trace (step 1 of App. D / App. H), shared by the
 // per-frame trace kernel and the batched schedule.
 #pragma once
+#include "lights.hpp"
 #include "ocr_common.hpp"
 #include "traverse.hpp"
 
@@ -14,9 +15,10 @@ __device__ inline void load3(const float *p, int64_t i, float v[3]) {
 
 // Sample pixel (px, py), trace its ray and write its occluder record.
 // `stack` is this lane's LDS stack, `stride` apart between entries.  With
-// COUNT the walk's work is added to *ws.
-template <int MODE, bool COUNT = false>
-__device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, float R, const LightF &L, uint32_t sd,
+// COUNT the walk's work is added to *ws.  LT: one light (LightF) or several
+// (LightSetF, shadows).
+template <int MODE, bool COUNT = false, class LT = LightF>
+__device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, float R, const LT &L, uint32_t sd,
                                    uint32_t sample, const OccView &out, int px, int py, uint32_t *stack,
                                    int stride, WalkStats *ws = nullptr) {
     int64_t i = (int64_t)py * g.w + px;
@@ -35,11 +37,12 @@ __device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, floa
         tmax = R;
     } else {
         float y[3];
-        light_point((uint32_t)px, (uint32_t)py, sample, sd, L, y);
+        LightF Lc;  // the light the sample lies on
+        pick_light((uint32_t)px, (uint32_t)py, sample, sd, L, y, Lc);
         d[0] = y[0] - o[0];
         d[1] = y[1] - o[1];
         d[2] = y[2] - o[2];
-        if (!shadow_traced(n, o, d, L)) {
+        if (!shadow_traced(n, o, d, Lc)) {
             out.hit[i] = OCR_HIT_SELF;
             return;
         }

@@ -365,6 +365,17 @@ def terrain_light(hmax: float = 4.0) -> RectLight:
                      np.array([0.0, 0.0, 1.0], np.float32))
 
 
+def two_lights(hmax: float = 4.0):
+    """The terrain light and a second, 2 m x 1 m rectangle 10 m above the
+    highest terrain point, rotated about the vertical and tilted (its edges
+    are not axis-aligned), facing down: the shadows-of-several-lights input."""
+    th = 0.5
+    eu = np.array([np.cos(th), 0.1, np.sin(th)], np.float32) * np.float32(2.0)
+    ev = np.cross(np.array([0.0, -1.0, 0.0]), eu.astype(np.float64))
+    ev = (ev / np.linalg.norm(ev)).astype(np.float32)
+    return [terrain_light(hmax), RectLight(np.array([25.0, hmax + 10.0, 30.0], np.float32), eu, ev)]
+
+
 _CACHE: dict = {}
 
 
