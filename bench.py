@@ -107,7 +107,7 @@ SERVED_SCENES = [dict(seed=100 + i, cells=c, spheres=n)
 SERVED_SIZES = [(1280, 720), (1920, 1080), (2560, 1440)]
 
 
-TRACE_TU = ["density.hpp", "ocr_common.hpp", "trace.hip", "trace_pixel.hpp", "traverse.hpp"]
+TRACE_TU = ["density.hpp", "lights.hpp", "ocr_common.hpp", "trace.hip", "trace_pixel.hpp", "traverse.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ao_1080p_hbm_traffic.md")
 
 
@@ -326,7 +326,9 @@ def run_frame(args):
     reuse_tops = hits * window_reuse_ops(r, mode) / (per["reuse_biased"] * 1e-3) / 1e12
     if dominant == "validate":
         # traversal and densities are VALU-bound: price the useful operations
-        kname = f"ocr::validate_window_kernel<{0 if mode == 'ao' else 1}, false>"  # one validation per definition
+        # one validation per light type (single-light kernels carry LightF)
+        lt = "ocr::LightSetF" if mode == "shadow2" else "ocr::LightF"
+        kname = f"ocr::validate_window_kernel<{0 if mode == 'ao' else 1}, false, {lt}>"
         traffic = measured_traffic(kname) if args.workload == "ao_1080p" else None
         roof = dict(bound="alu", achieved=round(val_tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
                     frac=round(val_tops / VALU_PEAK_TOPS, 4), traffic=traffic, kernel=kname)
@@ -364,7 +366,8 @@ def run_frame(args):
         "reuse_roofline": dict(bound="alu", achieved=round(reuse_tops, 3), peak=round(VALU_PEAK_TOPS, 1),
                                unit="TFLOP/s", frac=round(reuse_tops / VALU_PEAK_TOPS, 4),
                                hbm_gbs=round(reuse_gbs, 1), hbm_frac=round(reuse_gbs / HBM_PEAK_GBS, 4),
-                               kernel=f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2, 'di': 3, 'shadow2': 1}[mode]}, false>",
+                               kernel=f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2, 'di': 3, 'shadow2': 1}[mode]}, false, "
+                                      f"{'ocr::LightSetF' if mode == 'shadow2' else 'ocr::LightF'}>",
                                ops_per_candidate=window_reuse_ops(r, mode)),
         "rays_per_step": rays,
         "occluder_hits": hits,
@@ -382,7 +385,7 @@ def run_frame(args):
         counted_trace(ocr, torch, bvh, dg, tmode, R, light, cfg["sample_seed"], args.steps - 1), per["trace"],
         "trace_kernel")
     if args.workload == "ao_1080p":
-        result["trace_roofline"]["traffic"] = measured_traffic("ocr::trace_kernel<0>")
+        result["trace_roofline"]["traffic"] = measured_traffic("ocr::trace_kernel<0, ocr::LightF>")
     if args.cpu_baseline == "on":
         result["cpu_baseline"] = cpu_baseline(scene, gb, cfg, light, args.cpu_seconds)
     return result
