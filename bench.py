@@ -311,6 +311,12 @@ def run_frame(args):
     torch.cuda.synchronize()
     walks, nodes, box_tests, tri_tests, segments = [int(v) for v in stats.cpu().tolist()]
     valid_px = int(gb.valid.sum())
+    # reported statistics: the fraction of valid pixels whose raw estimate is
+    # negative (outputs are not clamped, and a sum of reuse weights can exceed
+    # the unoccluded value)
+    vmask = torch.from_numpy(gb.valid).to(dev)
+    negative = {k: round(float((o[vmask] < 0).float().mean().item()), 6)
+                for k, o in (("biased", out_b), ("unbiased", out_u))}
     hits = int((occ.hit_u32() < ocr.HIT_SELF).sum())
     # Algorithmic bytes of one reuse launch: the G-buffer (pos, nrm, prim:
     # 28 B/px), the records (dz, nz, hit: 28 B/px) and the output (4 B/px).
@@ -370,6 +376,7 @@ def run_frame(args):
                                       f"{'ocr::LightSetF' if mode == 'shadow2' else 'ocr::LightF'}>",
                                ops_per_candidate=window_reuse_ops(r, mode)),
         "rays_per_step": rays,
+        "negative_pixel_fraction": negative,
         "occluder_hits": hits,
         "valid_pixels": valid_px,
         "validation": {"walks": walks, "node_visits": nodes, "box_tests": box_tests, "tri_tests": tri_tests,

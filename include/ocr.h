@@ -442,7 +442,13 @@ typedef struct ocr_server ocr_server;
  *   poll_us:          completion polling interval of the worker (0 = 20)
  *   mock:             1 = no device work: each request "runs" for
  *                     mock_ns_per_pixel * w * h, for scheduler tests on a
- *                     machine without a GPU (no HIP call is made) */
+ *                     machine without a GPU (no HIP call is made)
+ *   fault_every:      fault injection for tests of failure handling: 0 = off;
+ *                     k > 0 = every k-th admission finds its request's launch
+ *                     failing with OCR_ERR_OOM after its memory was taken.
+ *                     The request then completes with that status, holds no
+ *                     arena memory and writes no output, and the server goes
+ *                     on with the next one (the path any launch failure takes) */
 typedef struct {
     size_t hbm_budget_bytes;
     int32_t max_slots;
@@ -450,6 +456,7 @@ typedef struct {
     int32_t poll_us;
     int32_t mock;
     double mock_ns_per_pixel;
+    int32_t fault_every;
 } ocr_server_options;
 
 /* A frame request.  scene_id / view select a resident G-buffer.  out: device
@@ -487,6 +494,7 @@ typedef struct {
     int64_t max_in_flight;
     double p50_ms, p99_ms, mean_ms, max_ms;  /* arrival-to-completion latency of completed requests */
     double frames_per_s;                     /* completed / (last completion - first arrival) */
+    int64_t failed;                          /* completed with an error status (counted in completed) */
 } ocr_server_stats;
 
 /* Create a server on the current device (mock: no device).  Starts one worker

@@ -82,7 +82,8 @@ class PlanInfo(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32), ("max_queue", ctypes.c_int32),
-                ("poll_us", ctypes.c_int32), ("mock", ctypes.c_int32), ("mock_ns_per_pixel", ctypes.c_double)]
+                ("poll_us", ctypes.c_int32), ("mock", ctypes.c_int32), ("mock_ns_per_pixel", ctypes.c_double),
+                ("fault_every", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -103,7 +104,7 @@ class ServerStats(ctypes.Structure):
                 ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64), ("waited_for_memory", ctypes.c_int64),
                 ("peak_bytes", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("max_in_flight", ctypes.c_int64),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
-                ("max_ms", ctypes.c_double), ("frames_per_s", ctypes.c_double)]
+                ("max_ms", ctypes.c_double), ("frames_per_s", ctypes.c_double), ("failed", ctypes.c_int64)]
 
 
 EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders",
@@ -685,12 +686,13 @@ def request(scene_id: int, view: int, mode="ao", ao_radius=1.0, light=None, seed
 
 class Server:
     """Served loop (ocr_server_*): resident scenes, HBM-budget admission,
-    concurrent slots.  mock=True runs the scheduler without a device."""
+    concurrent slots.  mock=True runs the scheduler without a device;
+    fault_every=k makes every k-th admission fail (failure-handling tests)."""
 
     def __init__(self, budget_bytes: int, slots: int = 8, max_queue: int = 0, poll_us: int = 0,
-                 mock: bool = False, mock_ns_per_pixel: float = 0.0):
+                 mock: bool = False, mock_ns_per_pixel: float = 0.0, fault_every: int = 0):
         opt = ServerOptions(int(budget_bytes), int(slots), int(max_queue), int(poll_us), 1 if mock else 0,
-                            float(mock_ns_per_pixel))
+                            float(mock_ns_per_pixel), int(fault_every))
         h = ctypes.c_void_p()
         _check(lib().ocr_server_create(ctypes.byref(opt), ctypes.byref(h)))
         self.h = h

@@ -134,7 +134,8 @@ struct ocr_server {
     std::thread worker;
     bool stop = false;
     uint64_t next_ticket = 1;
-    int64_t submitted = 0, completed = 0, refused = 0, waited_for_memory = 0, max_in_flight = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, refused = 0, waited_for_memory = 0, max_in_flight = 0;
+    int64_t admissions = 0;
     size_t peak_used = 0;
     double first_arrival_ms = -1.0, last_done_ms = 0.0;
 };
@@ -189,6 +190,7 @@ void finish(ocr_server *s, Slot &sl, double end_ms, ocr_status st) {
     }
     s->results.push_back(res);
     if (st == OCR_OK) s->latencies.push_back(res.latency_ms);
+    else s->failed++;
     s->completed++;
     s->last_done_ms = std::max(s->last_done_ms, end_ms);
     sl.busy = false;
@@ -240,7 +242,9 @@ void worker_loop(ocr_server *s) {
             int64_t inflight = 0;
             for (Slot &sl : s->slots) inflight += sl.busy;
             s->max_in_flight = std::max(s->max_in_flight, inflight);
-            if (s->opt.mock) {
+            if (s->opt.fault_every > 0 && ++s->admissions % s->opt.fault_every == 0) {
+                finish(s, *idle, clock_ms(), OCR_ERR_OOM);  // injected fault
+            } else if (s->opt.mock) {
                 idle->mock_end_ms = idle->start_ms + s->opt.mock_ns_per_pixel * 1e-6 * idle->job.w * idle->job.h;
             } else {
                 const ocr_status rc = launch_job(s, *idle);
@@ -285,6 +289,7 @@ ocr_status ocr_server_create(const ocr_server_options *opt, ocr_server **out) {
     if (opt->max_slots < 1 || opt->max_slots > 64) return fail(OCR_ERR_INVALID_ARG, "slots %d not in 1..64", opt->max_slots);
     if (opt->max_queue < 0 || opt->poll_us < 0) return fail(OCR_ERR_INVALID_ARG, "negative queue limit or poll interval");
     if (opt->mock && !(opt->mock_ns_per_pixel >= 0.0)) return fail(OCR_ERR_INVALID_ARG, "bad mock service time");
+    if (opt->fault_every < 0) return fail(OCR_ERR_INVALID_ARG, "negative fault_every");
     ocr_server *s = new (std::nothrow) ocr_server;
     if (!s) return fail(OCR_ERR_OOM, "server allocation failed");
     s->opt = *opt;
@@ -424,6 +429,7 @@ ocr_status ocr_server_get_stats(ocr_server *s, ocr_server_stats *st) {
     st->peak_bytes = (int64_t)s->peak_used;
     st->budget_bytes = (int64_t)s->arena->size();
     st->max_in_flight = s->max_in_flight;
+    st->failed = s->failed;
     std::vector<double> l = s->latencies;
     if (!l.empty()) {
         std::sort(l.begin(), l.end());

@@ -254,3 +254,36 @@ def test_shadow_no_reuse_converges(shadow_inconsistent):
     sc, gb, refs, light, kind = shadow_inconsistent
     z = _z_scores(sc, gb, oracle.params("shadow", "none", light=light, seed=7), refs)
     assert np.abs(z).max() < Z_MAX, z
+
+
+# --------------------------------------------------------------------------
+# Partition of unity of the balance heuristic
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("est", ["biased", "unbiased"])
+@pytest.mark.parametrize("n", [2, 4, 8])
+def test_group_weights_partition_unity(est, n):
+    # Within a fixed group every target shares the denominators P(j), so
+    # sum_{i in group} p_i(j) / P(j) = 1 for each candidate with P(j) > 0:
+    # the group's B_i sum to its number of such candidates.  A hit whose own
+    # density is positive has P(j) >= p_j(j) > 0, so on a scene where every
+    # hit lies within R of its own receiver that is its number of hits.
+    s = w.boxes_scene(1)
+    gb = w.render_gbuffer(s, w.boxes_camera(64, 64))
+    sc = oracle.Scene(s.V, s.F)
+    p = oracle.params("ao", est, "group", group_n=n, ao_radius=1.0, seed=6)
+    rec, r = oracle.frame(sc, gb, p)
+    gw = 4 if n == 8 else (2 if n >= 2 else 1)
+    gh = 2 if n >= 4 else 1
+    H, W = gb.prim.shape
+    checked = 0
+    for y0 in range(0, H, gh):
+        for x0 in range(0, W, gw):
+            sl = (slice(y0, y0 + gh), slice(x0, x0 + gw))
+            valid = gb.valid[sl]
+            if not valid.any() or (r.nvar[sl][valid] != 1).any():
+                continue
+            B = (1.0 - r.value[sl][valid]).sum()
+            hits = (rec.hit[sl][valid] < oracle.SELF).sum()
+            assert B == pytest.approx(hits, abs=1e-9)
+            checked += 1
+    assert checked > 100

@@ -2,7 +2,8 @@
 mock executor makes no HIP call and lets each request occupy its slot for a
 modelled time (mock_ns_per_pixel * w * h).  Covers FIFO admission, HBM-budget
 waiting and refusal, overlap of requests in flight, queue limits, server-held
-outputs and the latency statistics."""
+outputs, the latency statistics, and injected launch failures (the failing
+request reports its error and gives back its memory; the server carries on)."""
 import time
 
 import numpy as np
@@ -11,8 +12,9 @@ import pytest
 import paper_2607_23122_amd as ocr
 
 
-def _server(budget, slots, ns_per_px=0.0, max_queue=0):
-    return ocr.Server(budget, slots=slots, max_queue=max_queue, poll_us=50, mock=True, mock_ns_per_pixel=ns_per_px)
+def _server(budget, slots, ns_per_px=0.0, max_queue=0, fault_every=0):
+    return ocr.Server(budget, slots=slots, max_queue=max_queue, poll_us=50, mock=True, mock_ns_per_pixel=ns_per_px,
+                      fault_every=fault_every)
 
 
 def _views(sizes):
@@ -167,3 +169,43 @@ def test_destroy_with_queued_work():
     for i in range(10):
         srv.submit(_req(sid, 0, seed=i))
     srv.destroy()  # drains before returning
+
+
+def test_injected_faults_release_memory_and_server_carries_on():
+    w, h = 32, 32
+    state = 2 * ((12 * w * h + 255) // 256 * 256) + (4 * w * h + 255) // 256 * 256
+    outb = (4 * w * h + 255) // 256 * 256
+    # room for one request and one held output: a failed request that kept
+    # its state or output would leave every later one waiting for ever
+    srv = _server(state + outb, slots=2, ns_per_px=200.0, fault_every=3)
+    sid = srv.add_scene(None, _views([(w, h)]))
+    results = []
+    for i in range(9):
+        t = srv.submit(_req(sid, 0, seed=i, out=None))
+        r = _wait_done(srv, 1)[0]
+        assert r.ticket == t
+        results.append(r)
+        if r.status == 0:
+            srv.release(t)  # make room for the next
+        else:
+            with pytest.raises(ocr.OcrError):
+                srv.release(t)  # a failed request holds no output
+    assert [r.status for r in results] == [0, 0, -2] * 3  # OCR_ERR_OOM on every third admission
+    st = srv.stats()
+    assert st.completed == 9 and st.failed == 3 and st.queued == 0 and st.in_flight == 0
+    assert st.peak_bytes <= st.budget_bytes
+    # latency statistics cover the successful requests only
+    ok = sorted(r.latency_ms for r in results if r.status == 0)
+    assert st.max_ms == pytest.approx(ok[-1])
+    # a burst with faults: every request completes, the failures in admission order
+    for i in range(12):
+        srv.submit(_req(sid, 0, seed=i))
+    res = sorted(_wait_done(srv, 12), key=lambda r: r.ticket)
+    assert [r.status for r in res] == [0, 0, -2] * 4
+    assert srv.stats().failed == 7
+    srv.destroy()
+
+
+def test_fault_every_must_not_be_negative():
+    with pytest.raises(ocr.OcrError):
+        _server(1 << 20, slots=1, fault_every=-1)
