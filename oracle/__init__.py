@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("estimator", ctypes.c_int32), ("pattern", ctypes.c_int32),
                 ("radius", ctypes.c_int32), ("group_n", ctypes.c_int32), ("dark_guard", ctypes.c_int32),
                 ("ao_radius", ctypes.c_double), ("light", ctypes.c_float * 9), ("seed", ctypes.c_uint64),
-                ("sample", ctypes.c_uint32), ("pad", ctypes.c_int32), ("nlights", ctypes.c_int32),
+                ("sample", ctypes.c_uint32), ("light_pdf", ctypes.c_int32), ("nlights", ctypes.c_int32),
                 ("more_lights", ctypes.c_float * 27)]
 
 
@@ -68,6 +68,14 @@ def params(mode="ao", estimator="biased", pattern="window", radius=2, group_n=8,
                 else:
                     p.more_lights[9 * (k - 1) + i] = float(la[i])
         p.nlights = len(lights)
+        # the emitter density samples are drawn from (0 uniform, 1 bilinear);
+        # the bilinear density is built for one light and estimators 0-2
+        pdfs = [int(getattr(lt, "pdf", 0)) for lt in lights]
+        if any(pdfs):
+            if len(lights) > 1 or mode == "ao" or p.estimator > 2 or pdfs[0] != 1:
+                raise ValueError("the bilinear emitter density takes one light and the no-reuse, "
+                                 "biased or unbiased estimator")
+            p.light_pdf = 1
     p.seed = int(seed)
     p.sample = int(sample)
     return p
@@ -118,6 +126,8 @@ def _load():
     lib.orc_di_quadrature.argtypes = [vp, vp, vp, vp, ctypes.c_uint32, i32]
     lib.orc_sa_factor.restype = f64
     lib.orc_sa_factor.argtypes = [vp, vp, vp, vp]
+    lib.orc_light_q.restype = f64
+    lib.orc_light_q.argtypes = [vp, vp, f64, f64]
     lib.orc_pcg4d_first.restype = ctypes.c_uint32
     lib.orc_pcg4d_first.argtypes = [ctypes.c_uint32] * 4 + [vp]
     lib.orc_num_threads.restype = i32
@@ -328,6 +338,14 @@ def sa_factor(o, n, z, light) -> float:
     a = [np.ascontiguousarray(v, np.float64) for v in (o, n, z)]
     la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
     return float(_load().orc_sa_factor(*[_ptr(v) for v in a], _ptr(la)))
+
+
+def light_q(o, light, a, b) -> float:
+    """Area p_A(y | x) of the bilinear emitter density of receiver point o at
+    light coordinates (a, b) of y (|a|, |b| <= 1/2)."""
+    oa = np.ascontiguousarray(o, np.float64)
+    la = np.ascontiguousarray(light.as_array() if hasattr(light, "as_array") else light, np.float64)
+    return float(_load().orc_light_q(_ptr(oa), _ptr(la), float(a), float(b)))
 
 
 def emitter_irradiance(o, n, light) -> float:

@@ -217,6 +217,61 @@ static int light_point_multi(uint32_t px, uint32_t py, uint32_t s, uint32_t sd, 
     return l;
 }
 
+/* General emitter-area density p_A(y | x) (App., general area-domain
+ * sampling density): besides the uniform density 1 / Area, the bilinear
+ * density of a receiver point o.  Its corner weights are the shape of the
+ * solid-angle density cos(theta_y) / |o - y|^2 at the four corners, i.e.
+ * 1 / |o - y_k|^3 (cos(theta_y) = h / |o - y| with the same height h for every
+ * point of the rectangle), and over the rectangle it interpolates them
+ * bilinearly in the light coordinates (a, b).  It depends on the receiver, so
+ * reuse evaluates it at every receiver of a candidate.
+ *
+ * FP32 sample specification.  Corners k = 0..3 at (a_k, b_k) = (-1/2,-1/2),
+ * (1/2,-1/2), (-1/2,1/2), (1/2,1/2); |o - y_k|^2 clamped below at 2^-40; the
+ * weights divided by their maximum. */
+static void bilinear_weights32(const float *L, const float o[3], float w[4]) {
+    float m = 0.0f;
+    for (int k = 0; k < 4; ++k) {
+        float ak = (k & 1) ? 0.5f : -0.5f, bk = (k & 2) ? 0.5f : -0.5f, d[3];
+        for (int c = 0; c < 3; ++c) d[c] = o[c] - fmaf(bk, L[6 + c], fmaf(ak, L[3 + c], L[c]));
+        float d2 = fmaxf(fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0])), 0x1p-40f);
+        w[k] = 1.0f / (d2 * sqrtf(d2));
+        m = fmaxf(m, w[k]);
+    }
+    for (int k = 0; k < 4; ++k) w[k] = w[k] / m;
+}
+
+/* Inverse of the CDF of the density proportional to (1 - t) e0 + t e1 on
+ * [0, 1] (e0, e1 >= 0): the root in [0, 1] of (e1 - e0) t^2 + 2 e0 t =
+ * xi (e0 + e1), in the form without cancellation,
+ * t = xi (e0 + e1) / (e0 + sqrt((1 - xi) e0^2 + xi e1^2)). */
+static float sample_linear32(float xi, float e0, float e1) {
+    float r = sqrtf((1.0f - xi) * (e0 * e0) + xi * (e1 * e1));
+    float den = e0 + r;
+    if (!(den > 0.0f)) return 0.0f;
+    float t = xi * (e0 + e1) / den;
+    return fminf(t, 1.0f);
+}
+
+/* A point from the bilinear density of o: v (= b + 1/2) from its marginal,
+ * linear between the corner sums w_0 + w_1 (v = 0) and w_2 + w_3 (v = 1), with
+ * h[1]; then u (= a + 1/2) from the conditional at that v, linear between the
+ * edge weights interpolated at v, with h[0]; the point as for uniform
+ * sampling. */
+static void light_point_bilinear(uint32_t px, uint32_t py, uint32_t s, uint32_t sd, const float *L,
+                                 const float o[3], float y[3]) {
+    uint32_t h[4] = {px, py, s, sd};
+    pcg4d(h);
+    float w[4];
+    bilinear_weights32(L, o, w);
+    float tv = sample_linear32(unit24(h[1]), w[0] + w[1], w[2] + w[3]);
+    float f0 = (1.0f - tv) * w[0] + tv * w[2];
+    float f1 = (1.0f - tv) * w[1] + tv * w[3];
+    float tu = sample_linear32(unit24(h[0]), f0, f1);
+    float a = tu - 0.5f, b = tv - 0.5f;
+    for (int c = 0; c < 3; ++c) y[c] = fmaf(b, L[6 + c], fmaf(a, L[3 + c], L[c]));
+}
+
 /* kind: 0 traced, 1 no trace (below the tangent plane, or receiver on the
  * back side of the one-sided light), 2 background pixel. */
 static int make_sample(int32_t W, const float *pos, const float *nrm, const uint32_t *prim, const orc_params *p,
@@ -231,7 +286,9 @@ static int make_sample(int32_t W, const float *pos, const float *nrm, const uint
         return 0;
     }
     float y[3];
-    const float *L = light_k(p, light_point_multi((uint32_t)px, (uint32_t)py, p->sample, sd, p, y));
+    const float *L = p->light;
+    if (p->light_pdf == 1) light_point_bilinear((uint32_t)px, (uint32_t)py, p->sample, sd, L, o, y);
+    else L = light_k(p, light_point_multi((uint32_t)px, (uint32_t)py, p->sample, sd, p, y));
     for (int c = 0; c < 3; ++c) dir[c] = y[c] - o[c];
     float front = fmaf(n[2], dir[2], fmaf(n[1], dir[1], n[0] * dir[0]));
     float nl[3] = {L[4] * L[8] - L[5] * L[7], L[5] * L[6] - L[3] * L[8], L[3] * L[7] - L[4] * L[6]};
@@ -714,6 +771,55 @@ static dens_t density_shadow(const double o[3], const double n[3], const double 
     return r;
 }
 
+/* Light coordinates (a, b) of y'(x, z): the ray from o through z meets the
+ * light's plane at y' = c + a e_u + b e_v (the rectangle is |a|, |b| <= 1/2).
+ * Returns 0 when the ray is parallel to the plane. */
+static int yprime_coords(const double o[3], const double z[3], const double *L, double *a, double *b) {
+    double c[3], eu[3], ev[3], nl[3], area, w[3], co[3];
+    light_frame(L, c, eu, ev, nl, &area);
+    sub3(z, o, w);
+    sub3(c, o, co);
+    double nw = dot3(nl, w);
+    if (nw == 0.0) return 0;
+    double s = dot3(nl, co) / nw;
+    double yc[3] = {o[0] + s * w[0] - c[0], o[1] + s * w[1] - c[1], o[2] + s * w[2] - c[2]};
+    *a = dot3(yc, eu) / dot3(eu, eu);
+    *b = dot3(yc, ev) / dot3(ev, ev);
+    return 1;
+}
+
+/* Area(A) p_A(y | x) of the bilinear density at light coordinates (a, b),
+ * FP64: the bilinear interpolation over the unit square (u, v) = (a + 1/2,
+ * b + 1/2) of the corner weights w_k = 1 / |o - y_k|^3 (|o - y_k|^2 clamped
+ * below at 2^-40 as in the sampler), scaled by 4 / sum_k w_k so that its mean
+ * over the rectangle, i.e. the integral of p_A, is 1. */
+static double bilinear_q(const double o[3], const double *L, double a, double b) {
+    double w[4], sum = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        double ak = (k & 1) ? 0.5 : -0.5, bk = (k & 2) ? 0.5 : -0.5, d[3];
+        for (int c = 0; c < 3; ++c) d[c] = o[c] - (L[c] + ak * L[3 + c] + bk * L[6 + c]);
+        double d2 = dot3(d, d);
+        if (d2 < 0x1p-40) d2 = 0x1p-40;
+        w[k] = 1.0 / (d2 * sqrt(d2));
+        sum += w[k];
+    }
+    double u = a + 0.5, v = b + 0.5;
+    double bil = (1.0 - u) * (1.0 - v) * w[0] + u * (1.0 - v) * w[1] + (1.0 - u) * v * w[2] + u * v * w[3];
+    return 4.0 * bil / sum;
+}
+
+/* q_x(y'(x, z)) = Area(A) p_A(y' | x) for the light density of the parameters
+ * (1 for the uniform density). */
+static double emitter_q(const orc_params *p, const double o[3], const double z[3]) {
+    if (p->light_pdf != 1) return 1.0;
+    double L[9], a, b;
+    for (int q = 0; q < 9; ++q) L[q] = p->light[q];
+    if (!yprime_coords(o, z, L, &a, &b)) return 1.0;
+    return bilinear_q(o, L, a, b);
+}
+
+double orc_light_q(const double *o, const double *light, double a, double b) { return bilinear_q(o, light, a, b); }
+
 double orc_density_ao(const double *o, const double *n, const double *z, const double *nz, double R) {
     return density_ao(o, n, z, nz, R).p;
 }
@@ -1041,7 +1147,15 @@ static dens_t pair_density(const reuse_ctx *c, int64_t k, int64_t j) {
     if (K == 1) {
         double L[9];
         for (int q = 0; q < 9; ++q) L[q] = c->p->light[q];
-        return density_shadow(o, n, c->z + 3 * j, c->nz + 3 * j, L);
+        dens_t d = density_shadow(o, n, c->z + 3 * j, c->nz + 3 * j, L);
+        if (c->p->light_pdf == 1 && d.ppass > 0.0) {
+            /* a general emitter density (Eq. reapp-shadow-general-solid-angle-pdf):
+             * p_A(y' | x) J chi_A = q_x(y') (1 / Area) J chi_A */
+            double q = emitter_q(c->p, o, c->z + 3 * j);
+            d.p *= q;
+            d.ppass *= q;
+        }
+        return d;
     }
     /* several lights: the density of z over the union of the lights is the
      * area-weighted sum of the per-light densities, sum_l (A_l / A_tot) p_l */
@@ -1246,10 +1360,12 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
         eval_light_reuse(c, t, ix, iy, value, nvar, var);
         return;
     }
-    if (p->estimator == 0 && p->mode < 2) {
+    if (p->estimator == 0 && p->mode < 2 && p->light_pdf == 0) {
         /* Eqs. (ao-mc-estimator) and (shadow-mc-estimator), one sample:
          * V = 1 when the ray or segment is free.  (Solid-angle shadows take
-         * the general path below with S(i) = {i}.) */
+         * the general path below with S(i) = {i}, and so do shadows sampled
+         * from a general emitter density, whose one-sample weight is
+         * 1 / (Area p_A(y' | x)).) */
         *value = c->hit[i] == ORC_MISS ? 1.0 : 0.0;
         var[0] = *value;
         *nvar = 1;
@@ -1323,6 +1439,20 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
         if (near) excluded = 1;
         for (int b = 0; b < m; ++b)
             cfac[b] = c->hit[t->S[b]] < ORC_SELF ? di_factor(o, n, c->z + 3 * t->S[b], L) : 0.0;
+        cf = cfac;
+    }
+    if (p->mode != 0 && p->light_pdf == 1) {
+        /* a general emitter density: every estimator factor divides by
+         * Area p_A(y'_ij | x_i) (C^gen of Eqs. reapp-shadow-general-solid-angle-mis-factor
+         * and reapp-di-general-one-sample-blocked; 1 / (Area p_A) for the area
+         * definition, whose factor is 1 under the uniform density) */
+        double o[3], n[3];
+        receiver_point(c, i, o, n);
+        for (int b = 0; b < m; ++b) {
+            int64_t j = t->S[b];
+            double q = c->hit[j] < ORC_SELF ? emitter_q(p, o, c->z + 3 * j) : 1.0;
+            cfac[b] = (cf ? cfac[b] : 1.0) / q;
+        }
         cf = cfac;
     }
     /* Dark-region guard (Sec. 4.4, biased shadows): every sample of the set

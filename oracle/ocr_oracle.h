@@ -31,7 +31,8 @@ typedef struct {
     float light[9];     /* centre, edge_u, edge_v (FP32 inputs) */
     uint64_t seed;
     uint32_t sample;    /* sample index s */
-    int32_t pad;
+    int32_t light_pdf;  /* shadows, one light: 0 uniform emitter-area density, 1 bilinear density of
+                           the receiver (corner weights 1 / |o - y_k|^3); estimators 0-2 */
     int32_t nlights;    /* shadows: number of rectangular lights (0 or 1: light[] only; up to 4) */
     float more_lights[3 * 9]; /* lights 1..nlights-1, as light[] */
 } orc_params;
@@ -70,6 +71,10 @@ void orc_reuse(const orc_scene *s, int32_t W, int32_t H, const float *pos, const
                const uint32_t *prim, const orc_params *p, const uint32_t *hit, const double *z,
                const double *nz, const uint8_t *graze, int32_t x0, int32_t y0, int32_t x1, int32_t y1,
                double *value, uint8_t *nvar, double *var);
+
+/* Area(A) p_A(y | x) of the bilinear emitter density of receiver point o at
+ * light coordinates (a, b) of y. */
+double orc_light_q(const double *o, const double *light, double a, double b);
 
 /* Multi-sample accumulation over samples p->sample .. p->sample+M-1:
  * per-pixel sum and sum of squares of the per-sample estimates. */

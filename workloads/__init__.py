@@ -102,10 +102,12 @@ class GBuffer:
 @dataclass
 class RectLight:
     """Rectangle centre c and edge vectors e_u, e_v; the emitting side is
-    normalize(e_u x e_v)."""
+    normalize(e_u x e_v).  pdf: the density its samples are drawn from, 0
+    uniform over the area, 1 the receiver-dependent bilinear density."""
     center: np.ndarray
     edge_u: np.ndarray
     edge_v: np.ndarray
+    pdf: int = 0
 
     def as_array(self) -> np.ndarray:
         return np.concatenate([self.center, self.edge_u, self.edge_v]).astype(np.float32)
