@@ -73,13 +73,34 @@ typedef struct {
     int32_t width, height;
 } ocr_gbuffer;
 
-/* One-sided rectangular emitter (uniform area sampling, Eq.
- * shadow-light-pdf): the rectangle c + a e_u + b e_v, |a|,|b| <= 1/2, emitting
- * towards normalize(e_u x e_v).  e_u and e_v must be orthogonal. */
+/* Emitter-area sampling densities p_A(y | x) of a light (ocr_rect_light.pdf).
+ *   OCR_LIGHT_UNIFORM:  1 / Area (Eq. shadow-light-pdf).
+ *   OCR_LIGHT_BILINEAR: a general, receiver-dependent area density (App.,
+ *     general area-domain sampling density): over the light coordinates
+ *     (a, b) the bilinear interpolation of the corner weights 1 / |o - y_k|^3,
+ *     the shape of the solid-angle density cos(theta_y) / |o - y|^2 at the
+ *     corners, normalised to unit mass.  The occluder density becomes
+ *     p_A(y' | x) J chi_A Occ and every estimator factor divides by
+ *     Area p_A(y' | x).  Sampling is specified in FP32 (corner weights with
+ *     |o - y_k|^2 clamped at 2^-40 and divided by their maximum; v = b + 1/2
+ *     from its linear marginal with h[1], then u = a + 1/2 from the linear
+ *     conditional with h[0], each by the inverse CDF
+ *     t = xi (e0 + e1) / (e0 + sqrt((1 - xi) e0^2 + xi e1^2)), capped at 1).
+ *     Taken by ocr_trace_occluders, ocr_sample_rays, ocr_validate_pairs (the
+ *     validation does not depend on the density), ocr_reuse_shadow,
+ *     ocr_reuse_shadow_solid_angle and ocr_reuse_direct_illumination; the
+ *     other entry points that take lights return OCR_ERR_UNSUPPORTED for it. */
+enum { OCR_LIGHT_UNIFORM = 0, OCR_LIGHT_BILINEAR = 1 };
+
+/* One-sided rectangular emitter: the rectangle c + a e_u + b e_v,
+ * |a|,|b| <= 1/2, emitting towards normalize(e_u x e_v).  e_u and e_v must be
+ * orthogonal.  pdf: OCR_LIGHT_UNIFORM (0) or OCR_LIGHT_BILINEAR; other
+ * values are OCR_ERR_INVALID_ARG. */
 typedef struct {
     float center[3];
     float edge_u[3];
     float edge_v[3];
+    int32_t pdf;
 } ocr_rect_light;
 
 /* First-hit occluder records (App. D / App. H, step 1), device buffers the

@@ -40,7 +40,11 @@ class _GBuffer(ctypes.Structure):
 
 
 class _Light(ctypes.Structure):
-    _fields_ = [("center", ctypes.c_float * 3), ("edge_u", ctypes.c_float * 3), ("edge_v", ctypes.c_float * 3)]
+    _fields_ = [("center", ctypes.c_float * 3), ("edge_u", ctypes.c_float * 3), ("edge_v", ctypes.c_float * 3),
+                ("pdf", ctypes.c_int32)]
+
+
+OCR_LIGHT_UNIFORM, OCR_LIGHT_BILINEAR = 0, 1
 
 
 class _Occ(ctypes.Structure):
@@ -268,12 +272,16 @@ class DeviceGBuffer:
 
 
 def light_struct(light) -> _Light:
+    """A light description: an object with as_array() (centre, e_u, e_v) and
+    an optional pdf (OCR_LIGHT_UNIFORM / OCR_LIGHT_BILINEAR), or 9 floats
+    (uniform density)."""
     la = light.as_array() if hasattr(light, "as_array") else np.asarray(light, np.float32)
     s = _Light()
     for i in range(3):
         s.center[i] = float(la[i])
         s.edge_u[i] = float(la[3 + i])
         s.edge_v[i] = float(la[6 + i])
+    s.pdf = int(getattr(light, "pdf", OCR_LIGHT_UNIFORM))
     return s
 
 

@@ -53,6 +53,8 @@ ocr_status make_light(const ocr_rect_light *l, LightF &L) {
     if (!l) return fail(OCR_ERR_INVALID_ARG, "light is NULL");
     if (!finite3(l->center) || !finite3(l->edge_u) || !finite3(l->edge_v))
         return fail(OCR_ERR_INVALID_ARG, "light has non-finite values");
+    if (l->pdf != OCR_LIGHT_UNIFORM && l->pdf != OCR_LIGHT_BILINEAR)
+        return fail(OCR_ERR_INVALID_ARG, "light pdf %d out of range", l->pdf);
     const float *u = l->edge_u, *v = l->edge_v;
     double uu = (double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2];
     double vv = (double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2];
@@ -95,6 +97,12 @@ ocr_status check_params(const ocr_reuse_params *p) {
     return OCR_OK;
 }
 
+ocr_status uniform_only(const ocr_rect_light *l, const char *who) {
+    if (l && l->pdf != OCR_LIGHT_UNIFORM)
+        return fail(OCR_ERR_UNSUPPORTED, "%s samples lights uniformly only (pdf %d)", who, l->pdf);
+    return OCR_OK;
+}
+
 ocr_status make_lights(const ocr_rect_light *lights, int32_t n, LightSetF &S) {
     std::memset(&S, 0, sizeof S);
     if (!lights) return fail(OCR_ERR_INVALID_ARG, "lights is NULL");
@@ -103,6 +111,7 @@ ocr_status make_lights(const ocr_rect_light *lights, int32_t n, LightSetF &S) {
     for (int k = 0; k < n; ++k) {
         ocr_status st = make_light(&lights[k], S.l[k]);
         if (st) return st;
+        if ((st = uniform_only(&lights[k], "several lights"))) return st;
     }
     return OCR_OK;
 }
@@ -114,7 +123,10 @@ ocr_status check_effect(int32_t mode, float ao_radius, const ocr_rect_light *lig
             return fail(OCR_ERR_INVALID_ARG, "AO radius %g must be finite and > 0", (double)ao_radius);
         return OCR_OK;
     }
-    if (mode == OCR_SHADOW) return make_light(light, L);
+    if (mode == OCR_SHADOW) {
+        ocr_status st = make_light(light, L);
+        return st ? st : uniform_only(light, "this entry point");
+    }
     return fail(OCR_ERR_INVALID_ARG, "mode %d out of range", mode);
 }
 
@@ -122,9 +134,10 @@ ocr_status check_effect(int32_t mode, float ao_radius, const ocr_rect_light *lig
 
 namespace {
 
+// pdf: the light's emitter density (OCR_LIGHT_UNIFORM for AO).
 ocr_status reuse_common(const ocr_bvh *bvh, const ocr_gbuffer *g, const ocr_occluders *occ, int mode, float R,
                         const LightF &L, const ocr_reuse_params *p, void *ws, size_t ws_bytes, float *out,
-                        void *stream, float scale = 1.0f) {
+                        void *stream, float scale = 1.0f, int pdf = OCR_LIGHT_UNIFORM) {
     ocr_status st = check_gbuf(g);
     if (st) return st;
     if ((st = check_params(p))) return st;
@@ -145,7 +158,10 @@ ocr_status reuse_common(const ocr_bvh *bvh, const ocr_gbuffer *g, const ocr_occl
                             nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "validation launch");
     }
-    e = launch_reuse(gv, ov, mode, R, L, *p, (const uint32_t *)ws, out, s, scale);
+    if (pdf == OCR_LIGHT_BILINEAR)
+        e = launch_reuse_bilinear(gv, ov, mode, LightBilinF{L}, *p, (const uint32_t *)ws, out, s, scale);
+    else
+        e = launch_reuse(gv, ov, mode, R, L, *p, (const uint32_t *)ws, out, s, scale);
     if (e != hipSuccess) return hip_fail(e, "reuse launch");
     return OCR_OK;
 }
@@ -244,8 +260,12 @@ ocr_status ocr_trace_occluders(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int3
     } else {
         return fail(OCR_ERR_INVALID_ARG, "mode %d out of range", mode);
     }
-    hipError_t e = launch_trace(bvh->dev, view(gbuf), mode, ao_radius, L, fold_seed(seed), sample,
-                                OccView{out->dz, out->nz, out->hit}, (hipStream_t)stream);
+    const OccView ov{out->dz, out->nz, out->hit};
+    hipError_t e = mode == OCR_SHADOW && light->pdf == OCR_LIGHT_BILINEAR
+                       ? launch_trace_bilinear(bvh->dev, view(gbuf), LightBilinF{L}, fold_seed(seed), sample, ov,
+                                               (hipStream_t)stream)
+                       : launch_trace(bvh->dev, view(gbuf), mode, ao_radius, L, fold_seed(seed), sample, ov,
+                                      (hipStream_t)stream);
     return e == hipSuccess ? OCR_OK : hip_fail(e, "trace launch");
 }
 
@@ -276,7 +296,11 @@ ocr_status ocr_sample_rays(const ocr_gbuffer *gbuf, int32_t mode, const ocr_rect
     } else if (mode != OCR_AO) {
         return fail(OCR_ERR_INVALID_ARG, "mode %d out of range", mode);
     }
-    hipError_t e = launch_samples(view(gbuf), mode, L, fold_seed(seed), sample, origin, dir, kind, (hipStream_t)stream);
+    hipError_t e = mode == OCR_SHADOW && light->pdf == OCR_LIGHT_BILINEAR
+                       ? launch_samples_bilinear(view(gbuf), LightBilinF{L}, fold_seed(seed), sample, origin, dir,
+                                                 kind, (hipStream_t)stream)
+                       : launch_samples(view(gbuf), mode, L, fold_seed(seed), sample, origin, dir, kind,
+                                        (hipStream_t)stream);
     return e == hipSuccess ? OCR_OK : hip_fail(e, "sample launch");
 }
 
@@ -342,7 +366,8 @@ ocr_status ocr_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const o
     LightF L;
     ocr_status st = make_light(light, L);
     if (st) return st;
-    return reuse_common(bvh, gbuf, occ, OCR_SHADOW, 1.0f, L, params, workspace, workspace_bytes, out, stream);
+    return reuse_common(bvh, gbuf, occ, OCR_SHADOW, 1.0f, L, params, workspace, workspace_bytes, out, stream, 1.0f,
+                        light->pdf);
 }
 
 ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
@@ -351,7 +376,8 @@ ocr_status ocr_reuse_shadow_solid_angle(const ocr_bvh *bvh, const ocr_gbuffer *g
     LightF L;
     ocr_status st = make_light(light, L);
     if (st) return st;
-    return reuse_common(bvh, gbuf, occ, kShadowSA, 1.0f, L, params, workspace, workspace_bytes, out, stream);
+    return reuse_common(bvh, gbuf, occ, kShadowSA, 1.0f, L, params, workspace, workspace_bytes, out, stream, 1.0f,
+                        light->pdf);
 }
 
 ocr_status ocr_trace_occluders_lights(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_rect_light *lights,
@@ -425,7 +451,8 @@ ocr_status ocr_reuse_direct_illumination(const ocr_bvh *bvh, const ocr_gbuffer *
     ocr_status st = make_light(light, L);
     if (st) return st;
     const float scale = (float)((double)albedo * (double)radiance / 3.14159265358979323846);
-    return reuse_common(bvh, gbuf, occ, kDI, 1.0f, L, params, workspace, workspace_bytes, out, stream, scale);
+    return reuse_common(bvh, gbuf, occ, kDI, 1.0f, L, params, workspace, workspace_bytes, out, stream, scale,
+                        light->pdf);
 }
 
 ocr_status ocr_filter_values(const ocr_gbuffer *gbuf, const ocr_reuse_params *params, const float *in, float *out,
@@ -449,6 +476,7 @@ ocr_status ocr_light_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, c
     if (!out) return fail(OCR_ERR_INVALID_ARG, "out is NULL");
     LightF L;
     if ((st = make_light(light, L))) return st;
+    if ((st = uniform_only(light, "light-sample reuse"))) return st;
     hipError_t e = launch_light_reuse(bvh->dev, view(gbuf), L, fold_seed(seed), sample, *params, out,
                                       (hipStream_t)stream);
     return e == hipSuccess ? OCR_OK : hip_fail(e, "light-sample reuse launch");

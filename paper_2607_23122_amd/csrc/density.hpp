@@ -61,8 +61,12 @@ __device__ inline RecvShadow recv_shadow(const float ok[3], const LightF &L) {
 // where y' = o_k + s w is the ray's crossing of the light plane; support:
 // z in front of the receiver's tangent plane, ray towards the emitting face,
 // s > 1 (the light beyond z) and y' inside the rectangle.
-__device__ inline float dens_shadow(const float w[3], const float nk[3], const RecvShadow &rk, const float nz[3],
-                                    const LightF &L) {
+// AB: also return the light coordinates (a, b) of y' in ab[0..1], for
+// densities that vary over the light (without it the coordinates are only
+// tested, and the tests may be skipped once one fails).
+template <bool AB>
+__device__ inline float dens_shadow_t(const float w[3], const float nk[3], const RecvShadow &rk, const float nz[3],
+                                      const LightF &L, float *ab) {
 #pragma clang fp contract(off)
     float front = dot3f(nk, w);
     float nlw = dot3f(L.nl, w);
@@ -75,7 +79,16 @@ __device__ inline float dens_shadow(const float w[3], const float nk[3], const R
     float b = __fmaf_rn(s, dot3f(L.vhat, w), rk.bk);
     bool ok = front > 0.0f && nlw < 0.0f && zw < 0.0f && s > 1.0f && fabsf(a) <= 0.5f && fabsf(b) <= 0.5f;
     float p = (s * s) * (zw * inl);
+    if constexpr (AB) {
+        ab[0] = a;
+        ab[1] = b;
+    }
     return ok ? p : 0.0f;
+}
+
+__device__ inline float dens_shadow(const float w[3], const float nk[3], const RecvShadow &rk, const float nz[3],
+                                    const LightF &L) {
+    return dens_shadow_t<false>(w, nk, rk, nz, L, nullptr);
 }
 
 // Fraction of the light rectangle in front of the tangent plane of (o, n):

@@ -1,8 +1,9 @@
 // Occluder-domain MIS reuse kernels (Sec. 4.2-4.4; steps 2-3 of App. D /
 // App. H): the sliding window (one 16x16 target tile per block; the tile
 // body is shared with the batched schedule), fixed groups, no reuse, and the
-// sample-mean scale; each for AO, area-definition shadows and shadows under
-// the solid-angle definition (kShadowSA).
+// sample-mean scale; each for AO, area-definition shadows, shadows under the
+// solid-angle definition (kShadowSA) and direct illumination (kDI), with the
+// light types of lights.hpp.
 //
 // Fixed groups (N = 1, 2, 4, 8): one lane per pixel; each receiver lane
 // evaluates its densities for the N candidates of its group into LDS and each
@@ -133,14 +134,17 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
         const float pij = s_p[tid][m];
         if (pij > 0.0f && P > 0.0f) {
             float term = pij * __builtin_amdgcn_rcpf(P);
-            if constexpr (MODE >= kShadowSA) {
+            if constexpr (MODE >= kShadowSA || kBilinear<LT>) {
                 // times g_ij (solid angle) or gd_ij (direct illumination) of
-                // this target and candidate m
+                // this target and candidate m, over q_i(y'_ij) for the
+                // bilinear emitter density
                 const float oj[3] = {s_o[0][jt], s_o[1][jt], s_o[2][jt]};
                 const float dzj[3] = {s_dz[0][jt], s_dz[1][jt], s_dz[2][jt]};
                 float w[3];
                 rel_vec(oj, o, dzj, w);
-                term *= MODE == kDI ? di_pair_g(w, n, rk.hk, L) : sa_pair_g(w, rk.hk, L);
+                if constexpr (MODE == kDI) term *= di_pair_g(w, n, rk.hk, L);
+                else if constexpr (MODE == kShadowSA) term *= sa_pair_g(w, rk.hk, L);
+                if constexpr (kBilinear<LT>) term *= inv_bilinear_q(w, rk, L);
             }
             B += term;
         }
@@ -171,12 +175,13 @@ __global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView oc
     float v;
     if constexpr (MODE == OCR_AO) {
         v = (!valid || occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
-    } else if constexpr (MODE == OCR_SHADOW) {
+    } else if constexpr (MODE == OCR_SHADOW && !kBilinear<LT>) {
         v = (valid && occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
     } else {
-        // solid-angle definition / direct illumination, S(i) = {i}: the
-        // unshadowed term minus C(x_i, z_i) for a hit whose own density is
-        // positive (the ratio p/p is 1)
+        // solid-angle definition / direct illumination / a light sampled from
+        // the bilinear density, S(i) = {i}: the unshadowed term minus
+        // C(x_i, z_i) for a hit whose own density is positive (the ratio p/p
+        // is 1)
         v = 0.0f;
         if (valid) {
             float x[3], n[3], o[3];
@@ -189,11 +194,17 @@ __global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView oc
                 float dz[3], nz[3];
                 ld3(occ.dz, gi, dz);
                 ld3(occ.nz, gi, nz);
-                const RecvShadow rk = recv_shadow(o, L);
-                if (dens_shadow(dz, n, rk, nz, L) > 0.0f)
-                    Bg = MODE == kDI ? di_pair_g(dz, n, rk.hk, L) : sa_pair_g(dz, rk.hk, L);
+                const auto rk = recv_of(o, L);
+                if (dens_light(dz, n, rk, nz, L) > 0.0f) {
+                    Bg = 1.0f;
+                    if constexpr (MODE == kDI) Bg = di_pair_g(dz, n, rk.hk, L);
+                    else if constexpr (MODE == kShadowSA) Bg = sa_pair_g(dz, rk.hk, L);
+                    if constexpr (kBilinear<LT>) Bg *= inv_bilinear_q(dz, rk, L);
+                }
             }
-            v = MODE == kDI ? di_estimate(o, n, L, Bg, scale) : sa_estimate(o, n, L, Bg);
+            if constexpr (MODE == kDI) v = di_estimate(o, n, L, Bg, scale);
+            else if constexpr (MODE == kShadowSA) v = sa_estimate(o, n, L, Bg);
+            else v = front_light(o, n, L) - Bg;
         }
     }
     out[gi] = accumulate ? out[gi] + v : v;
@@ -212,7 +223,7 @@ static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, co
                              int words, const ocr_reuse_params &p, float *out, float scale, hipStream_t st) {
     int tiles_x = (g.w + kWTX - 1) / kWTX, tiles_y = (g.h + kWTY - 1) / kWTY;
     int nt = tiles_x * tiles_y;
-    WinLayout lay = win_layout(p.radius, MODE, UNB, words);
+    WinLayout lay = win_layout(p.radius, MODE, UNB, words, kRecvFloats<LT>);
     // dynamic-LDS limit raised so far (64 KB by default); several host
     // threads may launch at once
     static std::atomic<size_t> attr_bytes{64 * 1024};
@@ -286,6 +297,29 @@ hipError_t launch_reuse_lights(const GBufView &g, const OccView &occ, const Ligh
     q.dark_guard = (p.estimator == OCR_BIASED && p.dark_guard) ? 1 : 0;
     hipError_t e = launch_mode<OCR_SHADOW, LightSetF>(g, occ, 1.0f, L, bits, pair_words(p), q,
                                                       p.estimator == OCR_UNBIASED, out, 1.0f, st);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+// one light sampled from the bilinear emitter density (shadows, solid-angle
+// shadows, direct illumination)
+hipError_t launch_reuse_bilinear(const GBufView &g, const OccView &occ, int mode, const LightBilinF &L,
+                                 const ocr_reuse_params &p, const uint32_t *bits, float *out, hipStream_t st,
+                                 float scale) {
+    const int words = pair_words(p);
+    const bool unb = p.estimator == OCR_UNBIASED;
+    ocr_reuse_params q = p;
+    q.dark_guard = (p.estimator == OCR_BIASED && p.dark_guard) ? 1 : 0;
+    hipError_t e;
+    switch (mode) {
+        case OCR_SHADOW:
+            e = launch_mode<OCR_SHADOW, LightBilinF>(g, occ, 1.0f, L, bits, words, q, unb, out, scale, st);
+            break;
+        case kShadowSA:
+            e = launch_mode<kShadowSA, LightBilinF>(g, occ, 1.0f, L, bits, words, q, unb, out, scale, st);
+            break;
+        default: e = launch_mode<kDI, LightBilinF>(g, occ, 1.0f, L, bits, words, q, unb, out, scale, st); break;
+    }
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }

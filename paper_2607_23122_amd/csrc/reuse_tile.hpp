@@ -54,7 +54,8 @@ __host__ __device__ inline size_t lds_take(size_t &off, size_t bytes) {
     return at;
 }
 
-__host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int words) {
+// nrecv: floats of a receiver's light terms (kRecvFloats of the light type).
+__host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int words, int nrecv = 3) {
     WinLayout l;
     l.RWX = kWTX + 2 * R;
     l.RWY = kWTY + 2 * R;
@@ -67,7 +68,7 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     l.B_off = lds_take(off, sizeof(unsigned long long) * kWTX * kWTY);
     l.o_off = lds_take(off, sizeof(float) * 3 * l.cells);
     l.n_off = lds_take(off, sizeof(float) * 3 * l.cells);
-    l.sh_off = lds_take(off, mode != OCR_AO ? sizeof(float) * 3 * l.cells : 0);
+    l.sh_off = lds_take(off, mode != OCR_AO ? sizeof(float) * nrecv * l.cells : 0);
     l.valid_off = lds_take(off, l.cells);
     l.miss_off = lds_take(off, l.cells);
     l.list_off = lds_take(off, 4 * sizeof(int) + sizeof(uint16_t) * l.cells);
@@ -76,23 +77,29 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     return l;
 }
 
-// The scattered term of target cell kc under the solid-angle definition
-// (MODE kShadowSA: p_i(j) / P_i(j) times g_ij) or for direct illumination
-// (kDI: times gd_ij), clamped below 2^31 so that the 32.32 fixed-point sum
-// cannot overflow (the factor reaches that size only within ~1e-5 of the
-// light).
-template <int MODE>
+// The scattered term of target cell kc: p_i(j) / P_i(j) times the factor
+// C(x_i, z_j) of the estimator, g_ij under the solid-angle definition
+// (kShadowSA), gd_ij for direct illumination (kDI), and divided by q_i(y'_ij)
+// for a light sampled from the bilinear density; clamped below 2^31 so that
+// the 32.32 fixed-point sum cannot overflow (the factor reaches that size only
+// within ~1e-5 of the light).
+template <int MODE, class LT>
 __device__ inline float weighted_term(float ratio, const float *s_o, const float *s_n, const float *s_sh, int CELLS,
-                                      int kc, const float oj[3], const float dzj[3], const LightF &L) {
+                                      int kc, const float oj[3], const float dzj[3], const LT &L) {
     const float oi[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
     float w[3];
     rel_vec(oj, oi, dzj, w);
-    float gf;
-    if (MODE == kDI) {
+    float gf = 1.0f;
+    if constexpr (MODE == kDI) {
         const float ni[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
         gf = di_pair_g(w, ni, s_sh[kc], L);
-    } else {
+    } else if constexpr (MODE == kShadowSA) {
         gf = sa_pair_g(w, s_sh[kc], L);
+    }
+    if constexpr (kBilinear<LT>) {
+        float v[6];
+        for (int a = 0; a < 6; ++a) v[a] = s_sh[a * CELLS + kc];
+        gf *= inv_bilinear_q(w, recv_load(v, L), L);
     }
     return fminf(ratio * gf, 0x1p31f);
 }
@@ -104,13 +111,13 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                                          const LT &L, const uint32_t *__restrict__ bits, int words, int R,
                                          int dark_guard, int accumulate, float *out, int tx, int ty,
                                          float scale = 1.0f) {
-    const WinLayout lay = win_layout(R, MODE, UNB, words);
+    const WinLayout lay = win_layout(R, MODE, UNB, words, kRecvFloats<LT>);
     const int TX = kWTX, TY = kWTY, RW = lay.RWX, CELLS = lay.cells, D = 2 * R, SIDE = lay.side, TW = 2 * R + 1;
     const float inv_rw = 1.0f / (float)RW;
     unsigned long long *s_B = reinterpret_cast<unsigned long long *>(smem + lay.B_off);
     float *s_o = reinterpret_cast<float *>(smem + lay.o_off);    // [3][cells]
     float *s_n = reinterpret_cast<float *>(smem + lay.n_off);    // [3][cells]
-    float *s_sh = reinterpret_cast<float *>(smem + lay.sh_off);  // [3][cells]
+    float *s_sh = reinterpret_cast<float *>(smem + lay.sh_off);  // [kRecvFloats][cells]
     uint8_t *s_valid = smem + lay.valid_off;
     uint8_t *s_miss = smem + lay.miss_off;
     int *s_count = reinterpret_cast<int *>(smem + lay.list_off);
@@ -148,11 +155,9 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
         }
         if (MODE != OCR_AO) {
             // the receiver's light terms (its point, for several lights)
-            float v[3] = {0.f, 0.f, 0.f};
+            float v[kRecvFloats<LT>] = {};
             if (valid) recv_store(recv_of(o, L), v);
-            s_sh[c] = v[0];
-            s_sh[CELLS + c] = v[1];
-            s_sh[2 * CELLS + c] = v[2];
+            for (int a = 0; a < kRecvFloats<LT>; ++a) s_sh[a * CELLS + c] = v[a];
         }
         s_valid[c] = valid;
         s_miss[c] = valid && hit == OCR_HIT_MISS;
@@ -209,7 +214,8 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                 if (MODE == OCR_AO) {
                     p = dens_ao(w, nk, nzj, R2);
                 } else {
-                    const float v[3] = {s_sh[kc], s_sh[CELLS + kc], s_sh[2 * CELLS + kc]};
+                    float v[kRecvFloats<LT>];
+                    for (int a = 0; a < kRecvFloats<LT>; ++a) v[a] = s_sh[a * CELLS + kc];
                     p = dens_light(w, nk, recv_load(v, L), nzj, L);
                 }
                 if (UNB && p > 0.0f) {
@@ -265,7 +271,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                 P += h;
                 if (tgt) {
                     float term = my_p * __builtin_amdgcn_rcpf(P);
-                    if constexpr (MODE >= kShadowSA)
+                    if constexpr (MODE >= kShadowSA || kBilinear<LT>)
                         term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ky0 + my_y, RW) + (kx0 + my_x),
                                                    oj, dzj, L);
                     atomicAdd(&s_B[(ky0 + my_y - R) * TX + (kx0 + my_x - R)],
@@ -294,7 +300,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                 const float pij = w_dens[__mul24(r2 + R, SIDE) + (t2 + R)];
                 if (pij > 0.0f && P > 0.0f) {
                     float term = pij * __builtin_amdgcn_rcpf(P);
-                    if constexpr (MODE >= kShadowSA)
+                    if constexpr (MODE >= kShadowSA || kBilinear<LT>)
                         term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ty0 + r2, RW) + (tx0 + t2), oj,
                                                    dzj, L);
                     atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],

@@ -329,8 +329,8 @@ __global__ __launch_bounds__(kBlock) void validate_group_kernel(DeviceBVH bvh, G
     }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void sample_kernel(GBufView g, LightF L, uint32_t sd, uint32_t sample, float *o_out,
+template <int MODE, class LT = LightF>
+__global__ __launch_bounds__(kBlock) void sample_kernel(GBufView g, LT L, uint32_t sd, uint32_t sample, float *o_out,
                                                         float *d_out, uint8_t *kind) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= (int64_t)g.w * g.h) return;
@@ -346,11 +346,12 @@ __global__ __launch_bounds__(kBlock) void sample_kernel(GBufView g, LightF L, ui
             k = 0;
         } else {
             float y[3];
-            light_point((uint32_t)px, (uint32_t)py, sample, sd, L, y);
+            LightF Lc;
+            pick_light((uint32_t)px, (uint32_t)py, sample, sd, L, o, y, Lc);
             d[0] = y[0] - o[0];
             d[1] = y[1] - o[1];
             d[2] = y[2] - o[2];
-            k = shadow_traced(n, o, d, L) ? 0 : 1;
+            k = shadow_traced(n, o, d, Lc) ? 0 : 1;
         }
     }
     for (int c = 0; c < 3; ++c) {
@@ -459,6 +460,26 @@ hipError_t launch_validate(const DeviceBVH &bvh, const GBufView &g, const OccVie
 hipError_t launch_validate_lights(const DeviceBVH &bvh, const GBufView &g, const OccView &occ, const LightSetF &L,
                                   const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats, hipStream_t st) {
     return launch_validate_t(bvh, g, occ, OCR_SHADOW, 1.0f, L, p, bits, stats, st);
+}
+
+// one light sampled from the bilinear emitter density (shadows)
+hipError_t launch_trace_bilinear(const DeviceBVH &bvh, const GBufView &g, const LightBilinF &L, uint32_t seed32,
+                                 uint32_t sample, const OccView &out, hipStream_t st) {
+    int tiles_x;
+    int nt = ntiles_for(g, tiles_x);
+    dim3 grid(grid_for(nt)), block(kBlock);
+    hipLaunchKernelGGL((trace_kernel<OCR_SHADOW, LightBilinF>), grid, block, 0, st, bvh, g, 1.0f, L, seed32, sample,
+                       out, tiles_x, nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_samples_bilinear(const GBufView &g, const LightBilinF &L, uint32_t seed32, uint32_t sample,
+                                   float *o, float *d, uint8_t *kind, hipStream_t st) {
+    int64_t n = (int64_t)g.w * g.h;
+    dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    hipLaunchKernelGGL((sample_kernel<OCR_SHADOW, LightBilinF>), grid, block, 0, st, g, L, seed32, sample, o, d,
+                       kind);
+    return hipGetLastError();
 }
 
 hipError_t launch_trace_lights(const DeviceBVH &bvh, const GBufView &g, const LightSetF &L, uint32_t seed32,

@@ -38,7 +38,7 @@ __device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, floa
     } else {
         float y[3];
         LightF Lc;  // the light the sample lies on
-        pick_light((uint32_t)px, (uint32_t)py, sample, sd, L, y, Lc);
+        pick_light((uint32_t)px, (uint32_t)py, sample, sd, L, o, y, Lc);
         d[0] = y[0] - o[0];
         d[1] = y[1] - o[1];
         d[2] = y[2] - o[2];

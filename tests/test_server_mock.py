@@ -111,6 +111,12 @@ def test_argument_checks():
     assert srv.try_submit(r)[0] == -1                        # accumulate not served
     bad_light = ocr.request(sid, 0, mode="shadow", light=np.zeros(9, np.float32), out=1)
     assert srv.try_submit(bad_light)[0] == -1                # degenerate light
+    import workloads as w
+    lt = w.RectLight(np.array([0, 5, 0], np.float32), np.array([1, 0, 0], np.float32),
+                     np.array([0, 0, 1], np.float32), 1)
+    assert srv.try_submit(ocr.request(sid, 0, mode="shadow", light=lt, out=1))[0] == -4  # bilinear density: not served
+    lt.pdf = 7
+    assert srv.try_submit(ocr.request(sid, 0, mode="shadow", light=lt, out=1))[0] == -1  # unknown density
     with pytest.raises(ocr.OcrError):
         ocr.Server(100, slots=1, mock=True)                  # budget below the minimum
     with pytest.raises(ocr.OcrError):
