@@ -5,7 +5,11 @@ Workload ao_1080p (default): ambient occlusion at 1920x1080 over a displaced
 terrain (512x512 cells, fBm heights) with 2000 level-2 icospheres (1,164,288
 triangles), 1 sample per pixel, AO radius 2 m, 7x7 reuse window; synthetic,
 seeded inputs standing in for the paper's scenes.  shadow_1080p: the same
-with the 1 x 1 m rectangular light.
+with the 1 x 1 m rectangular light; shadow_sa_1080p and di_1080p: its shadows
+under the solid-angle definition and its direct illumination;
+shadow_sa_bilinear_1080p: solid-angle shadows with the light sampled from the
+bilinear (general, receiver-dependent) emitter density; shadow2_1080p:
+shadows of two lights.
 
 One step = the whole per-frame path on one batch of input (a new sample
 index each step): occluder tracing (sample generation fused), the no-reuse
@@ -75,14 +79,20 @@ OPS_SA_G = 24
 OPS_DI_G = OPS_SA_G + 8
 OPS_DENS["di"] = OPS_DENS["shadow"]
 OPS_DENS["shadow2"] = 2 * OPS_DENS["shadow"]  # the density summed over two lights
+# the bilinear emitter density: q(a, b) per pair density (three FMAs and a
+# product = 7) and 1 / q(y') per scattered term (three dot products (15), two
+# reciprocals, s, two FMAs (a, b), three FMAs for q and a product = 29)
+OPS_BILIN_DENS, OPS_BILIN_G = 7, 29
 
 
-def window_reuse_ops(r, mode):
+def window_reuse_ops(r, mode, bilinear=False):
     """Useful FP32 ops per hit candidate of a window-r reuse launch: the
     (4r+1)^2 pair densities, the (4r+1)(2r+1) row box sums and (2r+1)^2
     column box sums of 2r adds each, and a reciprocal and product per target."""
     side, tw = 4 * r + 1, 2 * r + 1
     g = tw * tw * {"shadow_sa": OPS_SA_G, "di": OPS_DI_G}.get(mode, 0)
+    if bilinear:
+        g += side * side * OPS_BILIN_DENS + tw * tw * OPS_BILIN_G
     return side * side * OPS_DENS[mode] + side * tw * 2 * r + tw * tw * 2 * r + tw * tw * 2 + g
 
 WORKLOADS = {
@@ -98,6 +108,10 @@ WORKLOADS = {
     "shadow2_1080p": dict(mode="shadow2", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2,
                           sample_seed=1),
     "di_1080p": dict(mode="di", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2, sample_seed=1),
+    # solid-angle shadows with the light sampled from the bilinear (general,
+    # receiver-dependent) emitter density
+    "shadow_sa_bilinear_1080p": dict(mode="shadow_sa", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2,
+                                     sample_seed=1, light_pdf=1),
     "batched_16": dict(radius=2.0, window_r=3, sample_seed=1),
     "served": dict(radius=2.0, window_r=3, rate=400.0, budget_gib=4.0, slots=8),
 }
@@ -214,6 +228,9 @@ def run_frame(args):
     light = w.terrain_light() if mode != "ao" else None
     if mode == "shadow2":
         light = w.two_lights()
+    bilinear = cfg.get("light_pdf", 0) == 1
+    if bilinear:
+        light.pdf = 1
     tmode = "shadow" if mode in ("shadow_sa", "di", "shadow2") else mode  # the mode records are traced in
     log(f"[bench] inputs {time.time() - t0:.1f}s: {scene.ntris} tris, {W}x{H}, valid {gb.valid.mean():.3f}")
 
@@ -329,7 +346,7 @@ def run_frame(args):
     # pair densities deciding which pairs get a segment ((4r+1)^2 - 1 per candidate)
     val_ops = OPS_BOX * box_tests + OPS_TRI * tri_tests + hits * ((4 * r + 1) ** 2 - 1) * OPS_DENS[mode]
     val_tops = val_ops / (per["validate"] * 1e-3) / 1e12
-    reuse_tops = hits * window_reuse_ops(r, mode) / (per["reuse_biased"] * 1e-3) / 1e12
+    reuse_tops = hits * window_reuse_ops(r, mode, bilinear) / (per["reuse_biased"] * 1e-3) / 1e12
     if dominant == "validate":
         # traversal and densities are VALU-bound: price the useful operations
         # one validation per light type (single-light kernels carry LightF)
@@ -359,7 +376,8 @@ def run_frame(args):
                                f"{W}x{H}, 1 spp, R={R} m, 7x7 window, no-reuse + biased + unbiased"
                                + {"shadow2": ", shadows of two rectangular lights",
                                   "shadow_sa": ", shadows under the solid-angle definition",
-                                  "di": ", occluder-domain direct illumination"}.get(mode, ""),
+                                  "di": ", occluder-domain direct illumination"}.get(mode, "")
+                               + (", light sampled from the bilinear emitter density" if bilinear else ""),
                    "global_batch": 1, "seq_len": W * H, "parallelism": "single-gpu"},
         "kernels_ms": {k: round(v, 4) for k, v in per.items()},
         "kernels_ms_p50": {k: round(float(np.percentile(v, 50)), 4) for k, v in samples.items()},
@@ -373,8 +391,8 @@ def run_frame(args):
                                unit="TFLOP/s", frac=round(reuse_tops / VALU_PEAK_TOPS, 4),
                                hbm_gbs=round(reuse_gbs, 1), hbm_frac=round(reuse_gbs / HBM_PEAK_GBS, 4),
                                kernel=f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2, 'di': 3, 'shadow2': 1}[mode]}, false, "
-                                      f"{'ocr::LightSetF' if mode == 'shadow2' else 'ocr::LightF'}>",
-                               ops_per_candidate=window_reuse_ops(r, mode)),
+                                      f"{'ocr::LightSetF' if mode == 'shadow2' else 'ocr::LightBilinF' if bilinear else 'ocr::LightF'}>",
+                               ops_per_candidate=window_reuse_ops(r, mode, bilinear)),
         "rays_per_step": rays,
         "negative_pixel_fraction": negative,
         "occluder_hits": hits,
@@ -387,8 +405,8 @@ def run_frame(args):
         "roofline": roof,
     }
 
-    # (the counting trace takes one light)
-    result["trace_roofline"] = None if mode == "shadow2" else alu_roofline(
+    # (the counting trace takes one uniformly sampled light)
+    result["trace_roofline"] = None if mode == "shadow2" or bilinear else alu_roofline(
         counted_trace(ocr, torch, bvh, dg, tmode, R, light, cfg["sample_seed"], args.steps - 1), per["trace"],
         "trace_kernel")
     if args.workload == "ao_1080p":
