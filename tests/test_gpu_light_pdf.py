@@ -173,3 +173,46 @@ def test_entry_points_that_sample_uniformly_refuse_it(ocr, terrain):
     with pytest.raises(ocr.OcrError):
         ocr.light_reuse_shadow(case.bvh, case.dg, case.light, 1, 0, ocr.reuse_params("window", 1, 0, "biased"))
     assert b"uniformly" in ocr.lib().ocr_last_error()
+
+
+@pytest.mark.parametrize("est,ntiles", [("biased", 6), ("unbiased", 3)])
+def test_solid_angle_1080p_tiles(ocr, est, ntiles):
+    # the benchmark's configuration: 1080p terrain, the 1 m light sampled from
+    # the bilinear density, solid-angle shadows, 7x7 window; sampled tiles
+    from gpu_util import tiles
+    s = w.terrain_scene(2)
+    light = w.terrain_light()
+    light.pdf = 1
+    case = Case(ocr, "terrain_1080p", s, w.render_gbuffer(s, w.terrain_camera()), light)
+    occ = _trace(ocr, case, 1)
+    gpu = _reuse(ocr, case, "shadow_sa", occ, ocr.reuse_params("window", 3, 0, est))
+    assert np.isfinite(gpu).all() and (gpu[~case.gb.valid] == 0.0).all()
+    p = oracle.params("shadow_sa", est, "window", radius=3, light=light, seed=1)
+    gh = occ.hit_u32()
+    for t in tiles(case.gb.width, case.gb.height, ntiles, 32, seed=41):
+        hr = oracle.halo_region(p, case.gb.width, case.gb.height, t)
+        rec = oracle.records(case.osc, case.gb, p, hr)
+        res = oracle.reuse(case.osc, case.gb, p, rec, t)
+        inside = np.zeros_like(case.gb.valid)
+        inside[hr[1]:hr[3], hr[0]:hr[2]] = True
+        st = compare_values(gpu, res, region=t, exclude=mismatch_reach(np.where(inside, gh, rec.hit), rec, p))
+        log(f"    tile {t}: {st}")
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (37, 23), (64, 1)])
+def test_small_and_ragged_frames_at_the_largest_window(ocr, W, H):
+    # radius 8 stages 6 floats per receiver for the bilinear density (more
+    # than 64 KB of LDS per block)
+    s = scenes.build([scenes.FLOOR, scenes.plate_y(0.5, -0.5, 0.02, -3, 3)])
+    gb = scenes.floor_grid(W, H, 0.02, x0=-0.3, z0=-0.2)
+    light = w.RectLight(np.array([0.2, 1.0, 0.1], np.float32), np.array([1.2, 0, 0], np.float32),
+                        np.array([0, 0, 1.2], np.float32), 1)
+    case = Case(ocr, f"floor_{W}x{H}", s, gb, light)
+    occ = _trace(ocr, case, 4)
+    for mode in ("shadow", "shadow_sa", "di"):
+        for pattern, size, est in [("window", 8, "unbiased"), ("window", 8, "biased"), ("group", 8, "unbiased")]:
+            log(f"[bilinear ragged {W}x{H}] {mode} {pattern} {size} {est}")
+            gpu = _reuse(ocr, case, mode, occ, ocr.reuse_params(pattern, size, size, est))
+            p = oracle.params(mode, est, pattern, radius=size, group_n=size, light=light, seed=4)
+            rec, res = oracle.frame(case.osc, gb, p)
+            compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
