@@ -23,6 +23,15 @@ masks, which are not available; its convergence tests use white noise).
     python quality.py [--effects ao,shadow] [--light-sizes 1,4] [--views 3]
                       [--ref-spp 2048] [--seeds 4] [--budget-ao 2.0]
                       [--budget-shadow 5.0] [--width 1920 --height 1080]
+                      [--light-pdf uniform|bilinear]
+
+Effects: ao, shadow (area definition), shadow_sa (solid-angle definition)
+and di (direct illumination of Lambertian receivers, albedo 0.8, radiance
+100 / Area so that every light size emits the same power).  With
+--light-pdf bilinear the light is sampled from the receiver-dependent
+bilinear density (the reference stays the uniform no-reuse mean: both
+estimate the same quantity); Light (8U) takes uniform sampling only and is
+left out then, and for the solid-angle and DI effects.
 
 Shadows are evaluated for each light size in --light-sizes (square lights of
 that edge in metres at the benchmark light's position; 1 is the benchmark's
@@ -38,6 +47,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -50,7 +61,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def methods(effect):
+def methods(effect, pdf="uniform"):
     """name -> (kind, pattern, size, estimator)."""
     m = {"RT": ("reuse", "window", 0, "none"),
          "Occ (2)": ("reuse", "group", 2, "biased"),
@@ -63,8 +74,24 @@ def methods(effect):
         m["Filter (8)"] = ("filter", "group", 8, "none")
     else:
         m["Light (8)"] = ("filter", "group", 8, "none")
-        m["Light (8U)"] = ("light", "group", 8, "none")
+        if effect == "shadow" and pdf == "uniform":
+            m["Light (8U)"] = ("light", "group", 8, "none")
     return m
+
+
+LIGHT_EFFECTS = ("shadow", "shadow_sa", "di")
+
+
+def _reuse_light(ocr, view, p, out, ws=None, light=None):
+    """The light effect's reuse entry point (records traced as shadows)."""
+    light = light if light is not None else view.light
+    if view.effect == "shadow_sa":
+        ocr.reuse_shadow_solid_angle(view.bvh if ws is not None else None, view.dg, view.occ, light, p, out, ws)
+    elif view.effect == "di":
+        ocr.reuse_direct_illumination(view.bvh if ws is not None else None, view.dg, view.occ, light, p,
+                                      radiance=view.radiance, albedo=0.8, out=out, workspace=ws)
+    else:
+        ocr.reuse_shadow(view.bvh if ws is not None else None, view.dg, view.occ, light, p, out, ws)
 
 
 class View:
@@ -74,6 +101,9 @@ class View:
         self.dg = ocr.DeviceGBuffer.from_host(self.gb)
         self.valid = torch.from_numpy(self.gb.valid).to(self.dg.prim.device)
         self.bvh, self.effect, self.light = bvh, effect, light
+        # direct illumination: the same emitted power for every light size
+        self.radiance = 0.0 if light is None else 100.0 / float(
+            np.linalg.norm(np.cross(light.edge_u.astype(np.float64), light.edge_v.astype(np.float64))))
         H, W = self.gb.height, self.gb.width
         dev = self.dg.prim.device
         self.occ = ocr.Occluders.empty(H, W, dev)
@@ -84,21 +114,23 @@ class View:
                               device=dev)
 
 
-def run_sample(ocr, view, spec, seed, sample, out, accumulate):
-    """Enqueue one sample of a method, writing (or adding to) out."""
+def run_sample(ocr, view, spec, seed, sample, out, accumulate, light=None):
+    """Enqueue one sample of a method, writing (or adding to) out (light:
+    another sampling of the view's light, e.g. for the reference)."""
     kind, pattern, size, est = spec
-    light = view.light
+    light = light if light is not None else view.light
     if kind == "light":
         p = ocr.reuse_params(pattern, size, size, "none", accumulate=accumulate)
         ocr.light_reuse_shadow(view.bvh, view.dg, light, seed, sample, p, out)
         return
-    ocr.trace_occluders(view.bvh, view.dg, view.effect, R_AO, light, seed, sample, view.occ)
+    tmode = "ao" if view.effect == "ao" else "shadow"
+    ocr.trace_occluders(view.bvh, view.dg, tmode, R_AO, light, seed, sample, view.occ)
     if kind == "filter":
         p = ocr.reuse_params("window", 0, 0, "none")
         if view.effect == "ao":
             ocr.reuse_ao(None, view.dg, view.occ, R_AO, p, view.tmp)
         else:
-            ocr.reuse_shadow(None, view.dg, view.occ, light, p, view.tmp)
+            _reuse_light(ocr, view, p, view.tmp, light=light)
         ocr.filter_values(view.dg, ocr.reuse_params(pattern, size, size, "none", accumulate=accumulate), view.tmp,
                           out)
         return
@@ -106,13 +138,13 @@ def run_sample(ocr, view, spec, seed, sample, out, accumulate):
     if view.effect == "ao":
         ocr.reuse_ao(view.bvh, view.dg, view.occ, R_AO, p, out, view.ws)
     else:
-        ocr.reuse_shadow(view.bvh, view.dg, view.occ, light, p, out, view.ws)
+        _reuse_light(ocr, view, p, out, view.ws, light=light)
 
 
-def render(ocr, torch, view, spec, seed, nspp, first=0):
+def render(ocr, torch, view, spec, seed, nspp, first=0, light=None):
     out = torch.empty_like(view.tmp)
     for s in range(nspp):
-        run_sample(ocr, view, spec, seed, first + s, out, s > 0)
+        run_sample(ocr, view, spec, seed, first + s, out, s > 0, light)
     if nspp > 1:
         ocr.scale(out, 1.0 / nspp)
     return out
@@ -127,9 +159,9 @@ def mse(torch, est, ref, valid):
     return float(((est - ref) ** 2)[valid].mean().item())
 
 
-def square_light(w, size):
+def square_light(w, size, pdf=0):
     base = w.terrain_light()
-    return w.RectLight(base.center.copy(), base.edge_u * size, base.edge_v * size)
+    return w.RectLight(base.center.copy(), base.edge_u * size, base.edge_v * size, pdf)
 
 
 def time_per_spp(ocr, torch, view, spec, reps=5):
@@ -152,17 +184,19 @@ def evaluate(ocr, torch, effect, args, light_size=1.0):
     import workloads as w
     scene = w.terrain_scene(2)
     bvh = ocr.build_bvh(scene.V, scene.F)
-    light = square_light(w, light_size) if effect == "shadow" else None
+    pdf = 1 if args.light_pdf == "bilinear" else 0
+    light = square_light(w, light_size, pdf) if effect in LIGHT_EFFECTS else None
+    ref_light = square_light(w, light_size) if effect in LIGHT_EFFECTS else None
     W, H = args.width, args.height
     cams = [w.terrain_camera(W, H)] + [w.orbit_camera(v, args.views, W, H) for v in range(1, args.views)]
-    ms = methods(effect)
+    ms = methods(effect, args.light_pdf)
     budget = args.budget_ao if effect == "ao" else args.budget_shadow
     per_view = []
     times = None
     for vi, cam in enumerate(cams):
         view = View(ocr, torch, scene, bvh, cam, effect, light)
         t0 = time.time()
-        ref = render(ocr, torch, view, ms["RT"], 999, args.ref_spp)
+        ref = render(ocr, torch, view, ms["RT"], 999, args.ref_spp, light=ref_light)
         torch.cuda.synchronize()
         log(f"[quality] {effect} view {vi}: reference {args.ref_spp} spp in {time.time() - t0:.1f} s, "
             f"valid {view.gb.valid.mean():.3f}, mean {float(ref[view.valid].mean()):.4f}")
@@ -191,7 +225,8 @@ def evaluate(ocr, torch, effect, args, light_size=1.0):
     def ratios(key):
         return {n: float(np.mean([v[key][n] / v[key]["RT"] for v in per_view])) for n in names}
 
-    return dict(effect=effect, light_m=light_size if effect == "shadow" else None, views=len(cams), size=f"{W}x{H}",
+    return dict(effect=effect, light_m=light_size if effect in LIGHT_EFFECTS else None, light_pdf=args.light_pdf,
+                views=len(cams), size=f"{W}x{H}",
                 ref_spp=args.ref_spp, seeds=args.seeds,
                 budget_ms=budget, ms_per_spp={n: round(times[n], 4) for n in names},
                 equal_spp_relmse={n: float(np.mean([v["equal_spp"][n] for v in per_view])) for n in names},
@@ -204,7 +239,7 @@ def evaluate(ocr, torch, effect, args, light_size=1.0):
 
 def markdown(res):
     names = list(res["ms_per_spp"])
-    light = f", {res['light_m']:g} m light" if res["light_m"] else ""
+    light = f", {res['light_m']:g} m light, {res['light_pdf']} density" if res["light_m"] else ""
     lines = [f"### {res['effect']} ({res['size']}{light}, {res['views']} views, reference {res['ref_spp']} spp)", "",
              "| method | ms/spp | equal-spp RelMSE | ratio | MSE ratio | equal-time spp | equal-time RelMSE | ratio |",
              "|---|---|---|---|---|---|---|---|"]
@@ -230,6 +265,7 @@ def main():
     ap.add_argument("--budget-shadow", type=float, default=5.0)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--light-pdf", default="uniform", choices=["uniform", "bilinear"])
     args = ap.parse_args()
     import torch
     if not torch.cuda.is_available():
@@ -238,11 +274,11 @@ def main():
     ocr.lib()
     out = {}
     for effect in args.effects.split(","):
-        sizes = [float(v) for v in args.light_sizes.split(",")] if effect == "shadow" else [1.0]
+        sizes = [float(v) for v in args.light_sizes.split(",")] if effect in LIGHT_EFFECTS else [1.0]
         for size in sizes:
             res = evaluate(ocr, torch, effect, args, size)
             log(markdown(res))
-            out[effect if effect == "ao" else f"shadow_{size:g}m"] = res
+            out[effect if effect == "ao" else f"{effect}_{size:g}m"] = res
     print(json.dumps(out))
 
 

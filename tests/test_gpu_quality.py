@@ -2,7 +2,9 @@
 the oracle's FP64 quadrature at sampled pixels, and the properties of the
 estimators that hold on any scene -- biased reuse lowers the one-sample AO
 error, the unbiased estimators converge at the Monte Carlo rate, and
-light-sample reuse re-traced over 8 pixels behaves like 8 samples."""
+light-sample reuse re-traced over 8 pixels behaves like 8 samples; for
+solid-angle shadows and direct illumination, under uniform and bilinear
+light sampling, the unbiased estimators converge to the same reference."""
 import types
 
 import numpy as np
@@ -27,7 +29,8 @@ def ocr():
 
 
 def _args(**kw):
-    a = dict(views=1, ref_spp=256, seeds=2, budget_ao=2.0, budget_shadow=5.0, width=320, height=180)
+    a = dict(views=1, ref_spp=256, seeds=2, budget_ao=2.0, budget_shadow=5.0, width=320, height=180,
+             light_pdf="uniform")
     a.update(kw)
     return types.SimpleNamespace(**a)
 
@@ -68,4 +71,18 @@ def test_estimator_properties(ocr):
     assert sh["equal_spp_ratio"]["Light (8U)"] < 0.3
     for n in ("RT", "Occ (8U)"):
         c = sh["convergence"][n]
+        assert c["64"] < 0.08 * c["1"], (n, c)
+
+
+@pytest.mark.parametrize("effect", ["shadow_sa", "di"])
+@pytest.mark.parametrize("pdf", ["uniform", "bilinear"])
+def test_solid_angle_and_direct_illumination(ocr, effect, pdf):
+    import quality
+    res = quality.evaluate(ocr, torch, effect, _args(light_pdf=pdf), 4.0)
+    log(quality.markdown(res))
+    assert "Light (8U)" not in res["ms_per_spp"]
+    # unbiased estimators of either sampling density converge to the uniform
+    # no-reuse reference at the Monte Carlo rate
+    for n in ("RT", "Occ (8U)", "Occ (7x7U)"):
+        c = res["convergence"][n]
         assert c["64"] < 0.08 * c["1"], (n, c)
