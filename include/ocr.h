@@ -442,7 +442,8 @@ ocr_status ocr_plan_launch(ocr_plan *plan, void *stream);
 ocr_status ocr_plan_get_info(const ocr_plan *plan, ocr_plan_info *info);
 /* The plan's occluder records of view v (device pointers the plan owns). */
 ocr_status ocr_plan_get_records(const ocr_plan *plan, int32_t view, ocr_occluders *out);
-/* Wait for the device, then free the plan's memory, graph and stream. */
+/* Wait for the device, then free the plan's memory, graph and stream (freed
+ * even when the wait fails; that failure is returned as OCR_ERR_HIP). */
 ocr_status ocr_plan_free(ocr_plan *plan);
 
 /* ---------------------------------------------------------------------------

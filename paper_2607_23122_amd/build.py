@@ -11,6 +11,7 @@ import concurrent.futures as cf
 import os
 import shutil
 import subprocess
+import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -41,6 +42,11 @@ def _compile(src: str, obj_dir: str) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    # compiler warnings are shown, not swallowed (the host pass's note about the
+    # packed-FP32 target feature it does not know is expected)
+    warn = [ln for ln in r.stderr.splitlines() if "warning:" in ln and "packed-fp32-ops" not in ln]
+    if warn:
+        print("\n".join(warn), file=sys.stderr)
     return obj
 
 

@@ -211,7 +211,7 @@ ocr_status ocr_build_bvh(const float *verts, int64_t nverts, const uint32_t *tri
         e = hipMemcpyAsync((char *)b->mem + nbytes, hb.tris.data(), tbytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        hipFree(b->mem);
+        (void)hipFree(b->mem);
         delete b;
         return hip_fail(e, "BVH upload");
     }

@@ -119,8 +119,8 @@ hipError_t enqueue_all(ocr_plan *p, hipStream_t st) {
 }
 
 void destroy_graph(ocr_plan *p) {
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
     p->graph = nullptr;
 }
@@ -132,7 +132,7 @@ hipError_t time_trace(ocr_plan *p, hipStream_t st, double &ms) {
     if (e != hipSuccess) return e;
     e = hipEventCreate(&b);
     if (e != hipSuccess) {
-        hipEventDestroy(a);
+        (void)hipEventDestroy(a);
         return e;
     }
     std::vector<float> t;
@@ -145,8 +145,8 @@ hipError_t time_trace(ocr_plan *p, hipStream_t st, double &ms) {
         if (e == hipSuccess) e = hipEventElapsedTime(&x, a, b);
         if (rep > 0) t.push_back(x);
     }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     if (e == hipSuccess) {
         std::sort(t.begin(), t.end());
         ms = t[t.size() / 2];
@@ -189,8 +189,8 @@ ocr_status autotune(ocr_plan *p, hipStream_t st) {
 
 void free_plan(ocr_plan *p) {
     destroy_graph(p);
-    if (p->cap) hipStreamDestroy(p->cap);
-    if (p->mem) hipFree(p->mem);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->mem) (void)hipFree(p->mem);
     delete p;
 }
 
@@ -408,9 +408,10 @@ ocr_status ocr_plan_get_records(const ocr_plan *p, int32_t v, ocr_occluders *out
 
 ocr_status ocr_plan_free(ocr_plan *p) {
     if (!p) return OCR_OK;
-    hipDeviceSynchronize();
+    // the plan's memory is freed either way; a failed wait is reported
+    const hipError_t e = hipDeviceSynchronize();
     free_plan(p);
-    return OCR_OK;
+    return e == hipSuccess ? OCR_OK : hip_fail(e, "device synchronize before freeing the plan");
 }
 
 }  // extern "C"

@@ -197,7 +197,8 @@ void finish(ocr_server *s, Slot &sl, double end_ms, ocr_status st) {
 }
 
 void worker_loop(ocr_server *s) {
-    if (!s->opt.mock) hipSetDevice(s->device);
+    // (a worker that cannot select the device completes every request with OCR_ERR_HIP)
+    const hipError_t dev_e = s->opt.mock ? hipSuccess : hipSetDevice(s->device);
     const int poll_us = s->opt.poll_us > 0 ? s->opt.poll_us : 20;
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
@@ -247,7 +248,7 @@ void worker_loop(ocr_server *s) {
             } else if (s->opt.mock) {
                 idle->mock_end_ms = idle->start_ms + s->opt.mock_ns_per_pixel * 1e-6 * idle->job.w * idle->job.h;
             } else {
-                const ocr_status rc = launch_job(s, *idle);
+                const ocr_status rc = dev_e == hipSuccess ? launch_job(s, *idle) : OCR_ERR_HIP;
                 if (rc) finish(s, *idle, clock_ms(), rc);
             }
         }
@@ -266,12 +267,13 @@ void worker_loop(ocr_server *s) {
 void destroy_server(ocr_server *s) {
     for (Slot &sl : s->slots) {
         if (sl.stream) {
-            hipStreamSynchronize(sl.stream);
-            hipStreamDestroy(sl.stream);
+            // (teardown: nothing is left to report an error to)
+            (void)hipStreamSynchronize(sl.stream);
+            (void)hipStreamDestroy(sl.stream);
         }
-        if (sl.done) hipEventDestroy(sl.done);
+        if (sl.done) (void)hipEventDestroy(sl.done);
     }
-    if (s->arena_mem) hipFree(s->arena_mem);
+    if (s->arena_mem) (void)hipFree(s->arena_mem);
     delete s->arena;
     delete s;
 }
