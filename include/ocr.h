@@ -47,6 +47,12 @@ enum {
 
 /* effect */
 enum { OCR_AO = 0, OCR_SHADOW = 1 };
+/* Effects a batched view or a served request can ask for besides OCR_AO and
+ * OCR_SHADOW: shadows under the solid-angle definition
+ * (ocr_reuse_shadow_solid_angle) and direct illumination
+ * (ocr_reuse_direct_illumination); both trace shadow records.  The per-view
+ * trace and validation entry points take OCR_AO and OCR_SHADOW only. */
+enum { OCR_SHADOW_SOLID_ANGLE = 2, OCR_DIRECT_ILLUMINATION = 3 };
 /* estimator: no reuse (Eqs. ao-mc-estimator / shadow-mc-estimator), biased
  * reuse (local first-hit consistency), unbiased reuse (first-hit validation) */
 enum { OCR_NOREUSE = 0, OCR_BIASED = 1, OCR_UNBIASED = 2 };
@@ -369,8 +375,8 @@ ocr_status ocr_scale(float *out, int64_t n, float s, void *stream);
  * of uneven size, over several scenes and mixed effects, as one persistent
  * trace launch and one persistent reuse launch over a (view, tile) work list,
  * recorded once into a HIP graph and replayed.  Each view's output is bitwise
- * identical to ocr_trace_occluders followed by ocr_reuse_ao/_shadow (and, for
- * OCR_UNBIASED, ocr_validate_pairs) with the same arguments: the schedule
+ * identical to ocr_trace_occluders followed by the mode's per-view reuse entry
+ * point (and, for OCR_UNBIASED, ocr_validate_pairs) with the same arguments: the schedule
  * changes only which lane or block computes a pixel, never its arithmetic.
  * ------------------------------------------------------------------------- */
 
@@ -378,10 +384,16 @@ ocr_status ocr_scale(float *out, int64_t n, float s, void *stream);
  * plan's lifetime.
  *   bvh:       the view's scene
  *   gbuf:      device G-buffer (as for ocr_trace_occluders)
- *   mode, ao_radius, light, seed, sample: as for ocr_trace_occluders (light
- *              ignored for AO)
+ *   mode:      OCR_AO, OCR_SHADOW, OCR_SHADOW_SOLID_ANGLE or
+ *              OCR_DIRECT_ILLUMINATION (the last two trace shadow records)
+ *   ao_radius, light, seed, sample: as for ocr_trace_occluders (light ignored
+ *              for AO; uniformly sampled lights only, OCR_ERR_UNSUPPORTED
+ *              for another density)
  *   params:    reuse configuration (accumulate and validated must be 0)
- *   out:       device float[h][w], the estimate (as for ocr_reuse_ao/_shadow) */
+ *   out:       device float[h][w], the estimate (as for the per-view reuse
+ *              entry point of the mode)
+ *   radiance, albedo: direct illumination only (as
+ *              ocr_reuse_direct_illumination) */
 typedef struct {
     const ocr_bvh *bvh;
     ocr_gbuffer gbuf;
@@ -392,6 +404,8 @@ typedef struct {
     uint32_t sample;
     ocr_reuse_params params;
     float *out;
+    float radiance;
+    float albedo;
 } ocr_view_desc;
 
 typedef struct ocr_plan ocr_plan;
@@ -481,10 +495,13 @@ typedef struct {
     int32_t fault_every;
 } ocr_server_options;
 
-/* A frame request.  scene_id / view select a resident G-buffer.  out: device
- * float[h][w] to write, or NULL to have the server keep the output in its
- * arena (ocr_result.out) until ocr_server_release.  arrival_ms: arrival time
- * on the server clock (ocr_server_now_ms), 0 = stamped at submission. */
+/* A frame request.  scene_id / view select a resident G-buffer.  mode:
+ * OCR_AO, OCR_SHADOW, OCR_SHADOW_SOLID_ANGLE or OCR_DIRECT_ILLUMINATION (the
+ * light may use either emitter density).  out: device float[h][w] to write, or
+ * NULL to have the server keep the output in its arena (ocr_result.out) until
+ * ocr_server_release.  arrival_ms: arrival time on the server clock
+ * (ocr_server_now_ms), 0 = stamped at submission.  radiance, albedo: direct
+ * illumination only (as ocr_reuse_direct_illumination). */
 typedef struct {
     int32_t scene_id;
     int32_t view;
@@ -496,6 +513,8 @@ typedef struct {
     ocr_reuse_params params;
     float *out;
     double arrival_ms;
+    float radiance;
+    float albedo;
 } ocr_request;
 
 typedef struct {

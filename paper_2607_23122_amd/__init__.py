@@ -24,6 +24,9 @@ HIT_MISS = 0xFFFFFFFF
 HIT_SELF = 0xFFFFFFFE
 
 MODES = {"ao": OCR_AO, "shadow": OCR_SHADOW}
+# effects of a batched view or a served request: the trace modes plus the
+# light effects that reuse shadow records
+REQUEST_MODES = dict(MODES, shadow_sa=2, di=3)
 ESTIMATORS = {"none": OCR_NOREUSE, "biased": OCR_BIASED, "unbiased": OCR_UNBIASED}
 PATTERNS = {"window": OCR_WINDOW, "group": OCR_GROUP}
 
@@ -65,7 +68,7 @@ class BvhInfo(ctypes.Structure):
 class ViewDesc(ctypes.Structure):
     _fields_ = [("bvh", ctypes.c_void_p), ("gbuf", _GBuffer), ("mode", ctypes.c_int32), ("ao_radius", ctypes.c_float),
                 ("light", _Light), ("seed", ctypes.c_uint64), ("sample", ctypes.c_uint32), ("params", ReuseParams),
-                ("out", ctypes.c_void_p)]
+                ("out", ctypes.c_void_p), ("radiance", ctypes.c_float), ("albedo", ctypes.c_float)]
 
 
 OCR_PACK_ROW, OCR_PACK_BLOCK8, OCR_PACK_MORTON = 0, 1, 2
@@ -94,7 +97,7 @@ class Request(ctypes.Structure):
     _fields_ = [("scene_id", ctypes.c_int32), ("view", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("ao_radius", ctypes.c_float), ("light", _Light), ("seed", ctypes.c_uint64),
                 ("sample", ctypes.c_uint32), ("params", ReuseParams), ("out", ctypes.c_void_p),
-                ("arrival_ms", ctypes.c_double)]
+                ("arrival_ms", ctypes.c_double), ("radiance", ctypes.c_float), ("albedo", ctypes.c_float)]
 
 
 class Result(ctypes.Structure):
@@ -605,11 +608,13 @@ def _mode(mode) -> int:
 
 
 def view_desc(bvh: BVH, gbuf: DeviceGBuffer, out, mode="ao", ao_radius=1.0, light=None, seed=1, sample=0,
-              params: ReuseParams | None = None) -> ViewDesc:
+              params: ReuseParams | None = None, radiance=1.0, albedo=1.0) -> ViewDesc:
     d = ViewDesc()
     d.bvh = bvh.h.value
     d.gbuf = gbuf.c()
-    d.mode = _mode(mode)
+    d.mode = REQUEST_MODES[mode] if isinstance(mode, str) else int(mode)
+    d.radiance = float(radiance)
+    d.albedo = float(albedo)
     d.ao_radius = float(ao_radius)
     if light is not None:
         d.light = light_struct(light)
@@ -676,11 +681,13 @@ def server_now_ms() -> float:
 
 
 def request(scene_id: int, view: int, mode="ao", ao_radius=1.0, light=None, seed=1, sample=0,
-            params: ReuseParams | None = None, out=None, arrival_ms=0.0) -> Request:
+            params: ReuseParams | None = None, out=None, arrival_ms=0.0, radiance=1.0, albedo=1.0) -> Request:
     r = Request()
     r.scene_id = int(scene_id)
     r.view = int(view)
-    r.mode = _mode(mode)
+    r.mode = REQUEST_MODES[mode] if isinstance(mode, str) else int(mode)
+    r.radiance = float(radiance)
+    r.albedo = float(albedo)
     r.ao_radius = float(ao_radius)
     if light is not None:
         r.light = light_struct(light)

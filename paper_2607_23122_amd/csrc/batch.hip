@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kBBlock, 7) void batch_trace_kernel(const BatchView
 }
 
 // One block per reuse item (a window target tile of a window or no-reuse view).
-__global__ __launch_bounds__(kRBlock) void batch_reuse_kernel(const BatchView *__restrict__ views,
+__global__ __launch_bounds__(kRBlock, 6) void batch_reuse_kernel(const BatchView *__restrict__ views,
                                                               const uint32_t *__restrict__ r_first, int nviews,
                                                               const uint32_t *__restrict__ q_start, uint32_t *ctr) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -152,29 +152,52 @@ __global__ __launch_bounds__(kRBlock) void batch_reuse_kernel(const BatchView *_
                 const int px = tx * kWTX + t % kWTX, py = ty * kWTY + t / kWTX;
                 if (px < V.g.w && py < V.g.h) {
                     const int64_t gi = (int64_t)py * V.g.w + px;
-                    const bool valid = V.g.prim[gi] != OCR_HIT_MISS;
-                    const bool miss = V.occ.hit[gi] == OCR_HIT_MISS;
-                    V.out[gi] =
-                        V.mode == OCR_AO ? ((!valid || miss) ? 1.0f : 0.0f) : ((valid && miss) ? 1.0f : 0.0f);
+                    float v;
+                    switch (V.mode) {
+                        case OCR_AO: v = noreuse_value<OCR_AO>(V.g, V.occ, V.L, gi, 1.0f); break;
+                        case OCR_SHADOW: v = noreuse_value<OCR_SHADOW>(V.g, V.occ, V.L, gi, 1.0f); break;
+                        case kShadowSA: v = noreuse_value<kShadowSA>(V.g, V.occ, V.L, gi, 1.0f); break;
+                        default: v = noreuse_value<kDI>(V.g, V.occ, V.L, gi, V.scale); break;
+                    }
+                    V.out[gi] = v;
                 }
             }
             continue;
         }
         const bool unb = V.estimator == OCR_UNBIASED;
-        if (V.mode == OCR_AO) {
-            if (unb)
-                reuse_window_tile<OCR_AO, true>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius, 0, 0, V.out,
-                                                tx, ty);
-            else
-                reuse_window_tile<OCR_AO, false>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius, 0, 0,
-                                                 V.out, tx, ty);
-        } else {
-            if (unb)
-                reuse_window_tile<OCR_SHADOW, true>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius,
-                                                    V.dark_guard, 0, V.out, tx, ty);
-            else
-                reuse_window_tile<OCR_SHADOW, false>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius,
-                                                     V.dark_guard, 0, V.out, tx, ty);
+        switch (V.mode) {
+            case OCR_AO:
+                if (unb)
+                    reuse_window_tile<OCR_AO, true>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius, 0, 0,
+                                                    V.out, tx, ty);
+                else
+                    reuse_window_tile<OCR_AO, false>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius, 0, 0,
+                                                     V.out, tx, ty);
+                break;
+            case OCR_SHADOW:
+                if (unb)
+                    reuse_window_tile<OCR_SHADOW, true>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius,
+                                                        V.dark_guard, 0, V.out, tx, ty);
+                else
+                    reuse_window_tile<OCR_SHADOW, false>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius,
+                                                         V.dark_guard, 0, V.out, tx, ty);
+                break;
+            case kShadowSA:
+                if (unb)
+                    reuse_window_tile<kShadowSA, true>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius,
+                                                       V.dark_guard, 0, V.out, tx, ty);
+                else
+                    reuse_window_tile<kShadowSA, false>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius,
+                                                        V.dark_guard, 0, V.out, tx, ty);
+                break;
+            default:
+                if (unb)
+                    reuse_window_tile<kDI, true>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius,
+                                                 V.dark_guard, 0, V.out, tx, ty, V.scale);
+                else
+                    reuse_window_tile<kDI, false>(smem, V.g, V.occ, V.R2, V.L, V.bits, V.words, V.radius,
+                                                  V.dark_guard, 0, V.out, tx, ty, V.scale);
+                break;
         }
     }
 }

@@ -15,7 +15,7 @@ struct BatchView {
     float R2;
     uint32_t sd;        // folded seed
     uint32_t sample;
-    int32_t mode;
+    int32_t mode;       // OCR_AO, OCR_SHADOW, kShadowSA or kDI (the last two trace shadow records)
     int32_t estimator;
     int32_t radius;     // window radius
     int32_t dark_guard; // already restricted to the biased estimator
@@ -23,6 +23,7 @@ struct BatchView {
     int32_t r_tiles_x;  // reuse tiles (kWTX x kWTY) per row
     const uint32_t *bits;
     float *out;
+    float scale;        // direct illumination: albedo * radiance / pi (1 otherwise)
 };
 
 // Work queues: counters [0, 8) for the trace ranges, [8, 16) for the reuse

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -102,13 +103,14 @@ hipError_t enqueue_all(ocr_plan *p, hipStream_t st) {
     if (e != hipSuccess) return e;
     for (int v : p->unb_views) {
         const BatchView &V = p->hv[v];
-        e = launch_validate(V.bvh, V.g, V.occ, V.mode, V.R, V.L, p->desc[v].params, const_cast<uint32_t *>(V.bits),
-                            nullptr, st);
+        // the light effects validate the shadow pairs
+        e = launch_validate(V.bvh, V.g, V.occ, V.mode == OCR_AO ? OCR_AO : OCR_SHADOW, V.R, V.L, p->desc[v].params,
+                            const_cast<uint32_t *>(V.bits), nullptr, st);
         if (e != hipSuccess) return e;
     }
     for (int v : p->grp_views) {
         const BatchView &V = p->hv[v];
-        e = launch_reuse(V.g, V.occ, V.mode, V.R, V.L, p->desc[v].params, V.bits, V.out, st);
+        e = launch_reuse(V.g, V.occ, V.mode, V.R, V.L, p->desc[v].params, V.bits, V.out, st, V.scale);
         if (e != hipSuccess) return e;
     }
     if (p->reuse_items > 0) {
@@ -224,7 +226,18 @@ ocr_status ocr_plan_create(const ocr_view_desc *views, int32_t nviews, const ocr
         if (!d.out) return fail(OCR_ERR_INVALID_ARG, "view %d: out is NULL", v);
         BatchView &B = hv[v];
         std::memset(&B, 0, sizeof B);
-        if ((st = check_effect(d.mode, d.ao_radius, &d.light, B.L))) return fail(st, "view %d: %s", v, ocr_last_error());
+        if (d.mode < OCR_AO || d.mode > OCR_DIRECT_ILLUMINATION)
+            return fail(OCR_ERR_INVALID_ARG, "view %d: mode %d out of range", v, d.mode);
+        // the light effects trace shadow records (uniformly sampled lights)
+        const int32_t tmode = d.mode == OCR_AO ? OCR_AO : OCR_SHADOW;
+        if ((st = check_effect(tmode, d.ao_radius, &d.light, B.L))) return fail(st, "view %d: %s", v, ocr_last_error());
+        if (d.mode == OCR_DIRECT_ILLUMINATION && !(std::isfinite(d.radiance) && d.radiance >= 0.0f &&
+                                                   std::isfinite(d.albedo) && d.albedo >= 0.0f))
+            return fail(OCR_ERR_INVALID_ARG, "view %d: radiance %g and albedo %g must be finite and >= 0", v,
+                        (double)d.radiance, (double)d.albedo);
+        B.scale = d.mode == OCR_DIRECT_ILLUMINATION
+                      ? (float)((double)d.albedo * (double)d.radiance / 3.14159265358979323846)
+                      : 1.0f;
         B.bvh = d.bvh->dev;
         B.g = view(&d.gbuf);
         B.R = d.mode == OCR_AO ? d.ao_radius : 1.0f;

@@ -171,42 +171,7 @@ __global__ __launch_bounds__(kRBlock) void noreuse_kernel(GBufView g, OccView oc
                                                           float *out, float scale) {
     const int64_t gi = (int64_t)blockIdx.x * kRBlock + threadIdx.x;
     if (gi >= (int64_t)g.w * g.h) return;
-    const bool valid = g.prim[gi] != OCR_HIT_MISS;
-    float v;
-    if constexpr (MODE == OCR_AO) {
-        v = (!valid || occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
-    } else if constexpr (MODE == OCR_SHADOW && !kBilinear<LT>) {
-        v = (valid && occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
-    } else {
-        // solid-angle definition / direct illumination / a light sampled from
-        // the bilinear density, S(i) = {i}: the unshadowed term minus
-        // C(x_i, z_i) for a hit whose own density is positive (the ratio p/p
-        // is 1)
-        v = 0.0f;
-        if (valid) {
-            float x[3], n[3], o[3];
-            ld3(g.pos, gi, x);
-            ld3(g.nrm, gi, n);
-            offset_point(x, n, o);
-            float Bg = 0.0f;
-            const uint32_t hit = occ.hit[gi];
-            if (hit < OCR_HIT_SELF) {
-                float dz[3], nz[3];
-                ld3(occ.dz, gi, dz);
-                ld3(occ.nz, gi, nz);
-                const auto rk = recv_of(o, L);
-                if (dens_light(dz, n, rk, nz, L) > 0.0f) {
-                    Bg = 1.0f;
-                    if constexpr (MODE == kDI) Bg = di_pair_g(dz, n, rk.hk, L);
-                    else if constexpr (MODE == kShadowSA) Bg = sa_pair_g(dz, rk.hk, L);
-                    if constexpr (kBilinear<LT>) Bg *= inv_bilinear_q(dz, rk, L);
-                }
-            }
-            if constexpr (MODE == kDI) v = di_estimate(o, n, L, Bg, scale);
-            else if constexpr (MODE == kShadowSA) v = sa_estimate(o, n, L, Bg);
-            else v = front_light(o, n, L) - Bg;
-        }
-    }
+    const float v = noreuse_value<MODE>(g, occ, L, gi, scale);
     out[gi] = accumulate ? out[gi] + v : v;
 }
 

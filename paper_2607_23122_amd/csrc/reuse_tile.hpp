@@ -42,6 +42,45 @@ __device__ inline float finish(int mode, bool valid, float B, float F, bool dark
     return accumulate ? prev + v : v;
 }
 
+// The no-reuse estimate of pixel gi (S(i) = {i}).  AO: 1 - [hit]; area
+// shadows of a uniformly sampled light: [unblocked].  The solid-angle and
+// direct-illumination quantities, and any light sampled from the bilinear
+// density, take the N = 1 case of their MIS estimators: the unshadowed term
+// minus C(x_i, z_i) for a hit whose own density is positive (the ratio p/p
+// is 1).
+template <int MODE, class LT>
+__device__ inline float noreuse_value(const GBufView &g, const OccView &occ, const LT &L, int64_t gi, float scale) {
+    const bool valid = g.prim[gi] != OCR_HIT_MISS;
+    if constexpr (MODE == OCR_AO) {
+        return (!valid || occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
+    } else if constexpr (MODE == OCR_SHADOW && !kBilinear<LT>) {
+        return (valid && occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
+    } else {
+        if (!valid) return 0.0f;
+        float x[3], n[3], o[3];
+        ld3(g.pos, gi, x);
+        ld3(g.nrm, gi, n);
+        offset_point(x, n, o);
+        float Bg = 0.0f;
+        const uint32_t hit = occ.hit[gi];
+        if (hit < OCR_HIT_SELF) {
+            float dz[3], nz[3];
+            ld3(occ.dz, gi, dz);
+            ld3(occ.nz, gi, nz);
+            const auto rk = recv_of(o, L);
+            if (dens_light(dz, n, rk, nz, L) > 0.0f) {
+                Bg = 1.0f;
+                if constexpr (MODE == kDI) Bg = di_pair_g(dz, n, rk.hk, L);
+                else if constexpr (MODE == kShadowSA) Bg = sa_pair_g(dz, rk.hk, L);
+                if constexpr (kBilinear<LT>) Bg *= inv_bilinear_q(dz, rk, L);
+            }
+        }
+        if constexpr (MODE == kDI) return di_estimate(o, n, L, Bg, scale);
+        else if constexpr (MODE == kShadowSA) return sa_estimate(o, n, L, Bg);
+        else return front_light(o, n, L) - Bg;
+    }
+}
+
 // LDS layout of the window kernel for radius R (dynamic shared memory).
 struct WinLayout {
     int RWX, RWY, cells, side, dens, hsum, words;

@@ -160,13 +160,24 @@ ocr_status launch_job(ocr_server *s, Slot &sl) {
     void *ws = j.ws_bytes ? (void *)(st + 2 * align256(12 * px) + align256(4 * px)) : nullptr;
     float *out = r.out ? r.out : (float *)(s->arena_mem + sl.out_off);
     ocr_reuse_params p = r.params;
+    // the light effects all reuse shadow records
+    const int32_t tmode = r.mode == OCR_AO ? OCR_AO : OCR_SHADOW;
     ocr_status rc =
-        ocr_trace_occluders(sc.bvh, &gb, r.mode, r.ao_radius, &r.light, r.seed, r.sample, &occ, sl.stream);
+        ocr_trace_occluders(sc.bvh, &gb, tmode, r.ao_radius, &r.light, r.seed, r.sample, &occ, sl.stream);
     if (rc) return rc;
-    if (r.mode == OCR_AO)
-        rc = ocr_reuse_ao(sc.bvh, &gb, &occ, r.ao_radius, &p, ws, j.ws_bytes, out, sl.stream);
-    else
-        rc = ocr_reuse_shadow(sc.bvh, &gb, &occ, &r.light, &p, ws, j.ws_bytes, out, sl.stream);
+    switch (r.mode) {
+        case OCR_AO: rc = ocr_reuse_ao(sc.bvh, &gb, &occ, r.ao_radius, &p, ws, j.ws_bytes, out, sl.stream); break;
+        case OCR_SHADOW:
+            rc = ocr_reuse_shadow(sc.bvh, &gb, &occ, &r.light, &p, ws, j.ws_bytes, out, sl.stream);
+            break;
+        case OCR_SHADOW_SOLID_ANGLE:
+            rc = ocr_reuse_shadow_solid_angle(sc.bvh, &gb, &occ, &r.light, &p, ws, j.ws_bytes, out, sl.stream);
+            break;
+        default:
+            rc = ocr_reuse_direct_illumination(sc.bvh, &gb, &occ, &r.light, r.radiance, r.albedo, &p, ws, j.ws_bytes,
+                                               out, sl.stream);
+            break;
+    }
     if (rc) return rc;
     return hipEventRecord(sl.done, sl.stream) == hipSuccess ? OCR_OK : OCR_ERR_HIP;
 }
@@ -344,7 +355,18 @@ ocr_status ocr_server_submit(ocr_server *s, const ocr_request *r, uint64_t *tick
     if (r->params.accumulate || r->params.validated)
         return fail(OCR_ERR_INVALID_ARG, "accumulate and validated must be 0 in a request");
     LightF L;
-    if (ocr_status st = check_effect(r->mode, r->ao_radius, &r->light, L)) return st;
+    if (r->mode == OCR_AO) {
+        if (ocr_status st = check_effect(r->mode, r->ao_radius, &r->light, L)) return st;
+    } else if (r->mode >= OCR_SHADOW && r->mode <= OCR_DIRECT_ILLUMINATION) {
+        // any emitter density: the per-view entry points take it
+        if (ocr_status st = make_light(&r->light, L)) return st;
+        if (r->mode == OCR_DIRECT_ILLUMINATION &&
+            !(std::isfinite(r->radiance) && r->radiance >= 0.0f && std::isfinite(r->albedo) && r->albedo >= 0.0f))
+            return fail(OCR_ERR_INVALID_ARG, "radiance %g and albedo %g must be finite and >= 0",
+                        (double)r->radiance, (double)r->albedo);
+    } else {
+        return fail(OCR_ERR_INVALID_ARG, "request mode %d out of range", r->mode);
+    }
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stop) return fail(OCR_ERR_BUSY, "server is stopping");
     if (r->scene_id < 0 || r->scene_id >= (int32_t)s->scenes.size())

@@ -1,5 +1,6 @@
 """Batched schedule on the GPU: one plan over many views of uneven size,
-several scenes and mixed AO / shadow, estimators and patterns.
+several scenes and mixed AO, shadows, solid-angle shadows and direct
+illumination, estimators and patterns.
 
 Each view's records and estimate must be bitwise identical to the per-view
 entry points with the same arguments (which the parity tests hold to the
@@ -41,7 +42,16 @@ SPECS = [(0, 61, 37, "ao", "window", 2, "biased", True),
          (0, 33, 17, "ao", "group", 8, "biased", True),
          (1, 100, 60, "shadow", "group", 4, "unbiased", True),
          (0, 1, 1, "ao", "window", 2, "biased", True),
-         (1, 64, 64, "shadow", "window", 8, "biased", False)]
+         (1, 64, 64, "shadow", "window", 8, "biased", False),
+         (0, 77, 41, "shadow_sa", "window", 3, "biased", True),
+         (1, 90, 50, "shadow_sa", "window", 2, "unbiased", True),
+         (0, 40, 40, "shadow_sa", "group", 8, "unbiased", True),
+         (1, 120, 64, "di", "window", 3, "biased", True),
+         (0, 64, 48, "di", "window", 3, "unbiased", True),
+         (1, 50, 30, "di", "window", 2, "none", True),
+         (0, 36, 20, "di", "group", 4, "biased", True),
+         (1, 70, 31, "shadow_sa", "window", 3, "none", True)]
+DI_RADIANCE, DI_ALBEDO = 50.0, 0.7
 
 
 class View:
@@ -61,16 +71,22 @@ def mixed(ocr):
         v.gb = w.render_gbuffer(scenes[si], cam)
         v.dg = ocr.DeviceGBuffer.from_host(v.gb)
         v.R = 1.0 if si == 0 else 2.0
-        v.light = lights[si] if mode == "shadow" else None
+        v.light = lights[si] if mode != "ao" else None
         v.seed, v.sample = 100 + i, i % 3
         v.params = ocr.reuse_params(pattern, size, size, est, dark_guard=guard)
         v.opattern, v.osize, v.oest, v.oguard = pattern, size, est, guard
         # the per-view reference
-        occ = ocr.trace_occluders(bvhs[si], v.dg, mode, v.R, v.light, v.seed, v.sample)
+        occ = ocr.trace_occluders(bvhs[si], v.dg, "ao" if mode == "ao" else "shadow", v.R, v.light, v.seed,
+                                  v.sample)
         if mode == "ao":
             ref = ocr.reuse_ao(bvhs[si], v.dg, occ, v.R, v.params)
-        else:
+        elif mode == "shadow":
             ref = ocr.reuse_shadow(bvhs[si], v.dg, occ, v.light, v.params)
+        elif mode == "shadow_sa":
+            ref = ocr.reuse_shadow_solid_angle(bvhs[si], v.dg, occ, v.light, v.params)
+        else:
+            ref = ocr.reuse_direct_illumination(bvhs[si], v.dg, occ, v.light, v.params, radiance=DI_RADIANCE,
+                                                albedo=DI_ALBEDO)
         torch.cuda.synchronize()
         v.ref_out = to_np(ref).copy()
         v.ref_hit = occ.hit_u32().copy()
@@ -81,8 +97,8 @@ def mixed(ocr):
 
 def _descs(ocr, bvhs, views):
     outs = [torch.full((v.H, v.W), float("nan"), dtype=torch.float32, device="cuda") for v in views]
-    descs = [ocr.view_desc(bvhs[v.si], v.dg, outs[i], v.mode, v.R, v.light, v.seed, v.sample, v.params)
-             for i, v in enumerate(views)]
+    descs = [ocr.view_desc(bvhs[v.si], v.dg, outs[i], v.mode, v.R, v.light, v.seed, v.sample, v.params,
+                           radiance=DI_RADIANCE, albedo=DI_ALBEDO) for i, v in enumerate(views)]
     return descs, outs
 
 
@@ -151,13 +167,17 @@ def test_plan_views_against_oracle(ocr, mixed):
     plan = ocr.Plan(descs, ocr.plan_tuning((16, 16), "block8", True))
     plan.launch()
     torch.cuda.synchronize()
-    for i in (0, 1, 3):
+    for i in (0, 1, 3, 9, 12):
         v = views[i]
         log(f"[plan vs oracle] view {i}: {v.W}x{v.H} {v.mode} {v.opattern} {v.osize} {v.oest}")
         p = oracle.params(v.mode, v.oest, v.opattern, radius=v.osize, group_n=v.osize, dark_guard=v.oguard,
                           ao_radius=v.R, light=v.light, seed=v.seed, sample=v.sample)
         osc = oracle.Scene(scenes[v.si].V, scenes[v.si].F)
         rec, res = oracle.frame(osc, v.gb, p)
+        if v.mode == "di":
+            # the oracle works in units of albedo * radiance / pi
+            k = DI_ALBEDO * DI_RADIANCE / np.pi
+            res.value, res.var = res.value * k, res.var * k
         _, _, hit = plan.records_host(i, v.H, v.W)
         st = compare_values(to_np(outs[i]), res, exclude=mismatch_reach(hit, rec, p))
         log(f"    {st}")
@@ -184,6 +204,20 @@ def test_plan_argument_errors(ocr, mixed):
         ocr.Plan(bad, ocr.plan_tuning())
     with pytest.raises(ocr.OcrError):
         ocr.Plan([], ocr.plan_tuning())
+    # an unknown mode, a negative radiance, and a light of another density
+    bad = list(_descs(ocr, bvhs, views[1:3])[0])
+    bad[0].mode = 7
+    with pytest.raises(ocr.OcrError):
+        ocr.Plan(bad, ocr.plan_tuning())
+    bad[0].mode = 3
+    bad[0].radiance = -1.0
+    with pytest.raises(ocr.OcrError):
+        ocr.Plan(bad, ocr.plan_tuning())
+    bad[0].radiance = 1.0
+    bad[0].light.pdf = 1
+    with pytest.raises(ocr.OcrError) as e:
+        ocr.Plan(bad, ocr.plan_tuning())
+    assert e.value.status == -4
 
 
 def test_batched_workload_full_size(ocr):

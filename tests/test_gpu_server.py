@@ -2,7 +2,9 @@
 stream slots under an HBM budget.  Every result must be bitwise identical to
 the same request run alone through the per-view entry points, whether it ran
 in a mix with overlapping requests, waited for memory, or wrote to a
-server-held output."""
+server-held output.  The mix holds AO, shadows, solid-angle shadows and
+direct illumination, with lights sampled uniformly or from the bilinear
+density."""
 import time
 
 import numpy as np
@@ -29,6 +31,7 @@ BOX_LIGHT = w.RectLight(np.array([0.0, 6.0, 0.0], np.float32), np.array([2.0, 0.
                         np.array([0.0, 0.0, 2.0], np.float32))
 SIZES = [(160, 90), (96, 96), (257, 131)]
 CONFIGS = [("window", 3, "biased"), ("window", 2, "unbiased"), ("group", 8, "biased"), ("window", 3, "none")]
+DI_RADIANCE, DI_ALBEDO = 50.0, 0.7
 
 
 @pytest.fixture(scope="module")
@@ -48,17 +51,28 @@ def world(ocr):
     reqs = []
     for i in range(24):
         si, vi = int(rng.integers(2)), int(rng.integers(len(SIZES)))
-        mode = "ao" if rng.random() < 0.5 else "shadow"
+        mode = ["ao", "shadow", "shadow_sa", "di"][int(rng.integers(4))]
         pattern, size, est = CONFIGS[int(rng.integers(len(CONFIGS)))]
-        reqs.append(dict(si=si, vi=vi, mode=mode, R=1.0 if si == 0 else 2.0,
-                         light=lights[si] if mode == "shadow" else None, seed=1000 + i, sample=i % 4,
-                         params=ocr.reuse_params(pattern, size, size, est)))
+        light = None
+        if mode != "ao":
+            b = lights[si]
+            light = w.RectLight(b.center, b.edge_u, b.edge_v, int(rng.integers(2)))  # either density
+        reqs.append(dict(si=si, vi=vi, mode=mode, R=1.0 if si == 0 else 2.0, light=light, seed=1000 + i,
+                         sample=i % 4, params=ocr.reuse_params(pattern, size, size, est)))
     # each request alone, through the per-view entry points
     for r in reqs:
-        dg = pools[r["si"]][r["vi"]][1]
-        occ = ocr.trace_occluders(bvhs[r["si"]], dg, r["mode"], r["R"], r["light"], r["seed"], r["sample"])
-        out = ocr.reuse_ao(bvhs[r["si"]], dg, occ, r["R"], r["params"]) if r["mode"] == "ao" else \
-            ocr.reuse_shadow(bvhs[r["si"]], dg, occ, r["light"], r["params"])
+        dg, bvh = pools[r["si"]][r["vi"]][1], bvhs[r["si"]]
+        occ = ocr.trace_occluders(bvh, dg, "ao" if r["mode"] == "ao" else "shadow", r["R"], r["light"], r["seed"],
+                                  r["sample"])
+        if r["mode"] == "ao":
+            out = ocr.reuse_ao(bvh, dg, occ, r["R"], r["params"])
+        elif r["mode"] == "shadow":
+            out = ocr.reuse_shadow(bvh, dg, occ, r["light"], r["params"])
+        elif r["mode"] == "shadow_sa":
+            out = ocr.reuse_shadow_solid_angle(bvh, dg, occ, r["light"], r["params"])
+        else:
+            out = ocr.reuse_direct_illumination(bvh, dg, occ, r["light"], r["params"], radiance=DI_RADIANCE,
+                                                albedo=DI_ALBEDO)
         torch.cuda.synchronize()
         r["ref"] = to_np(out).copy()
     return bvhs, pools, reqs
@@ -76,7 +90,7 @@ def _serve(ocr, bvhs, pools, reqs, budget, slots, held, pace_ms=0.0):
     for k, r in enumerate(reqs):
         out = bufs[k]
         rq = ocr.request(sids[r["si"]], r["vi"], r["mode"], r["R"], r["light"], r["seed"], r["sample"], r["params"],
-                         out)
+                         out, radiance=DI_RADIANCE, albedo=DI_ALBEDO)
         t = srv.submit(rq)
         tickets[t] = k
         outs[t] = out

@@ -114,9 +114,14 @@ def test_argument_checks():
     import workloads as w
     lt = w.RectLight(np.array([0, 5, 0], np.float32), np.array([1, 0, 0], np.float32),
                      np.array([0, 0, 1], np.float32), 1)
-    assert srv.try_submit(ocr.request(sid, 0, mode="shadow", light=lt, out=1))[0] == -4  # bilinear density: not served
+    for mode in ("shadow", "shadow_sa", "di"):
+        assert srv.try_submit(ocr.request(sid, 0, mode=mode, light=lt, out=1))[0] == 0  # bilinear density served
+    bad_di = ocr.request(sid, 0, mode="di", light=lt, out=1, radiance=-1.0)
+    assert srv.try_submit(bad_di)[0] == -1                  # negative radiance
+    bad_di = ocr.request(sid, 0, mode="di", light=lt, out=1, albedo=float("nan"))
+    assert srv.try_submit(bad_di)[0] == -1                  # non-finite albedo
     lt.pdf = 7
-    assert srv.try_submit(ocr.request(sid, 0, mode="shadow", light=lt, out=1))[0] == -1  # unknown density
+    assert srv.try_submit(ocr.request(sid, 0, mode="shadow_sa", light=lt, out=1))[0] == -1  # unknown density
     with pytest.raises(ocr.OcrError):
         ocr.Server(100, slots=1, mock=True)                  # budget below the minimum
     with pytest.raises(ocr.OcrError):
