@@ -179,7 +179,8 @@ ocr_status ocr_bvh_get_info(const ocr_bvh *bvh, ocr_bvh_info *info);
  *   AO (mode OCR_AO): cosine-weighted direction (Eq. ao-direction-pdf, by
  *     Malley's method in the basis of Duff et al., JCGT 2017), ray
  *     t in (0, ao_radius];
- *   shadow (OCR_SHADOW): uniform light point y (Eq. shadow-light-pdf),
+ *   shadow (OCR_SHADOW): light point y from the light's emitter density
+ *     (uniform, Eq. shadow-light-pdf, or bilinear: see OCR_LIGHT_BILINEAR),
  *     segment o -> y, t in (0, 1); not traced (OCR_HIT_SELF) when y is
  *     behind the receiver's tangent plane or the receiver is behind the
  *     light's emitting face.
@@ -197,15 +198,15 @@ ocr_status ocr_trace_occluders(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int3
  * traced to stats (device
  * uint64[5], caller-zeroed; the layout of ocr_validate_pairs' counts).  A
  * separate, slower kernel for work accounting (roofline figures), not for
- * frames.  Errors as ocr_trace_occluders, and OCR_ERR_INVALID_ARG for a
- * NULL stats. */
+ * frames.  Errors as ocr_trace_occluders, OCR_ERR_INVALID_ARG for a NULL
+ * stats, and OCR_ERR_UNSUPPORTED for a light not sampled uniformly. */
 ocr_status ocr_trace_occluders_counted(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, int32_t mode, float ao_radius,
                                        const ocr_rect_light *light, uint64_t seed, uint32_t sample,
                                        ocr_occluders *out, uint64_t *stats, void *stream);
 
 /* The sample step alone (row A1 of the trace): for every pixel, the offset
  * receiver point o, the ray direction (AO: the cosine-weighted direction;
- * shadow: y - o for the uniform light point y) and its kind (0 traced,
+ * shadow: y - o for the light point y of the light's density) and its kind (0 traced,
  * 1 not traced -- shadow sample behind the tangent plane or receiver behind
  * the light, 2 background).  Bit-identical to what ocr_trace_occluders
  * traces.  origin, dir: device float[h][w][3]; kind: device uint8[h][w].
@@ -260,7 +261,11 @@ ocr_status ocr_reuse_ao(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_o
  * exact fraction of the light in front of the receiver's tangent plane
  * (F_i = 1 for a receiver facing the whole light).  Biased with dark_guard:
  * 0 when no sample of S(i) is unblocked.  OCR_NOREUSE gives [hit_i is a
- * miss].  Background pixels get 0.  Errors as ocr_reuse_ao. */
+ * miss].  For a light sampled from the bilinear density the densities are
+ * p_A(y' | x) J chi_A and each term p_i(j) / P_i(j) is divided by
+ * Area p_A(y'_ij | x_i) (OCR_NOREUSE: F_i - 1 / (Area p_A) for a hit).
+ * The records must be traced with the same light (density included).
+ * Background pixels get 0.  Errors as ocr_reuse_ao. */
 ocr_status ocr_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
                             const ocr_rect_light *light, const ocr_reuse_params *params, void *workspace,
                             size_t workspace_bytes, float *out, void *stream);
@@ -271,8 +276,10 @@ ocr_status ocr_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const o
  *   out[i] = F_Omega(x_i) - sum_j C_Omega(x_i, z_j) p_i(j) / P_i(j)
  * (Eq. reapp-shadow-solid-angle-estimator), with p, P, the validation and
  * the records exactly as for ocr_reuse_shadow (the light is still sampled
- * uniformly on its area: trace with OCR_SHADOW), the factor
+ * on its area: trace with OCR_SHADOW), the factor
  *   C_Omega(x, z) = Area / Omega_A(x) * <n_y', w_{y'->x}> / |x - y'|^2
+ * for a uniformly sampled light, divided by Area p_A(y' | x) for one sampled
+ * from the bilinear density (the density p_A(y' | x) J chi_A in p and P),
  * at the light crossing y' of the ray from x through z (Eq.
  * reapp-shadow-solid-angle-mis-factor), and F_Omega = Omega_front /
  * Omega_A, the part of the light's solid angle in front of the receiver's
@@ -322,7 +329,8 @@ ocr_status ocr_validate_pairs_lights(const ocr_bvh *bvh, const ocr_gbuffer *gbuf
  *   out[i] = U(x_i) - sum_j C_DI(x_i, z_j) p_i(j) / P_i(j)
  * (Eq. reapp-di-general-mis-estimator) with p, P, the validation and the
  * records exactly as for ocr_reuse_shadow (trace with OCR_SHADOW: the light
- * is sampled uniformly on its area), C_DI(x, z) = Area g(x, y') and
+ * is sampled on its area), C_DI(x, z) = Area g(x, y') for a uniformly sampled
+ * light (g(x, y') / p_A(y' | x) for the bilinear density) and
  * g(x, y) = (rho / pi) L_e cos+(n_x, w_{x->y}) <n_y, w_{y->x}> / |x - y|^2
  * (Eq. reapp-di-general-mis-factor with p_A = 1 / Area), and U the unshadowed
  * term of Eq. reapp-di-unshadowed-term, computed exactly by Lambert's polygon
