@@ -261,6 +261,181 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
     }
 }
 
+// The same validation for the light effects, in runs.  A light candidate has
+// a few pairs with positive density (the light subtends a narrow cone), so a
+// walk per candidate would leave most of its 64 lanes idle.  A wavefront
+// instead takes a run of up to kLightRun consecutive candidates, lists the
+// positive pairs of all of them in LDS (each with its candidate's place in the
+// run), and walks once per 64 listed pairs, each lane its own segment o_k ->
+// z_j (traverse_wave_any takes any segments; neighbouring candidates' segments
+// head for the same light from nearby points, so their paths through the BVH
+// largely coincide).  The list is walked early when the next candidate might
+// not fit.  Bits, segments and grid are as in validate_window_kernel; AO keeps
+// that kernel (its candidates fill their own walks).
+constexpr int kLightRun = 8;                   // candidates per run, light effects
+constexpr int kRunWords = 128;                 // validation words of a run in LDS
+static_assert(kRunWords >= kMaxWords, "a run holds at least one candidate's words");
+
+// A candidate of the current run, as its walks need it.
+struct RunCand {
+    float oj[3], dzj[3];
+    int32_t jx, jy;
+    uint32_t hj;
+    int32_t pad;
+};
+
+// COUNT: the work-accounting instantiation (lane-masked walk, same bits),
+// which adds the segments' useful work to stats[0..4].  Bounded to 7 waves
+// per SIMD (72 registers, a few spilled): at its natural 88 registers (5
+// waves) the walk ran 12% slower; 8 waves spilled more and lost on shadows.
+template <int MODE, bool COUNT, class LT = LightF>
+__global__ __launch_bounds__(kBlock, 7) void validate_run_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
+                                                                 LT L, int D, int words, uint32_t *bits,
+                                                                 const uint32_t *lists, uint32_t per_xcd,
+                                                                 uint64_t *stats) {
+    constexpr int kRun = kLightRun;
+    __shared__ uint32_t wnode[kBlock / 64][kStackTotal];
+    __shared__ unsigned long long wmask[kBlock / 64][COUNT ? kStackTotal : 1];
+    // listed pairs: (place in the run << 11) | q
+    __shared__ uint16_t wq[kBlock / 64][kMaxPairs];
+    __shared__ uint32_t wbits[kBlock / 64][kRunWords];
+    __shared__ RunCand wcand[kBlock / 64][kRun];
+    WalkStats ws;
+    // wave-uniform by construction; readfirstlane lets the compiler keep the
+    // candidate bookkeeping derived from it in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int side = 2 * D + 1, npairs = side * side;
+    const float inv_side = 1.0f / (float)side;
+    const int qself = D * side + D;
+    // candidates per run: bounded by the run's words in LDS
+    const int run = min(kRun, kRunWords / words);
+    // the 8 lists concatenated (roughly tile order); consecutive runs go to
+    // the waves of one block, which then share the CU's caches
+    uint32_t total = 0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) total += lists[x * kCountStride];
+    const uint32_t stride = gridDim.x * (kBlock / 64);
+    for (uint32_t ri = blockIdx.x * (kBlock / 64) + wave; ri * (uint32_t)run < total; ri += stride) {
+        const uint32_t c0 = ri * (uint32_t)run;
+        const int nrun = (int)min((uint32_t)run, total - c0);
+        for (int w = lane; w < nrun * words; w += 64) wbits[wave][w] = 0u;
+        wave_sync();
+        int count = 0, done = 0;  // listed pairs; candidates whose words are written
+        // Walk the listed pairs (each lane its own segment), then write the
+        // words of the candidates gathered so far.
+        auto flush = [&](int upto) {
+            wave_sync();
+            for (int e0 = 0; e0 < count; e0 += 64) {
+                TRay r;
+                r.ign0 = r.ign1 = OCR_HIT_MISS;
+                const int idx = e0 + lane;
+                const bool want = idx < count;
+                int q = 0, b = 0;
+                if (want) {
+                    const uint32_t e = wq[wave][idx];
+                    b = (int)(e >> 11);
+                    q = (int)(e & 2047u);
+                    const RunCand &c = wcand[wave][b];
+                    int64_t k;
+                    uint32_t primk;
+                    float ok[3], nk[3], w[3];
+                    pair_receiver(g, c.jx, c.jy, side, inv_side, D, q, k, primk, ok, nk);
+                    rel_vec(c.oj, ok, c.dzj, w);
+                    make_ray(ok, w, c.hj, primk, 1.0f - 1e-4f, r);
+                }
+                bool blocked;
+                if (COUNT) {
+                    blocked = traverse_wave_any_masked(bvh, r, 1.0f - 1e-4f, want, wnode[wave], wmask[wave], ws);
+                } else {
+                    TRay rr[1] = {r};
+                    const bool wr[1] = {want};
+                    bool br[1];
+                    traverse_wave_any<1>(bvh, rr, 1.0f - 1e-4f, wr, br, wnode[wave], ws);
+                    blocked = br[0];
+                }
+                if (want && !blocked) atomicOr(&wbits[wave][b * words + (q >> 5)], 1u << (q & 31));
+            }
+            wave_sync();
+            for (int b = done; b < upto; ++b) {
+                const RunCand &c = wcand[wave][b];
+                const int64_t j = (int64_t)c.jy * g.w + c.jx;
+                for (int w = lane; w < words; w += 64) bits[j * words + w] = wbits[wave][b * words + w];
+            }
+            done = upto;
+            count = 0;
+            wave_sync();  // the list is read before it is refilled
+        };
+        for (int b = 0; b < nrun; ++b) {
+            // list x and the position in it of candidate c0 + b (scalar)
+            uint32_t off = c0 + (uint32_t)b, base = 8 * kCountStride;
+#pragma unroll
+            for (int x = 0; x < 7; ++x) {
+                const uint32_t n = lists[x * kCountStride];
+                if (off >= n) {
+                    off -= n;
+                    base += per_xcd;
+                } else {
+                    break;
+                }
+            }
+            const int64_t j = __builtin_amdgcn_readfirstlane((int)lists[base + off]);
+            const int jy = (int)((uint32_t)j / (uint32_t)g.w), jx = (int)j - jy * g.w;
+            const uint32_t hj = occ.hit[j];
+            float xj[3], nj[3], oj[3], dzj[3], nzj[3];
+            load3(g.pos, j, xj);
+            load3(g.nrm, j, nj);
+            offset_point(xj, nj, oj);
+            load3(occ.dz, j, dzj);
+            load3(occ.nz, j, nzj);
+            // room for this candidate's pairs in the list
+            if (count + npairs - 1 > kMaxPairs) flush(b);
+            if (lane == 0) {
+                RunCand &c = wcand[wave][b];
+                for (int a = 0; a < 3; ++a) {
+                    c.oj[a] = oj[a];
+                    c.dzj[a] = dzj[a];
+                }
+                c.jx = jx;
+                c.jy = jy;
+                c.hj = hj;
+                // z_j is its own first hit
+                atomicOr(&wbits[wave][b * words + (qself >> 5)], 1u << (qself & 31));
+            }
+            // the receivers with positive density, listed in q order
+            for (int qb = 0; qb < npairs; qb += 64) {
+                const int q = qb + lane;
+                bool want = false;
+                int64_t k;
+                uint32_t primk;
+                float ok[3], nk[3];
+                if (q < npairs && pair_receiver(g, jx, jy, side, inv_side, D, q, k, primk, ok, nk) && k != j) {
+                    float w[3];
+                    rel_vec(oj, ok, dzj, w);
+                    float p;
+                    if (MODE == OCR_AO) {
+                        p = dens_ao(w, nk, nzj, R2);
+                    } else {
+                        p = dens_light(w, nk, recv_of(ok, L), nzj, L);
+                    }
+                    want = p > 0.0f;
+                }
+                const unsigned long long m = __ballot(want);
+                if (want) wq[wave][count + __popcll(m & below)] = (uint16_t)((b << 11) | q);
+                count += __popcll(m);
+            }
+        }
+        flush(nrun);
+    }
+    if (COUNT && lane == 0) {
+        atomicAdd((unsigned long long *)&stats[0], (unsigned long long)ws.walks);
+        atomicAdd((unsigned long long *)&stats[1], (unsigned long long)ws.nodes);
+        atomicAdd((unsigned long long *)&stats[2], (unsigned long long)ws.box_tests);
+        atomicAdd((unsigned long long *)&stats[3], (unsigned long long)ws.tri_tests);
+        atomicAdd((unsigned long long *)&stats[4], (unsigned long long)ws.segments);
+    }
+}
+
 // First-hit validation for fixed groups: one lane per (candidate m, receiver
 // k) pair of a group; block = 32 x 8 pixels, which the group shapes tile.
 // Bit (ky - my + D)(2D+1) + (kx - mx + D) of m's words, D = the group extent.
@@ -424,15 +599,15 @@ static hipError_t launch_validate_t(const DeviceBVH &bvh, const GBufView &g, con
                            nt);
         // persistent grid: a multiple of 8 blocks (one share per XCD), ~32 per CU
         dim3 grid(8192), block(kBlock);
-#define OCR_VAL(M, C)                                                                                        \
-    hipLaunchKernelGGL((validate_window_kernel<M, C, LT>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, \
-                       bits, lists, per_xcd, stats)
+#define OCR_VAL(K, M, C)                                                                                    \
+    hipLaunchKernelGGL((K<M, C, LT>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, lists, per_xcd, \
+                       stats)
         if (mode == OCR_AO) {
-            if (stats) OCR_VAL(OCR_AO, true);
-            else OCR_VAL(OCR_AO, false);
+            if (stats) OCR_VAL(validate_window_kernel, OCR_AO, true);
+            else OCR_VAL(validate_window_kernel, OCR_AO, false);
         } else {
-            if (stats) OCR_VAL(OCR_SHADOW, true);
-            else OCR_VAL(OCR_SHADOW, false);
+            if (stats) OCR_VAL(validate_run_kernel, OCR_SHADOW, true);
+            else OCR_VAL(validate_run_kernel, OCR_SHADOW, false);
         }
 #undef OCR_VAL
     } else {
