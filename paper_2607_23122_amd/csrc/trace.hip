@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
 // largely coincide).  The list is walked early when the next candidate might
 // not fit.  Bits, segments and grid are as in validate_window_kernel; AO keeps
 // that kernel (its candidates fill their own walks).
-constexpr int kLightRun = 8;                   // candidates per run, light effects
+constexpr int kLightRun = 6;                   // candidates per run, light effects
 constexpr int kRunWords = 128;                 // validation words of a run in LDS
 static_assert(kRunWords >= kMaxWords, "a run holds at least one candidate's words");
 
