@@ -110,19 +110,6 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ
     if (cand) lists[8 * kCountStride + xcd * per_xcd + off + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)j;
 }
 
-// First-hit validation (Eq. occ-first-hit) for the sliding window, one
-// wavefront per candidate j.  The receivers k = j + (q % side - D,
-// q / side - D), side = 2D + 1, D = 2r, whose density of z_j is positive
-// are gathered first (lane q of each 64-wide round, then compacted into a
-// list in LDS), and the wave then walks the BVH once per 64 listed
-// receivers: an any-hit segment o_k -> z_j over t in (0, 1 - 1e-4), ignoring
-// z_j's triangle and k's own, decides Occ(x_k, z_j), all segments ending at
-// z_j (traverse_wave_any).  Bit q of j's words is set when z_j is the first
-// hit from o_k (k == j: always).  An oversubscribed grid (8192 blocks)
-// strides through the concatenated candidate lists; the hardware dispatcher
-// then balances the uneven per-candidate work at block granularity.  This
-// was measured faster than giving each XCD a contiguous range, than a
-// resident-sized grid, and than taking candidates from atomic counters.
 constexpr int kMaxPairs = 33 * 33;             // (4r+1)^2 at r = 8
 constexpr int kMaxWords = (kMaxPairs + 31) / 32;
 
@@ -144,135 +131,29 @@ __device__ inline bool pair_receiver(const GBufView &g, int jx, int jy, int side
     return true;
 }
 
-// COUNT: the work-accounting instantiation (lane-masked walk, same bits),
-// which adds the segments' useful work to stats[0..4].  Bounded to 7 waves
-// per SIMD (72 registers, a few spilled): at its natural 88 registers (5
-// waves) the walk ran 12% slower; 8 waves spilled more and lost on shadows.
-template <int MODE, bool COUNT, class LT = LightF>
-__global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
-                                                                 LT L, int D, int words, uint32_t *bits,
-                                                                 const uint32_t *lists, uint32_t per_xcd,
-                                                                 uint64_t *stats) {
-    __shared__ uint32_t wnode[kBlock / 64][kStackTotal];
-    __shared__ unsigned long long wmask[kBlock / 64][COUNT ? kStackTotal : 1];
-    __shared__ uint16_t wq[kBlock / 64][kMaxPairs];
-    __shared__ uint32_t wbits[kBlock / 64][kMaxWords];
-    WalkStats ws;
-    // wave-uniform by construction; readfirstlane lets the compiler keep the
-    // candidate bookkeeping derived from it in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    const int side = 2 * D + 1, npairs = side * side;
-    const float inv_side = 1.0f / (float)side;
-    // the 8 lists concatenated (roughly tile order); consecutive candidates go
-    // to the waves of one block, which then share the CU's caches
-    uint32_t total = 0;
-#pragma unroll
-    for (int x = 0; x < 8; ++x) total += lists[x * kCountStride];
-    const uint32_t stride = gridDim.x * (kBlock / 64);
-    for (uint32_t li = blockIdx.x * (kBlock / 64) + wave; li < total; li += stride) {
-        // list x and the position in it of the li-th candidate (scalar)
-        uint32_t off = li, base = 8 * kCountStride;
-#pragma unroll
-        for (int x = 0; x < 7; ++x) {
-            const uint32_t n = lists[x * kCountStride];
-            if (off >= n) {
-                off -= n;
-                base += per_xcd;
-            } else {
-                break;
-            }
-        }
-        const int64_t j = __builtin_amdgcn_readfirstlane((int)lists[base + off]);
-        const int jy = (int)((uint32_t)j / (uint32_t)g.w), jx = (int)j - jy * g.w;
-        const uint32_t hj = occ.hit[j];
-        float xj[3], nj[3], oj[3], dzj[3], nzj[3];
-        load3(g.pos, j, xj);
-        load3(g.nrm, j, nj);
-        offset_point(xj, nj, oj);
-        load3(occ.dz, j, dzj);
-        load3(occ.nz, j, nzj);
-        // (1) the receivers with positive density, compacted in q order
-        for (int w = lane; w < words; w += 64) wbits[wave][w] = 0u;
-        int count = 0;
-        for (int base = 0; base < npairs; base += 64) {
-            const int q = base + lane;
-            bool want = false;
-            int64_t k;
-            uint32_t primk;
-            float ok[3], nk[3];
-            if (q < npairs && pair_receiver(g, jx, jy, side, inv_side, D, q, k, primk, ok, nk) && k != j) {
-                float w[3];
-                rel_vec(oj, ok, dzj, w);
-                float p;
-                if (MODE == OCR_AO) {
-                    p = dens_ao(w, nk, nzj, R2);
-                } else {
-                    p = dens_light(w, nk, recv_of(ok, L), nzj, L);
-                }
-                want = p > 0.0f;
-            }
-            const unsigned long long m = __ballot(want);
-            if (want) wq[wave][count + __popcll(m & below)] = (uint16_t)q;
-            count += __popcll(m);
-        }
-        wave_sync();
-        // (2) one walk per 64 listed segments
-        for (int c0 = 0; c0 < count; c0 += 64) {
-            TRay r;
-            r.ign0 = r.ign1 = OCR_HIT_MISS;
-            const int idx = c0 + lane;
-            const bool want = idx < count;
-            int q = 0;
-            if (want) {
-                q = wq[wave][idx];
-                int64_t k;
-                uint32_t primk;
-                float ok[3], nk[3], w[3];
-                pair_receiver(g, jx, jy, side, inv_side, D, q, k, primk, ok, nk);
-                rel_vec(oj, ok, dzj, w);
-                make_ray(ok, w, hj, primk, 1.0f - 1e-4f, r);
-            }
-            bool blocked;
-            if (COUNT) {
-                blocked = traverse_wave_any_masked(bvh, r, 1.0f - 1e-4f, want, wnode[wave], wmask[wave], ws);
-            } else {
-                TRay rr[1] = {r};
-                const bool wr[1] = {want};
-                bool br[1];
-                traverse_wave_any<1>(bvh, rr, 1.0f - 1e-4f, wr, br, wnode[wave], ws);
-                blocked = br[0];
-            }
-            if (want && !blocked) atomicOr(&wbits[wave][q >> 5], 1u << (q & 31));
-        }
-        // (3) z_j is its own first hit; write j's words
-        const int qself = D * side + D;
-        if (lane == 0) atomicOr(&wbits[wave][qself >> 5], 1u << (qself & 31));
-        wave_sync();
-        for (int w = lane; w < words; w += 64) bits[j * words + w] = wbits[wave][w];
-        wave_sync();  // the words are read before the next candidate clears them
-    }
-    if (COUNT && lane == 0) {
-        atomicAdd((unsigned long long *)&stats[0], (unsigned long long)ws.walks);
-        atomicAdd((unsigned long long *)&stats[1], (unsigned long long)ws.nodes);
-        atomicAdd((unsigned long long *)&stats[2], (unsigned long long)ws.box_tests);
-        atomicAdd((unsigned long long *)&stats[3], (unsigned long long)ws.tri_tests);
-        atomicAdd((unsigned long long *)&stats[4], (unsigned long long)ws.segments);
-    }
-}
-
-// The same validation for the light effects, in runs.  A light candidate has
-// a few pairs with positive density (the light subtends a narrow cone), so a
-// walk per candidate would leave most of its 64 lanes idle.  A wavefront
-// instead takes a run of up to kLightRun consecutive candidates, lists the
-// positive pairs of all of them in LDS (each with its candidate's place in the
-// run), and walks once per 64 listed pairs, each lane its own segment o_k ->
-// z_j (traverse_wave_any takes any segments; neighbouring candidates' segments
-// head for the same light from nearby points, so their paths through the BVH
-// largely coincide).  The list is walked early when the next candidate might
-// not fit.  Bits, segments and grid are as in validate_window_kernel; AO keeps
-// that kernel (its candidates fill their own walks).
+// First-hit validation (Eq. occ-first-hit) for the sliding window.  The
+// receivers k = j + (q % side - D, q / side - D), side = 2D + 1, D = 2r, of a
+// candidate j whose density of z_j is positive are gathered (lane q of each
+// 64-wide round) into a list in LDS, and the wave walks the BVH once per 64
+// listed pairs: an any-hit segment o_k -> z_j over t in (0, 1 - 1e-4),
+// ignoring z_j's triangle and k's own, decides Occ(x_k, z_j)
+// (traverse_wave_any; each lane its own segment).  Bit q of j's words is set
+// when z_j is the first hit from o_k (k == j: always).  A wave takes a run of
+// consecutive candidates and lists the pairs of all of them, tagged with the
+// candidate's place in the run, before walking: a shadow candidate has a few
+// pairs (the light subtends a narrow cone), so a walk per candidate would
+// leave most lanes idle, while neighbouring candidates' segments head for the
+// same light from nearby points and share most of their path through the
+// BVH; an AO candidate has dozens, and short runs only fill its last, partly
+// empty walk.  The list is walked early when the next candidate might not
+// fit.  An oversubscribed grid (8192 blocks) strides through the concatenated
+// candidate lists; the hardware dispatcher then balances the uneven per-run
+// work at block granularity.  (Measured faster than giving each XCD a
+// contiguous range, than a resident-sized grid, and than taking candidates
+// from atomic counters; run lengths 6 for the light effects and 4 for AO were
+// the fastest measured.)
 constexpr int kLightRun = 6;                   // candidates per run, light effects
+constexpr int kAoRun = 4;                      // candidates per run, AO
 constexpr int kRunWords = 128;                 // validation words of a run in LDS
 static_assert(kRunWords >= kMaxWords, "a run holds at least one candidate's words");
 
@@ -286,14 +167,14 @@ struct RunCand {
 
 // COUNT: the work-accounting instantiation (lane-masked walk, same bits),
 // which adds the segments' useful work to stats[0..4].  Bounded to 7 waves
-// per SIMD (72 registers, a few spilled): at its natural 88 registers (5
-// waves) the walk ran 12% slower; 8 waves spilled more and lost on shadows.
+// per SIMD (72 registers, some spilled): at its natural register count (5
+// waves) the walk ran 12% slower.
 template <int MODE, bool COUNT, class LT = LightF>
-__global__ __launch_bounds__(kBlock, 7) void validate_run_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
+__global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
                                                                  LT L, int D, int words, uint32_t *bits,
                                                                  const uint32_t *lists, uint32_t per_xcd,
                                                                  uint64_t *stats) {
-    constexpr int kRun = kLightRun;
+    constexpr int kRun = MODE == OCR_AO ? kAoRun : kLightRun;
     __shared__ uint32_t wnode[kBlock / 64][kStackTotal];
     __shared__ unsigned long long wmask[kBlock / 64][COUNT ? kStackTotal : 1];
     // listed pairs: (place in the run << 11) | q
@@ -599,15 +480,15 @@ static hipError_t launch_validate_t(const DeviceBVH &bvh, const GBufView &g, con
                            nt);
         // persistent grid: a multiple of 8 blocks (one share per XCD), ~32 per CU
         dim3 grid(8192), block(kBlock);
-#define OCR_VAL(K, M, C)                                                                                    \
-    hipLaunchKernelGGL((K<M, C, LT>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, bits, lists, per_xcd, \
-                       stats)
+#define OCR_VAL(M, C)                                                                                        \
+    hipLaunchKernelGGL((validate_window_kernel<M, C, LT>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, \
+                       bits, lists, per_xcd, stats)
         if (mode == OCR_AO) {
-            if (stats) OCR_VAL(validate_window_kernel, OCR_AO, true);
-            else OCR_VAL(validate_window_kernel, OCR_AO, false);
+            if (stats) OCR_VAL(OCR_AO, true);
+            else OCR_VAL(OCR_AO, false);
         } else {
-            if (stats) OCR_VAL(validate_run_kernel, OCR_SHADOW, true);
-            else OCR_VAL(validate_run_kernel, OCR_SHADOW, false);
+            if (stats) OCR_VAL(OCR_SHADOW, true);
+            else OCR_VAL(OCR_SHADOW, false);
         }
 #undef OCR_VAL
     } else {
