@@ -372,6 +372,21 @@ def run_frame(args):
         traffic = measured_traffic(kname) if args.workload == "ao_1080p" else None
         roof = dict(bound="alu", achieved=round(val_tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
                     frac=round(val_tops / VALU_PEAK_TOPS, 4), traffic=traffic, kernel=kname)
+    elif dominant in ("reuse_biased", "reuse_unbiased"):
+        # a 7x7 window reuse binds on the VALU (up to 169 densities per
+        # candidate): its useful operations against the VALU peak, with its
+        # algorithmic HBM rate beside them
+        t_ms = per[dominant]
+        tops = hits * window_reuse_ops(r, mode, bilinear) / (t_ms * 1e-3) / 1e12
+        # (the unbiased launch also reads each pixel's validation words)
+        vbytes = (((4 * r + 1) ** 2 + 31) // 32) * 4 * W * H if dominant == "reuse_unbiased" else 0
+        gbs = (reuse_bytes + vbytes) / (t_ms * 1e-3) / 1e9
+        lt = "ocr::LightSetF" if mode == "shadow2" else "ocr::LightBilinF" if bilinear else "ocr::LightF"
+        kname = (f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2, 'di': 3, 'shadow2': 1}[mode]}, "
+                 f"{'true' if dominant == 'reuse_unbiased' else 'false'}, {lt}>")
+        roof = dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
+                    frac=round(tops / VALU_PEAK_TOPS, 4), traffic=None, kernel=kname, hbm_gbs=round(gbs, 1),
+                    hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
     else:
         roof = dict(bound="hbm", achieved=round(reuse_gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(reuse_gbs / HBM_PEAK_GBS, 5), traffic=None, kernel=dominant)
