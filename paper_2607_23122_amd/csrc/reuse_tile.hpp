@@ -246,22 +246,30 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
                 qx = q - __mul24(qy, WD);
                 const int kx = kx0 + qx, ky = ky0 + qy;
                 const int kc = __mul24(ky, RW) + kx;
-                float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
-                float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
-                float w[3];
-                rel_vec(oj, ok, dzj, w);
-                if (MODE == OCR_AO) {
-                    p = dens_ao(w, nk, nzj, R2);
-                } else {
-                    float v[kRecvFloats<LT>];
-                    for (int a = 0; a < kRecvFloats<LT>; ++a) v[a] = s_sh[a * CELLS + kc];
-                    p = dens_light(w, nk, recv_load(v, L), nzj, L);
-                }
-                if (UNB && p > 0.0f) {
-                    // candidate j's validation bit for the receiver at offset k - j
+                // unbiased: candidate j's validation bit for the receiver at
+                // offset k - j first.  It is set only where the validation
+                // found the same density positive (and the segment free), so
+                // a pair without it contributes 0 whatever its density, and a
+                // round with no bit set skips the densities altogether
+                // (shadow candidates have a few positive pairs, clustered).
+                bool need = true;
+                if (UNB) {
                     const int qb = __mul24(ky - cy + D, SIDE) + (kx - cx + D);
                     const uint32_t wv = bits[gj * words + (qb >> 5)];
-                    if (!((wv >> (qb & 31)) & 1u)) p = 0.0f;
+                    need = (wv >> (qb & 31)) & 1u;
+                }
+                if (need) {
+                    float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
+                    float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
+                    float w[3];
+                    rel_vec(oj, ok, dzj, w);
+                    if (MODE == OCR_AO) {
+                        p = dens_ao(w, nk, nzj, R2);
+                    } else {
+                        float v[kRecvFloats<LT>];
+                        for (int a = 0; a < kRecvFloats<LT>; ++a) v[a] = s_sh[a * CELLS + kc];
+                        p = dens_light(w, nk, recv_load(v, L), nzj, L);
+                    }
                 }
                 w_dens[__mul24(qy, SIDE) + qx] = p;
             }
