@@ -381,6 +381,130 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
     }
 }
 
+// Wave-coherent closest-hit traversal for coherent rays (shadow segments of
+// a pixel tile towards one light).  Every lane of the wave calls it with its
+// own ray (want = false: the lane rides along).  The wave walks the union of
+// its rays' paths from a wave-uniform stack in LDS (`wstack`, kStackTotal
+// entries), node and triangle fetches by scalar loads; each lane keeps its
+// own closest hit and tests boxes against it (the per-lane walk's culling),
+// a child is taken when some active lane's ray meets its box, and children
+// are visited nearest first for the first active lane.  The closest
+// (t, triangle id) with traverse's tie-break does not depend on the order in
+// which nodes are visited, so the result is traverse<false, INCLUSIVE>'s.
+template <bool INCLUSIVE>
+__device__ inline Hit traverse_wave_closest(const DeviceBVH &bvh, const TRay &r, float tmax, bool want,
+                                            uint32_t *wstack) {
+    Hit h;
+    h.t = tmax;
+    h.tri = OCR_HIT_MISS;
+    h.leaf_tri = 0;
+    const unsigned long long amask = wave_ballot(want);
+    if (amask == 0ull) return h;
+    const int leader = __builtin_amdgcn_readfirstlane((int)__builtin_ctzll(amask));
+    const float grow = 1.0f + 0x1p-20f;
+    int sp = 0;
+    uint32_t node = 0;
+    for (;;) {
+        if (!(node & kLeafBit)) {
+            const cfloat *np = (const cfloat *)(bvh.nodes + node);
+            const cuint *cp = (const cuint *)(bvh.nodes + node);
+            float lxs[4], hxs[4], lys[4], hys[4], lzs[4], hzs[4];
+            uint32_t chs[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                lxs[i] = np[i];
+                hxs[i] = np[4 + i];
+                lys[i] = np[8 + i];
+                hys[i] = np[12 + i];
+                lzs[i] = np[16 + i];
+                hzs[i] = np[20 + i];
+                chs[i] = cp[24 + i];
+            }
+            // all of the node's scalar loads issue together
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                asm volatile("" ::"s"(lxs[i]), "s"(hxs[i]), "s"(lys[i]), "s"(hys[i]), "s"(lzs[i]), "s"(hzs[i]),
+                             "s"(chs[i]));
+            // per child: taken by some lane, and its order key (the leader's
+            // entry distance as bits -- entry distances are >= 0, so their bits
+            // order as integers -- or after all of those if the leader misses it)
+            uint32_t key[4], cand[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                key[i] = 0xFFFFFFFFu;
+                cand[i] = kEmpty;
+                if (chs[i] == kEmpty) continue;  // wave-uniform
+                float t0x = __fmaf_rn(lxs[i], r.inv[0], r.off_lo[0]), t1x = __fmaf_rn(hxs[i], r.inv[0], r.off_hi[0]);
+                float t0y = __fmaf_rn(lys[i], r.inv[1], r.off_lo[1]), t1y = __fmaf_rn(hys[i], r.inv[1], r.off_hi[1]);
+                float t0z = __fmaf_rn(lzs[i], r.inv[2], r.off_lo[2]), t1z = __fmaf_rn(hzs[i], r.inv[2], r.off_hi[2]);
+                float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+                float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
+                tfar = fminf(tfar, h.t * grow);
+                const bool in = want && tnear <= tfar;
+                const unsigned long long m = wave_ballot(in);
+                if (m != 0ull) {
+                    cand[i] = chs[i];
+                    const uint32_t lt = (uint32_t)__builtin_amdgcn_readlane(__float_as_int(in ? tnear : INFINITY),
+                                                                            leader);
+                    key[i] = (m >> leader) & 1ull ? lt : 0xFFFFFFFEu;
+                }
+            }
+            // nearest first: sort the four (key, child) pairs (5 compare-exchanges)
+#define OCR_KSWAP(a, b)                                          \
+    if (key[b] < key[a]) {                                       \
+        uint32_t tk = key[a]; key[a] = key[b]; key[b] = tk;      \
+        uint32_t tc = cand[a]; cand[a] = cand[b]; cand[b] = tc;  \
+    }
+            OCR_KSWAP(0, 1)
+            OCR_KSWAP(2, 3)
+            OCR_KSWAP(0, 2)
+            OCR_KSWAP(1, 3)
+            OCR_KSWAP(1, 2)
+#undef OCR_KSWAP
+            if (cand[0] != kEmpty) {
+#pragma unroll
+                for (int k = 3; k >= 1; --k) {
+                    if (cand[k] != kEmpty) {
+                        wstack[sp] = cand[k];
+                        ++sp;
+                    }
+                }
+                node = __builtin_amdgcn_readfirstlane(cand[0]);
+                continue;
+            }
+        } else {
+            const uint32_t first = node & 0x07FFFFFFu;
+            const uint32_t count = ((node >> 27) & 0xFu) + 1u;
+            for (uint32_t q = 0; q < count; ++q) {
+                const cfloat *tp = (const cfloat *)(bvh.tris + 3 * (size_t)(first + q));
+                float4 v0, v1, v2;
+                v0.x = tp[0]; v0.y = tp[1]; v0.z = tp[2]; v0.w = tp[3];
+                v1.x = tp[4]; v1.y = tp[5]; v1.z = tp[6]; v1.w = tp[7];
+                v2.x = tp[8]; v2.y = tp[9]; v2.z = tp[10]; v2.w = tp[11];
+                const uint32_t id = __float_as_uint(v0.w);
+                if (want && id != r.ign0 && id != r.ign1) {
+                    const float t = tri_hit(r, v0, v1, v2);
+                    if (t > 0.0f) {
+                        bool take;
+                        if (t < h.t) take = true;
+                        else if (t == h.t) take = h.tri == OCR_HIT_MISS ? INCLUSIVE : id < h.tri;
+                        else take = false;
+                        if (take) {
+                            h.t = t;
+                            h.tri = id;
+                            h.leaf_tri = first + q;
+                        }
+                    }
+                }
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        node = __builtin_amdgcn_readfirstlane(wstack[sp]);
+    }
+    return h;
+}
+
 // The same walk with lane masks, for work accounting: each stack entry
 // carries the ballot mask of the lanes whose segment touches that child's
 // box, and only those lanes (less any found blocked since) test the
