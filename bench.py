@@ -619,14 +619,39 @@ def run_served(args):
                     max_in_flight=int(st.max_in_flight), waited_for_memory=int(st.waited_for_memory),
                     peak_mb=round(st.peak_bytes / 2 ** 20, 1))
 
+    def saturate(slots, n=1000):
+        """Capacity: n requests of the same mix submitted at once (arrival =
+        submission), completed frames/s from the first submission to the
+        last completion."""
+        srv = ocr.Server(int(cfg["budget_gib"] * 2 ** 30), slots=slots, poll_us=10)
+        sids = [srv.add_scene(bvhs[i], pools[i]) for i in range(8)]
+        t_first = ocr.server_now_ms()
+        for k in range(n):
+            si, vi, mode = picks[k % len(picks)]
+            srv.submit(ocr.request(sids[si], vi, mode, R, light if mode == "shadow" else None, k, 0, params, None))
+        done, last = 0, t_first
+        while done < n:
+            for res in srv.poll(1024):
+                if res.status != 0:
+                    raise RuntimeError(f"request failed: {res.status}")
+                done += 1
+                last = max(last, res.end_ms)
+                srv.release(res.ticket)
+            time.sleep(0.0002)
+        srv.destroy()
+        return round(n / ((last - t_first) * 1e-3), 1)
+
     log(f"[bench] served: {len(arrivals)} Poisson arrivals at {rate}/s over {total_s:.0f} s, "
         f"offered {offered_gpx:.3f} Gpx/s")
     main_run = serve(cfg["slots"])
     log(f"[bench] {cfg['slots']} slots: {main_run}")
     base = None
+    capacity = {f"slots_{cfg['slots']}": saturate(cfg["slots"])}
     if args.served_baseline == "on":
         base = serve(1)
         log(f"[bench] 1-slot FIFO: {base}")
+        capacity["fifo_one_slot"] = saturate(1)
+    log(f"[bench] capacity (1000 requests at once): {capacity}")
     # the dominant kernel as served: the trace of one 1080p request, timed and counted
     si, vi = 2, 1
     dg = pools[si][vi]
@@ -658,7 +683,7 @@ def run_served(args):
                    "global_batch": 1, "seq_len": None, "parallelism": "single-gpu"},
         "p50_ms": main_run["p50_ms"], "p99_ms": main_run["p99_ms"],
         "offered_gpx_per_s": round(offered_gpx, 3), "stable": bool(stable),
-        "served": main_run, "fifo_one_slot": base,
+        "served": main_run, "fifo_one_slot": base, "capacity_frames_per_s": capacity,
         "roofline": alu_roofline(work, trace_ms, "trace_kernel (1080p request)"),
     }
     if args.cpu_baseline == "on":
