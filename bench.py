@@ -37,6 +37,8 @@ import argparse
 import json
 import os
 import platform
+import re
+import subprocess
 import sys
 import time
 
@@ -195,11 +197,16 @@ def main():
     ap.add_argument("--served-poses", type=int, default=2, help="camera poses per scene and resolution (served)")
     ap.add_argument("--served-baseline", default="on", choices=["on", "off"],
                     help="also run the one-slot FIFO server on the same arrivals")
+    ap.add_argument("--primer", default="on", choices=["on", "off"],
+                    help="first run a short AO frame step in a child process (absorbs the slow first GPU "
+                         "process of a freshly started machine)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (a frame would shard by image "
               "bands with halo recompute, see the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    primer = run_primer() if args.primer == "on" else None
 
     import torch
 
@@ -212,7 +219,34 @@ def main():
         result = run_served(args)
     else:
         result = run_frame(args)
+    result["primer"] = primer
     print(json.dumps(result), flush=True)
+
+
+def run_primer():
+    """Runs a short AO frame step (two steps after a second of settle steps)
+    in a child process before this process touches the GPU, and returns the
+    child's trace time.  On freshly started machines the first process that
+    used the GPU was seen to run the trace kernel about 13x slower for its
+    whole life (later processes ran normally), which the settle steps do not
+    cure; the child takes that place.  A failing child ends the bench with
+    its status: the GPU is not used again after a failure."""
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "ao_1080p", "--steps", "2", "--warmup", "0",
+           "--settle-seconds", "1.0", "--cpu-baseline", "off", "--primer", "off"]
+    t0 = time.perf_counter()
+    try:
+        p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=300)
+    except subprocess.TimeoutExpired:
+        log("[bench] primer process timed out")
+        sys.exit(124)
+    if p.returncode != 0:
+        log(p.stderr[-4000:])
+        log(f"[bench] primer process failed with status {p.returncode}")
+        sys.exit(p.returncode if p.returncode > 0 else 1)
+    m = re.findall(r"steps: .*?; trace ([0-9.]+)", p.stderr)
+    trace_ms = float(m[-1]) if m else None
+    log(f"[bench] primer process: {time.perf_counter() - t0:.1f} s, trace {trace_ms} ms/step")
+    return {"seconds": round(time.perf_counter() - t0, 1), "trace_ms": trace_ms}
 
 
 def settle(torch, fn, seconds, max_calls=2000):
