@@ -203,13 +203,16 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (a frame would shard by image "
-              "bands with halo recompute, see the design notes); run with --gpus 1", file=sys.stderr)
+              "bands with halo recompute); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-
-    primer = run_primer() if args.primer == "on" else None
 
     import torch
 
+    # (counting devices does not initialise the GPU in this process)
+    if torch.cuda.device_count() == 0:
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    primer = run_primer() if args.primer == "on" else None
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)

@@ -41,7 +41,7 @@
  *     reapp-shadow-solid-angle-mis-factor), with the emitter's solid angle
  *     computed exactly, and its quadrature reference.
  *
- * Readings where the paper is silent (each listed in the design notes):
+ * Readings where the paper is silent:
  * receiver point o = x + 2^-16 (1 + max|x|) n and the receiver's own
  * triangle ignored by its rays; candidates and receivers of a target are the
  * valid pixels of its reuse set (a clipped (2r+1)^2 window, or a fixed
