@@ -293,7 +293,7 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
             const cfloat *np = (const cfloat *)(bvh.nodes + node);
             const cuint *cp = (const cuint *)(bvh.nodes + node);
             float lxs[4], hxs[4], lys[4], hys[4], lzs[4], hzs[4];
-            uint32_t chs[4];
+            uint32_t chs[4], pads[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 lxs[i] = np[i];
@@ -303,13 +303,15 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
                 lzs[i] = np[16 + i];
                 hzs[i] = np[20 + i];
                 chs[i] = cp[24 + i];
+                pads[i] = cp[28 + i];
             }
             // all of the node's scalar loads issue together, ahead of the
-            // per-child branches (else each child waits for its own)
+            // per-child branches (else each child waits for its own); the
+            // whole 128-byte node, pad words included, is two 64-byte loads
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 asm volatile("" ::"s"(lxs[i]), "s"(hxs[i]), "s"(lys[i]), "s"(hys[i]), "s"(lzs[i]), "s"(hzs[i]),
-                             "s"(chs[i]));
+                             "s"(chs[i]), "s"(pads[i]));
             uint32_t next = kEmpty;
 #pragma unroll
             for (int i = 3; i >= 0; --i) {
@@ -353,6 +355,9 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
                 v0.x = tp[0]; v0.y = tp[1]; v0.z = tp[2]; v0.w = tp[3];
                 v1.x = tp[4]; v1.y = tp[5]; v1.z = tp[6]; v1.w = tp[7];
                 v2.x = tp[8]; v2.y = tp[9]; v2.z = tp[10]; v2.w = tp[11];
+                // the triangle's 12 words as one batch of scalar loads
+                asm volatile("" ::"s"(v0.x), "s"(v0.y), "s"(v0.z), "s"(v0.w), "s"(v1.x), "s"(v1.y), "s"(v1.z),
+                             "s"(v1.w), "s"(v2.x), "s"(v2.y), "s"(v2.z), "s"(v2.w));
                 const uint32_t id = __float_as_uint(v0.w);
 #pragma unroll
                 for (int q = 0; q < NR; ++q) st.tri_tests += __popcll(__ballot(active[q] && id != r[q].ign0 && id != r[q].ign1));
@@ -409,7 +414,7 @@ __device__ inline Hit traverse_wave_closest(const DeviceBVH &bvh, const TRay &r,
             const cfloat *np = (const cfloat *)(bvh.nodes + node);
             const cuint *cp = (const cuint *)(bvh.nodes + node);
             float lxs[4], hxs[4], lys[4], hys[4], lzs[4], hzs[4];
-            uint32_t chs[4];
+            uint32_t chs[4], pads[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 lxs[i] = np[i];
@@ -419,12 +424,14 @@ __device__ inline Hit traverse_wave_closest(const DeviceBVH &bvh, const TRay &r,
                 lzs[i] = np[16 + i];
                 hzs[i] = np[20 + i];
                 chs[i] = cp[24 + i];
+                pads[i] = cp[28 + i];
             }
-            // all of the node's scalar loads issue together
+            // all of the node's scalar loads issue together: the whole 128-byte
+            // node, pad words included, as two 64-byte loads
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 asm volatile("" ::"s"(lxs[i]), "s"(hxs[i]), "s"(lys[i]), "s"(hys[i]), "s"(lzs[i]), "s"(hzs[i]),
-                             "s"(chs[i]));
+                             "s"(chs[i]), "s"(pads[i]));
             // per child: taken by some lane, and its order key (the leader's
             // entry distance as bits -- entry distances are >= 0, so their bits
             // order as integers -- or after all of those if the leader misses it)
@@ -481,6 +488,9 @@ __device__ inline Hit traverse_wave_closest(const DeviceBVH &bvh, const TRay &r,
                 v0.x = tp[0]; v0.y = tp[1]; v0.z = tp[2]; v0.w = tp[3];
                 v1.x = tp[4]; v1.y = tp[5]; v1.z = tp[6]; v1.w = tp[7];
                 v2.x = tp[8]; v2.y = tp[9]; v2.z = tp[10]; v2.w = tp[11];
+                // the triangle's 12 words as one batch of scalar loads
+                asm volatile("" ::"s"(v0.x), "s"(v0.y), "s"(v0.z), "s"(v0.w), "s"(v1.x), "s"(v1.y), "s"(v1.z),
+                             "s"(v1.w), "s"(v2.x), "s"(v2.y), "s"(v2.z), "s"(v2.w));
                 const uint32_t id = __float_as_uint(v0.w);
                 if (want && id != r.ign0 && id != r.ign1) {
                     const float t = tri_hit(r, v0, v1, v2);
