@@ -56,6 +56,19 @@ HBM_PEAK_GBS = 8000.0
 # test's (12 of its 26 ops in 6 FMAs; 17 instructions with three-operand
 # min/max) tops out near 26 / 34 = 0.76 of this peak.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak (packed FP32 issue): the roofline's
+# `peak`; the unpacked rate above is reported beside it
+PUBLISHED_FP32_TOPS = 157.3
+
+
+def alu_roof(tops, **extra):
+    """An ALU roofline entry: achieved useful TFLOP/s against the published
+    FP32 peak, and against the unpacked issue rate the build can reach."""
+    d = dict(bound="alu", achieved=round(tops, 3), peak=PUBLISHED_FP32_TOPS, unit="TFLOP/s",
+             frac=round(tops / PUBLISHED_FP32_TOPS, 4), peak_unpacked=round(VALU_PEAK_TOPS, 1),
+             frac_unpacked=round(tops / VALU_PEAK_TOPS, 4))
+    d.update(extra)
+    return d
 # FP32 operations of one test of one ray or segment, counted from the kernels
 # (the counted tests are those each ray or segment needs on its own; lanes
 # of a wave that execute a test their segment does not need are not useful
@@ -152,10 +165,9 @@ def alu_roofline(stats, ms, kernel):
     the launch's average duration, against the VALU peak."""
     ops = OPS_BOX * stats[2] + OPS_TRI * stats[3]
     tops = ops / (ms * 1e-3) / 1e12
-    return dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
-                frac=round(tops / VALU_PEAK_TOPS, 4), traffic=None, kernel=kernel,
-                work={"walks": int(stats[0]), "node_visits": int(stats[1]), "box_tests": int(stats[2]),
-                      "tri_tests": int(stats[3])})
+    return alu_roof(tops, traffic=None, kernel=kernel,
+                    work={"walks": int(stats[0]), "node_visits": int(stats[1]), "box_tests": int(stats[2]),
+                          "tri_tests": int(stats[3])})
 
 
 def counted_trace(ocr, torch, bvh, dg, mode, R, light, seed, sample):
@@ -197,6 +209,13 @@ def main():
     ap.add_argument("--served-poses", type=int, default=2, help="camera poses per scene and resolution (served)")
     ap.add_argument("--served-baseline", default="on", choices=["on", "off"],
                     help="also run the one-slot FIFO server on the same arrivals")
+    ap.add_argument("--served-rates", type=lambda v: [float(x) for x in v.split(",") if x], default=[1800.0],
+                    help="further offered loads (requests/s), served and FIFO on the same arrivals")
+    ap.add_argument("--amortised-reps", type=int, default=3,
+                    help="repetitions of 200 accumulated samples for the amortised per-sample times (0: off)")
+    ap.add_argument("--extras", default="on", choices=["on", "off"],
+                    help="with the default workload, also measure the shadow frame, GROUP 8 reuse, the batched "
+                         "plan and the served loop, each as an object of the same JSON line")
     ap.add_argument("--primer", default="on", choices=["on", "off"],
                     help="first run a short AO frame step in a child process (absorbs the slow first GPU "
                          "process of a freshly started machine)")
@@ -220,8 +239,10 @@ def main():
         result = run_batched(args)
     elif args.workload == "served":
         result = run_served(args)
+    elif args.workload == "ao_1080p" and args.extras == "on":
+        result = run_all(args)
     else:
-        result = run_frame(args)
+        result = run_frame(args, amortised_reps=args.amortised_reps)
     result["primer"] = primer
     print(json.dumps(result), flush=True)
 
@@ -266,18 +287,36 @@ def settle(torch, fn, seconds, max_calls=2000):
     torch.cuda.synchronize()
 
 
-def run_frame(args):
+def frame_inputs(ctx, cfg):
+    """The 1080p terrain scene, its G-buffer and BVH (built once, shared by
+    the frame workloads of one run)."""
+    import paper_2607_23122_amd as ocr
+    import workloads as w
+    key = (cfg["scene_seed"], cfg["width"], cfg["height"])
+    if ctx.get("key") != key:
+        t0 = time.time()
+        scene = w.terrain_scene(cfg["scene_seed"])
+        gb = w.render_gbuffer(scene, w.terrain_camera(cfg["width"], cfg["height"]))
+        t_in = time.time() - t0
+        bvh = ocr.build_bvh(scene.V, scene.F)
+        ctx.clear()
+        ctx.update(key=key, scene=scene, gb=gb, bvh=bvh, dg=ocr.DeviceGBuffer.from_host(gb, "cuda:0"), t_in=t_in)
+    return ctx["scene"], ctx["gb"], ctx["bvh"], ctx["dg"]
+
+
+def run_frame(args, workload=None, ctx=None, cpu_seconds=None, amortised_reps=0):
     import numpy as np
     import torch
 
     import paper_2607_23122_amd as ocr
     import workloads as w
 
-    cfg = WORKLOADS[args.workload]
+    workload = workload or args.workload
+    ctx = {} if ctx is None else ctx
+    cpu_seconds = args.cpu_seconds if cpu_seconds is None else cpu_seconds
+    cfg = WORKLOADS[workload]
     mode, W, H, R, r = cfg["mode"], cfg["width"], cfg["height"], cfg["radius"], cfg["window_r"]
-    t0 = time.time()
-    scene = w.terrain_scene(cfg["scene_seed"])
-    gb = w.render_gbuffer(scene, w.terrain_camera(W, H))
+    scene, gb, bvh, dg = frame_inputs(ctx, cfg)
     light = w.terrain_light() if mode != "ao" else None
     if mode == "shadow2":
         light = w.two_lights()
@@ -285,13 +324,11 @@ def run_frame(args):
     if bilinear:
         light.pdf = 1
     tmode = "shadow" if mode in ("shadow_sa", "di", "shadow2") else mode  # the mode records are traced in
-    log(f"[bench] inputs {time.time() - t0:.1f}s: {scene.ntris} tris, {W}x{H}, valid {gb.valid.mean():.3f}")
+    log(f"[bench] {workload}: inputs {ctx['t_in']:.1f}s: {scene.ntris} tris, {W}x{H}, valid {gb.valid.mean():.3f}")
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    bvh = ocr.build_bvh(scene.V, scene.F)
     info = bvh.info()
-    dg = ocr.DeviceGBuffer.from_host(gb, dev)
     occ = ocr.Occluders.empty(H, W, dev)
     p_none = ocr.reuse_params("window", r, 0, "none")
     p_b = ocr.reuse_params("window", r, 0, "biased")
@@ -406,9 +443,8 @@ def run_frame(args):
         # one validation per light type (single-light kernels carry LightF)
         lt = "ocr::LightSetF" if mode == "shadow2" else "ocr::LightF"
         kname = f"ocr::validate_window_kernel<{0 if mode == 'ao' else 1}, false, {lt}>"
-        traffic = measured_traffic(kname) if args.workload == "ao_1080p" else None
-        roof = dict(bound="alu", achieved=round(val_tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
-                    frac=round(val_tops / VALU_PEAK_TOPS, 4), traffic=traffic, kernel=kname)
+        traffic = measured_traffic(kname) if workload == "ao_1080p" else None
+        roof = alu_roof(val_tops, traffic=traffic, kernel=kname)
     elif dominant in ("reuse_biased", "reuse_unbiased"):
         # a 7x7 window reuse binds on the VALU (up to 169 densities per
         # candidate): its useful operations against the VALU peak, with its
@@ -421,9 +457,7 @@ def run_frame(args):
         lt = "ocr::LightSetF" if mode == "shadow2" else "ocr::LightBilinF" if bilinear else "ocr::LightF"
         kname = (f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2, 'di': 3, 'shadow2': 1}[mode]}, "
                  f"{'true' if dominant == 'reuse_unbiased' else 'false'}, {lt}>")
-        roof = dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 1), unit="TFLOP/s",
-                    frac=round(tops / VALU_PEAK_TOPS, 4), traffic=None, kernel=kname, hbm_gbs=round(gbs, 1),
-                    hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+        roof = alu_roof(tops, traffic=None, kernel=kname, hbm_gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
     else:
         roof = dict(bound="hbm", achieved=round(reuse_gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(reuse_gbs / HBM_PEAK_GBS, 5), traffic=None, kernel=dominant)
@@ -441,7 +475,7 @@ def run_frame(args):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: terrain 512x512 cells + 2000 icospheres ({scene.ntris} tris), "
+        "config": {"workload": f"{workload}: terrain 512x512 cells + 2000 icospheres ({scene.ntris} tris), "
                                f"{W}x{H}, 1 spp, R={R} m, 7x7 window, no-reuse + biased + unbiased"
                                + {"shadow2": ", shadows of two rectangular lights",
                                   "shadow_sa": ", shadows under the solid-angle definition",
@@ -456,9 +490,7 @@ def run_frame(args):
         "reused_samples_per_s": round(hits * (2 * r + 1) ** 2 / (per["reuse_biased"] * 1e-3), 1),
         "pair_densities_per_s": round(pair_evals / (per["reuse_biased"] * 1e-3), 1),
         "biased_frame_ms": round(per["trace"] + per["reuse_biased"], 4),
-        "reuse_roofline": dict(bound="alu", achieved=round(reuse_tops, 3), peak=round(VALU_PEAK_TOPS, 1),
-                               unit="TFLOP/s", frac=round(reuse_tops / VALU_PEAK_TOPS, 4),
-                               hbm_gbs=round(reuse_gbs, 1), hbm_frac=round(reuse_gbs / HBM_PEAK_GBS, 4),
+        "reuse_roofline": alu_roof(reuse_tops, hbm_gbs=round(reuse_gbs, 1), hbm_frac=round(reuse_gbs / HBM_PEAK_GBS, 4),
                                kernel=f"ocr::reuse_window_kernel<{ {'ao': 0, 'shadow': 1, 'shadow_sa': 2, 'di': 3, 'shadow2': 1}[mode]}, false, "
                                       f"{'ocr::LightSetF' if mode == 'shadow2' else 'ocr::LightBilinF' if bilinear else 'ocr::LightF'}>",
                                ops_per_candidate=window_reuse_ops(r, mode, bilinear)),
@@ -478,11 +510,161 @@ def run_frame(args):
     result["trace_roofline"] = None if mode == "shadow2" or bilinear else alu_roofline(
         counted_trace(ocr, torch, bvh, dg, tmode, R, light, cfg["sample_seed"], args.steps - 1), per["trace"],
         "trace_kernel")
-    if args.workload == "ao_1080p":
+    if workload == "ao_1080p":
         result["trace_roofline"]["traffic"] = measured_traffic("ocr::trace_kernel<0, ocr::LightF>")
-    if args.cpu_baseline == "on":
-        result["cpu_baseline"] = cpu_baseline(scene, gb, cfg, light, args.cpu_seconds)
+    if amortised_reps > 0 and mode in ("ao", "shadow"):
+        result["amortised_ms_per_spp"] = amortised(ocr, torch, bvh, dg, occ, tmode, R, light, cfg["sample_seed"],
+                                                   (p_none, p_b, p_u), ws, out_n, amortised_reps)
+    if args.cpu_baseline == "on" and cpu_seconds > 0:
+        # the GPU outputs of sample 0 (the oracle's tiles use the same sample)
+        step(0)
+        torch.cuda.synchronize()
+        gpu = {"hit": occ.hit_u32(), "none": out_n.cpu().numpy(), "biased": out_b.cpu().numpy(),
+               "unbiased": out_u.cpu().numpy()}
+        result["cpu_baseline"], par = cpu_baseline(scene, gb, cfg, light, cpu_seconds, gpu)
+        result["grazing_fraction"] = par["grazing_fraction"]
+        result["excluded_fraction"] = par["excluded_fraction"]
+        result["parity_sample"] = par
     return result
+
+
+def amortised(ocr, torch, bvh, dg, occ, tmode, R, light, seed, params, ws, out, reps, spp=200):
+    """The paper's amortised timing (the protocol of its absolute-runtime
+    tables): each repetition accumulates `spp` samples of the whole per-sample
+    pass into one buffer (trace, then the estimator: no reuse, biased, or
+    validation + unbiased), the time of `reps` repetitions divided by the
+    samples taken; ms per sample."""
+    p_none, p_b, p_u = params
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, p in (("noreuse", p_none), ("biased", p_b), ("unbiased", p_u)):
+        def one_rep(base):
+            for s in range(spp):
+                ocr.trace_occluders(bvh, dg, tmode, R, light, seed, base + s, occ)
+                acc = ocr.ReuseParams(p.pattern, p.radius, p.group_n, p.estimator, p.dark_guard, 0 if s == 0 else 1,
+                                      p.validated)
+                if p.estimator == 2:
+                    ocr.validate_pairs(bvh, dg, occ, tmode, R, light, p, ws)
+                if tmode == "ao":
+                    ocr.reuse_ao(None, dg, occ, R, acc, out, ws)
+                else:
+                    ocr.reuse_shadow(None, dg, occ, light, acc, out, ws)
+            ocr.scale(out, 1.0 / spp)
+        one_rep(10_000)  # warm-up repetition
+        torch.cuda.synchronize()
+        ev = _events(torch, 2)
+        ev[0].record(stream)
+        for k in range(reps):
+            one_rep(20_000 + k * spp)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        res[name] = round(ev[0].elapsed_time(ev[1]) / (reps * spp), 4)
+    res["protocol"] = f"{spp} spp accumulated per repetition, {reps} repetitions, time / samples"
+    log(f"[bench] amortised ms per sample: {res}")
+    return res
+
+
+FRAME_KEYS = ["value", "unit", "ms_per_step", "config", "kernels_ms", "kernels_ms_p50", "kernels_ms_p90",
+              "trace_mrays_s", "reuse_gbs", "roofline", "reuse_roofline", "trace_roofline", "negative_pixel_fraction",
+              "amortised_ms_per_spp", "grazing_fraction", "excluded_fraction", "parity_sample", "cpu_baseline"]
+
+
+def run_all(args):
+    """The default line: the 1080p AO step (the headline), then each further
+    configuration's own headline as an object of the same line -- the 1080p
+    shadow step, GROUP 8 reuse against the HBM roof, the batched plan and the
+    served loop (shorter runs than their own workloads' defaults)."""
+    import copy
+
+    import torch
+    ctx = {}
+    t0 = time.time()
+    result = run_frame(args, "ao_1080p", ctx, amortised_reps=args.amortised_reps)
+    sh = run_frame(args, "shadow_1080p", ctx, cpu_seconds=min(4.0, args.cpu_seconds), amortised_reps=args.amortised_reps)
+    result["shadow_1080p"] = {k: sh[k] for k in FRAME_KEYS if k in sh}
+    result["group8_reuse"] = run_group8(args, ctx)
+    ctx.clear()
+    torch.cuda.empty_cache()
+    log(f"[bench] frame workloads done at {time.time() - t0:.0f} s")
+    a = copy.copy(args)
+    a.cpu_baseline = "off"
+    a.steps, a.warmup = min(args.steps, 10), min(args.warmup, 2)
+    b = run_batched(a)
+    result["batched_16"] = {k: b[k] for k in ("value", "unit", "ms_per_step", "config", "mpx_per_s", "plan_ms",
+                                              "plan_no_graph_ms", "per_view_pairs_ms", "speedup_vs_per_view",
+                                              "tuning", "roofline")}
+    torch.cuda.empty_cache()
+    log(f"[bench] batched done at {time.time() - t0:.0f} s")
+    a.served_seconds, a.served_warmup_seconds = min(args.served_seconds, 4.0), min(args.served_warmup_seconds, 1.0)
+    a.served_poses = 1
+    sv = run_served(a)
+    result["served"] = {k: sv[k] for k in ("value", "unit", "config", "p50_ms", "p99_ms", "offered_gpx_per_s",
+                                           "stable", "served", "fifo_one_slot", "capacity_frames_per_s",
+                                           "higher_loads", "roofline")}
+    log(f"[bench] served done at {time.time() - t0:.0f} s")
+    return result
+
+
+def run_group8(args, ctx, launches=30):
+    """GROUP 8 reuse (the paper's own pattern: 4x2 pixel groups) and the
+    no-reuse write-out on the 1080p frame, AO and shadows: median launch time
+    over `launches` launches, and the algorithmic bytes' rate against the HBM
+    roof.  Biased GROUP 8 reads the G-buffer (28 B/px) and the records
+    (28 B/px) and writes the estimate (4 B/px); no reuse reads the G-buffer's
+    primitive id and the hit id and writes the estimate (12 B/px)."""
+    import numpy as np
+    import torch
+
+    import paper_2607_23122_amd as ocr
+    import workloads as w
+
+    cfg = WORKLOADS["ao_1080p"]
+    W, H, R = cfg["width"], cfg["height"], cfg["radius"]
+    scene, gb, bvh, dg = frame_inputs(ctx, cfg)
+    stream = torch.cuda.current_stream()
+    occ = ocr.Occluders.empty(H, W)
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    p_b = ocr.reuse_params("group", 0, 8, "biased")
+    p_u = ocr.reuse_params("group", 0, 8, "unbiased", validated=True)
+    p_n = ocr.reuse_params("group", 0, 8, "none")
+    ws = torch.empty(ocr.workspace_bytes(W, H, p_u), dtype=torch.uint8, device="cuda")
+    res = {}
+    for mode in ("ao", "shadow"):
+        light = w.terrain_light() if mode == "shadow" else None
+        ocr.trace_occluders(bvh, dg, mode, R, light, cfg["sample_seed"], 0, occ)
+
+        def reuse(p, wsp=None):
+            if mode == "ao":
+                ocr.reuse_ao(None, dg, occ, R, p, out, wsp)
+            else:
+                ocr.reuse_shadow(None, dg, occ, light, p, out, wsp)
+
+        def timed(fn):
+            for _ in range(5):
+                fn()
+            ev = _events(torch, 2 * launches)
+            for k in range(launches):
+                ev[2 * k].record(stream)
+                fn()
+                ev[2 * k + 1].record(stream)
+            torch.cuda.synchronize()
+            return float(np.median([ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(launches)]))
+
+        t_b = timed(lambda: reuse(p_b))
+        t_v = timed(lambda: ocr.validate_pairs(bvh, dg, occ, mode, R, light, p_u, ws))
+        t_u = timed(lambda: reuse(p_u, ws))
+        t_n = timed(lambda: reuse(p_n))
+        gbs_b = 60.0 * W * H / (t_b * 1e-3) / 1e9
+        gbs_n = 12.0 * W * H / (t_n * 1e-3) / 1e9
+        res[mode] = {"biased_ms": round(t_b, 4), "biased_gbs": round(gbs_b, 1),
+                     "biased_hbm_frac": round(gbs_b / HBM_PEAK_GBS, 4),
+                     "validate_ms": round(t_v, 4), "unbiased_reuse_ms": round(t_u, 4),
+                     "noreuse_ms": round(t_n, 4), "noreuse_gbs": round(gbs_n, 1),
+                     "noreuse_hbm_frac": round(gbs_n / HBM_PEAK_GBS, 4)}
+    res["note"] = ("median event-timed launch; biased 60 B/px, no reuse 12 B/px of algorithmic bytes at "
+                   f"{W}x{H}; HBM peak {HBM_PEAK_GBS:.0f} GB/s")
+    log(f"[bench] group 8: {res}")
+    return res
 
 
 def _events(torch, n):
@@ -611,15 +793,22 @@ def run_served(args):
     params = ocr.reuse_params("window", r, 0, "biased")
     rate = cfg["rate"]
     total_s = args.served_warmup_seconds + args.served_seconds
-    rng = np.random.default_rng(7)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * total_s * 1.5) + 16))
-    arrivals = arrivals[arrivals < total_s]
-    picks = [(int(rng.integers(8)), int(rng.integers(len(pools[0]))), "ao" if rng.random() < 0.5 else "shadow")
-             for _ in range(len(arrivals))]
     px_of = [[dg.width * dg.height for dg in pool] for pool in pools]
+
+    def trace_of(rate):
+        """Poisson arrivals at `rate` over total_s (numpy seed 7), each
+        picking (scene, G-buffer, AO or shadow) uniformly."""
+        rng = np.random.default_rng(7)
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * total_s * 1.5) + 16))
+        arr = arr[arr < total_s]
+        pk = [(int(rng.integers(8)), int(rng.integers(len(pools[0]))), "ao" if rng.random() < 0.5 else "shadow")
+              for _ in range(len(arr))]
+        return arr, pk
+
+    arrivals, picks = trace_of(rate)
     offered_gpx = sum(px_of[s][v] for s, v, _ in picks) / total_s / 1e9
 
-    def serve(slots):
+    def serve(slots, arrivals=arrivals, picks=picks):
         srv = ocr.Server(int(cfg["budget_gib"] * 2 ** 30), slots=slots, poll_us=10)
         sids = [srv.add_scene(bvhs[i], pools[i]) for i in range(8)]
         start = ocr.server_now_ms() + 50.0
@@ -651,7 +840,8 @@ def run_served(args):
 
         def pct(q):
             return float(ls[min(len(ls) - 1, max(0, int(np.ceil(q * len(ls))) - 1))])
-        return dict(requests=len(meas), frames_per_s=round(len(meas) / span, 1), p50_ms=round(pct(0.5), 3),
+        return dict(requests=len(meas), offered_per_s=round(len(meas) / (args.served_seconds), 1),
+                    frames_per_s=round(len(meas) / span, 1), p50_ms=round(pct(0.5), 3),
                     p99_ms=round(pct(0.99), 3), max_ms=round(float(ls[-1]), 3), mean_ms=round(float(ls.mean()), 3),
                     max_in_flight=int(st.max_in_flight), waited_for_memory=int(st.waited_for_memory),
                     peak_mb=round(st.peak_bytes / 2 ** 20, 1))
@@ -689,6 +879,18 @@ def run_served(args):
         log(f"[bench] 1-slot FIFO: {base}")
         capacity["fifo_one_slot"] = saturate(1)
     log(f"[bench] capacity (1000 requests at once): {capacity}")
+    # offered loads above the one-slot FIFO's capacity (and below the 8-slot
+    # server's), where completed frames/s can differ between the two
+    loads = {}
+    for hi_rate in args.served_rates:
+        arr2, pk2 = trace_of(hi_rate)
+        srv8 = serve(cfg["slots"], arr2, pk2)
+        fifo = serve(1, arr2, pk2) if args.served_baseline == "on" else None
+        loads[f"rate_{int(hi_rate)}"] = {"slots_8": srv8, "fifo_one_slot": fifo,
+                                         "stable_8": bool(srv8["frames_per_s"] >= 0.95 * hi_rate),
+                                         "stable_fifo": None if fifo is None else
+                                         bool(fifo["frames_per_s"] >= 0.95 * hi_rate)}
+        log(f"[bench] offered {hi_rate}/s: 8 slots {srv8}; FIFO {fifo}")
     # the dominant kernel as served: the trace of one 1080p request, timed and counted
     si, vi = 2, 1
     dg = pools[si][vi]
@@ -720,7 +922,7 @@ def run_served(args):
                    "global_batch": 1, "seq_len": None, "parallelism": "single-gpu"},
         "p50_ms": main_run["p50_ms"], "p99_ms": main_run["p99_ms"],
         "offered_gpx_per_s": round(offered_gpx, 3), "stable": bool(stable),
-        "served": main_run, "fifo_one_slot": base, "capacity_frames_per_s": capacity,
+        "served": main_run, "fifo_one_slot": base, "capacity_frames_per_s": capacity, "higher_loads": loads,
         "roofline": alu_roofline(work, trace_ms, "trace_kernel (1080p request)"),
     }
     if args.cpu_baseline == "on":
@@ -764,11 +966,16 @@ def cpu_baseline_views(scenes, views, cfg, light, budget_s, px_per_frame):
                       f"{px_per_frame:.0f} px per frame"}
 
 
-def cpu_baseline(scene, gb, cfg, light, budget_s):
+def cpu_baseline(scene, gb, cfg, light, budget_s, gpu=None):
     """The oracle, as it stands, on 64x64-target tiles of the same frame:
     records for each tile's halo, then the no-reuse, biased and unbiased
     estimates, until about budget_s seconds of work; Mrays/s = target pixels
-    completed per second."""
+    completed per second.  With `gpu` (the GPU's hit ids and estimates of the
+    same sample), the tiles double as a parity sample: the fraction of traced
+    rays the oracle flags as grazing, hit-id mismatches, and the fraction of
+    targets excluded from the comparison (a differing grazing trace in the
+    reuse set, or not comparable by the oracle); the others must lie within
+    1e-4 of an admissible oracle value."""
     import numpy as np
 
     import oracle
@@ -778,24 +985,67 @@ def cpu_baseline(scene, gb, cfg, light, budget_s):
     mode = "shadow" if mode == "shadow2" else mode  # (the oracle takes the list of lights)
     rng = np.random.default_rng(7)
     done_px, ntiles = 0, 0
+    par = dict(rays=0, grazing=0, mismatches=0, targets=0, excluded=0, compared=0, bad=0, max_err=0.0)
     t0 = time.perf_counter()
     while True:
         x = int(rng.integers(0, W - 64))
         y = int(rng.integers(0, H - 64))
         t = (x, y, x + 64, y + 64)
+        pu = oracle.params(mode, "unbiased", "window", radius=r, ao_radius=R, light=light, seed=cfg["sample_seed"])
+        hr = oracle.halo_region(pu, W, H, t)
+        rec = oracle.records(sc, gb, pu, hr)
+        res = {}
         for est in ("none", "biased", "unbiased"):
             p = oracle.params(mode, est, "window", radius=r, ao_radius=R, light=light, seed=cfg["sample_seed"])
-            rec = oracle.records(sc, gb, p, oracle.halo_region(p, W, H, t))
-            oracle.reuse(sc, gb, p, rec, t)
+            res[est] = oracle.reuse(sc, gb, p, rec, t)
         done_px += 64 * 64
         ntiles += 1
+        if gpu is not None:
+            hx0, hy0, hx1, hy1 = hr
+            valid = gb.valid[hy0:hy1, hx0:hx1]
+            ohit = rec.hit[hy0:hy1, hx0:hx1]
+            traced = valid & (ohit != oracle.SELF)
+            bad = traced & (gpu["hit"][hy0:hy1, hx0:hx1] != ohit)
+            par["rays"] += int(traced.sum())
+            par["grazing"] += int((traced & rec.graze[hy0:hy1, hx0:hx1].astype(bool)).sum())
+            par["mismatches"] += int(bad.sum())
+            # targets whose window holds a differing trace
+            pad = np.pad(bad, r)
+            reach = np.zeros_like(bad)
+            for dy in range(2 * r + 1):
+                for dx in range(2 * r + 1):
+                    reach |= pad[dy:dy + bad.shape[0], dx:dx + bad.shape[1]]
+            reach = reach[y - hy0:y - hy0 + 64, x - hx0:x - hx0 + 64]
+            for est in ("none", "biased", "unbiased"):
+                rr = res[est]
+                nv = rr.nvar[y:y + 64, x:x + 64]
+                if est == "none":
+                    nv = np.where(bad[y - hy0:y - hy0 + 64, x - hx0:x - hx0 + 64], 0, nv)
+                else:
+                    nv = np.where(reach, 0, nv)
+                var = rr.var[y:y + 64, x:x + 64]
+                err = np.abs(gpu[est][y:y + 64, x:x + 64].astype(np.float64)[..., None] - var)
+                err = np.where(np.arange(8)[None, None, :] < nv[..., None], err, np.inf).min(axis=-1)
+                ok = nv > 0
+                par["targets"] += int(nv.size)
+                par["compared"] += int(ok.sum())
+                par["excluded"] += int((~ok).sum())
+                par["bad"] += int((ok & (err > 1e-4)).sum())
+                if ok.any():
+                    par["max_err"] = max(par["max_err"], float(err[ok].max()))
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
-    return {"value": round(done_px / el / 1e6, 4), "unit": "Mrays/s", "cores": oracle.num_threads(),
+    base = {"value": round(done_px / el / 1e6, 4), "unit": "Mrays/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{ntiles} random 64x64-pixel tiles of the same frame (with their 3-pixel halos), "
+            "sample": f"{ntiles} random 64x64-pixel tiles of the same frame (with their {r}-pixel halos), "
                       f"records + no-reuse + biased + unbiased 7x7, {el:.1f} s on {cpu_model()}"}
+    par["tiles"] = ntiles
+    par["grazing_fraction"] = round(par["grazing"] / max(1, par["rays"]), 8)
+    par["excluded_fraction"] = round(par["excluded"] / max(1, par["targets"]), 8)
+    par["max_err"] = float(f"{par['max_err']:.3e}")
+    log(f"[bench] parity sample: {par}")
+    return base, par
 
 
 if __name__ == "__main__":

@@ -172,6 +172,25 @@ ocr_status ocr_build_bvh(const float *verts, int64_t nverts, const uint32_t *tri
 ocr_status ocr_bvh_free(ocr_bvh *bvh);
 ocr_status ocr_bvh_get_info(const ocr_bvh *bvh, ocr_bvh_info *info);
 
+/* The hierarchy ocr_build_bvh uploads, built on the host only and copied to
+ * caller memory for inspection (a structural check of the build); it makes
+ * no HIP call, so it runs without a GPU.
+ *   nodes: host buffer of node_capacity nodes of 128 bytes, or NULL to ask
+ *     for the count only.  A node is float lo_x[4], hi_x[4], lo_y[4],
+ *     hi_y[4], lo_z[4], hi_z[4] (the four child boxes), uint32 child[4],
+ *     uint32 pad[4]; node 0 is the root.  child: 0xFFFFFFFF = empty slot;
+ *     bit 31 clear = interior node index; bit 31 set = leaf of
+ *     (bits 30..27) + 1 triangles starting at triangle (bits 26..0) of
+ *     tri_data.
+ *   tri_data: host float[3 * ntris][4] or NULL: the triangles in leaf order,
+ *     three vertices each; the w word of the first vertex holds the
+ *     triangle's row in `tris` (as uint32 bits).
+ *   out_nnodes, out_depth: node count and depth (levels of nodes).
+ * Errors: as ocr_build_bvh, and OCR_ERR_INVALID_ARG when nodes is given and
+ * node_capacity is below the count (out_nnodes is set first). */
+ocr_status ocr_build_bvh_host(const float *verts, int64_t nverts, const uint32_t *tris, int64_t ntris, void *nodes,
+                              int64_t node_capacity, float *tri_data, int64_t *out_nnodes, int32_t *out_depth);
+
 /* Step 1 of App. D (AO) / App. H (shadow): one sample per valid pixel with
  * the counter-based hash pcg4d(px, py, sample, seed32 + a*0x9E3779B9)
  * (Jarzynski and Olano, JCGT 2020; seed32 = low ^ high word of seed), then a

@@ -114,7 +114,7 @@ class ServerStats(ctypes.Structure):
                 ("max_ms", ctypes.c_double), ("frames_per_s", ctypes.c_double), ("failed", ctypes.c_int64)]
 
 
-EXPORTS = ["ocr_build_bvh", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders",
+EXPORTS = ["ocr_build_bvh", "ocr_build_bvh_host", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders",
            "ocr_trace_occluders_counted", "ocr_sample_rays",
            "ocr_workspace_bytes", "ocr_validate_pairs",
            "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_reuse_shadow_solid_angle", "ocr_reuse_direct_illumination",
@@ -141,6 +141,8 @@ def lib():
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     L.ocr_build_bvh.restype = i32
     L.ocr_build_bvh.argtypes = [vp, i64, vp, i64, vp, ctypes.POINTER(vp)]
+    L.ocr_build_bvh_host.restype = i32
+    L.ocr_build_bvh_host.argtypes = [vp, i64, vp, i64, vp, i64, vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
     L.ocr_bvh_free.restype = i32
     L.ocr_bvh_free.argtypes = [vp]
     L.ocr_bvh_get_info.restype = i32
@@ -347,6 +349,26 @@ class BVH:
             self.free()
         except Exception:
             pass
+
+
+NODE_DTYPE = np.dtype([("lo_x", "<f4", 4), ("hi_x", "<f4", 4), ("lo_y", "<f4", 4), ("hi_y", "<f4", 4),
+                       ("lo_z", "<f4", 4), ("hi_z", "<f4", 4), ("child", "<u4", 4), ("pad", "<u4", 4)])
+
+
+def build_bvh_host(V, F):
+    """The hierarchy ocr_build_bvh uploads, built on the host only (no GPU):
+    (nodes as a NODE_DTYPE array, leaf-ordered triangles float32[ntris, 3, 4],
+    depth)."""
+    V = np.ascontiguousarray(V, np.float32)
+    F = np.ascontiguousarray(F, np.uint32)
+    nn, depth = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().ocr_build_bvh_host(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], None, 0, None,
+                                    ctypes.byref(nn), ctypes.byref(depth)))
+    nodes = np.zeros(nn.value, NODE_DTYPE)
+    tris = np.zeros((F.shape[0], 3, 4), np.float32)
+    _check(lib().ocr_build_bvh_host(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], nodes.ctypes.data,
+                                    nodes.size, tris.ctypes.data, ctypes.byref(nn), ctypes.byref(depth)))
+    return nodes, tris, int(depth.value)
 
 
 def build_bvh(V, F, stream=None) -> BVH:

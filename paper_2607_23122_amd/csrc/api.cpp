@@ -174,10 +174,13 @@ const char *ocr_last_error(void) { return g_err.c_str(); }
 
 const char *ocr_version(void) { return "ocr-mi355x 0.1 (gfx950)"; }
 
-ocr_status ocr_build_bvh(const float *verts, int64_t nverts, const uint32_t *tris, int64_t ntris, void *stream,
-                         ocr_bvh **out) {
-    if (!out) return fail(OCR_ERR_INVALID_ARG, "out is NULL");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Argument checks and the host build shared by ocr_build_bvh and
+// ocr_build_bvh_host.
+ocr_status host_build(const float *verts, int64_t nverts, const uint32_t *tris, int64_t ntris, HostBVH &hb) {
     if (!verts || !tris) return fail(OCR_ERR_INVALID_ARG, "NULL vertex or triangle array");
     if (nverts < 1 || ntris < 1) return fail(OCR_ERR_INVALID_ARG, "empty scene (%lld verts, %lld tris)",
                                              (long long)nverts, (long long)ntris);
@@ -188,13 +191,44 @@ ocr_status ocr_build_bvh(const float *verts, int64_t nverts, const uint32_t *tri
                         tris[i], (long long)nverts);
     for (int64_t i = 0; i < 3 * nverts; ++i)
         if (!std::isfinite(verts[i])) return fail(OCR_ERR_INVALID_ARG, "vertex %lld is not finite", (long long)(i / 3));
-    HostBVH hb;
     try {
         if (build_bvh_host(verts, nverts, tris, ntris, hb) != 0)
             return fail(OCR_ERR_UNSUPPORTED, "BVH depth %d exceeds the traversal stack", hb.depth);
     } catch (const std::bad_alloc &) {
         return fail(OCR_ERR_OOM, "host allocation failed while building the BVH");
     }
+    return OCR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ocr_status ocr_build_bvh_host(const float *verts, int64_t nverts, const uint32_t *tris, int64_t ntris, void *nodes,
+                              int64_t node_capacity, float *tri_data, int64_t *out_nnodes, int32_t *out_depth) {
+    if (!out_nnodes || !out_depth) return fail(OCR_ERR_INVALID_ARG, "NULL count output");
+    HostBVH hb;
+    ocr_status st = host_build(verts, nverts, tris, ntris, hb);
+    if (st) return st;
+    *out_nnodes = (int64_t)hb.nodes.size();
+    *out_depth = hb.depth;
+    if (nodes) {
+        if (node_capacity < (int64_t)hb.nodes.size())
+            return fail(OCR_ERR_INVALID_ARG, "node buffer holds %lld nodes, %lld needed", (long long)node_capacity,
+                        (long long)hb.nodes.size());
+        std::memcpy(nodes, hb.nodes.data(), hb.nodes.size() * sizeof(Node4));
+    }
+    if (tri_data) std::memcpy(tri_data, hb.tris.data(), hb.tris.size() * sizeof(float4));
+    return OCR_OK;
+}
+
+ocr_status ocr_build_bvh(const float *verts, int64_t nverts, const uint32_t *tris, int64_t ntris, void *stream,
+                         ocr_bvh **out) {
+    if (!out) return fail(OCR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    HostBVH hb;
+    ocr_status st = host_build(verts, nverts, tris, ntris, hb);
+    if (st) return st;
     ocr_bvh *b = new (std::nothrow) ocr_bvh;
     if (!b) return fail(OCR_ERR_OOM, "handle allocation failed");
     size_t nbytes = hb.nodes.size() * sizeof(Node4), tbytes = hb.tris.size() * sizeof(float4);

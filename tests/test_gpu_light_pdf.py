@@ -132,7 +132,6 @@ def test_terrain_reuse_matches_oracle(ocr, terrain, mode, pattern, size, est):
     res.value, res.var = res.value * k, res.var * k
     st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
     log(f"    {st}")
-    assert st["excluded"] <= 2e-3 * st["targets"]
 
 
 @pytest.mark.parametrize("mode", ["shadow", "shadow_sa", "di"])
@@ -147,11 +146,10 @@ def test_near_light_reuse_matches_oracle(ocr, near, mode, pattern, size, est):
     p = oracle.params(mode, est, pattern, radius=size, group_n=size, light=case.light, seed=6)
     rec, res = oracle.frame(case.osc, case.gb, p)
     res.value, res.var = res.value * k, res.var * k
-    st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
-    log(f"    {st}")
     # the plates' edges lie on pixel columns of this grid, so more segments
     # graze them than on the terrain (the oracle flags those targets)
-    assert st["excluded"] <= 1e-2 * st["targets"]
+    st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p), max_excluded=1e-2)
+    log(f"    {st}")
 
 
 def test_the_density_enters_the_estimate(ocr, terrain):

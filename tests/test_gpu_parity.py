@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as w
-from gpu_util import compare_hits, compare_records, compare_values, log, mismatch_reach, tiles, to_np
+from gpu_util import compare_hits, compare_mean, compare_records, compare_values, log, mismatch_reach, tiles, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -141,7 +141,6 @@ def test_reuse_ao_boxes(ocr, boxes, pattern, size, est):
     rec, res = oracle.frame(boxes.osc, boxes.gb, p)
     st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
     log(f"    {st}")
-    assert st["excluded"] <= 1e-3 * st["targets"]
 
 
 @pytest.mark.parametrize("pattern,size,est,guard", [("window", 3, "biased", True), ("window", 3, "biased", False),
@@ -156,7 +155,6 @@ def test_reuse_shadow_terrain_small(ocr, terrain_small, pattern, size, est, guar
     rec, res = oracle.frame(case.osc, case.gb, p)
     st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
     log(f"    {st}")
-    assert st["excluded"] <= 2e-3 * st["targets"]
 
 
 @pytest.mark.parametrize("pattern,size,est,guard", [("window", 3, "biased", True), ("window", 3, "biased", False),
@@ -173,7 +171,6 @@ def test_reuse_shadow_solid_angle_terrain_small(ocr, terrain_small, pattern, siz
     rec, res = oracle.frame(case.osc, case.gb, p)
     st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
     log(f"    {st}")
-    assert st["excluded"] <= 2e-3 * st["targets"]
 
 
 @pytest.mark.parametrize("est,pattern,size", [("none", "window", 0), ("biased", "window", 2),
@@ -194,11 +191,10 @@ def test_reuse_shadow_solid_angle_near_light(ocr, est, pattern, size):
     gpu = _reuse(ocr, case, "shadow_sa", occ, ocr.reuse_params(pattern, size, size, est))
     p = _oparams(case, "shadow_sa", est, pattern, size, seed=6)
     rec, res = oracle.frame(case.osc, gb, p)
-    st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p))
-    log(f"    {st}")
     # the plates' edges lie on pixel columns of this grid, so more segments
     # graze them than in the other cases (the oracle flags those targets)
-    assert st["excluded"] <= 1e-2 * st["targets"]
+    st = compare_values(gpu, res, exclude=mismatch_reach(occ.hit_u32(), rec, p), max_excluded=1e-2)
+    log(f"    {st}")
     f = res.value[res.nvar > 0]
     assert (f < 0.999).mean() > 0.5  # the case does exercise F_Omega < 1 and blocked terms
 
@@ -223,7 +219,6 @@ def test_reuse_direct_illumination_terrain_small(ocr, terrain_small, pattern, si
     rec, res = oracle.frame(case.osc, case.gb, p)
     st = compare_values(gpu, _scaled(res, 100.0), exclude=mismatch_reach(occ.hit_u32(), rec, p))
     log(f"    {st}")
-    assert st["excluded"] <= 2e-3 * st["targets"]
 
 
 @pytest.mark.parametrize("est,pattern,size", [("none", "window", 0), ("biased", "window", 2),
@@ -243,10 +238,9 @@ def test_reuse_direct_illumination_near_light(ocr, est, pattern, size):
     gpu = _reuse(ocr, case, "di", occ, ocr.reuse_params(pattern, size, size, est), radiance=4.0)
     p = _oparams(case, "di", est, pattern, size, seed=6)
     rec, res = oracle.frame(case.osc, gb, p)
-    st = compare_values(gpu, _scaled(res, 4.0), exclude=mismatch_reach(occ.hit_u32(), rec, p))
-    log(f"    {st}")
     # plate edges on pixel columns graze more segments (see the solid-angle case)
-    assert st["excluded"] <= 1e-2 * st["targets"]
+    st = compare_values(gpu, _scaled(res, 4.0), exclude=mismatch_reach(occ.hit_u32(), rec, p), max_excluded=1e-2)
+    log(f"    {st}")
 
 
 def test_reuse_ao_terrain_small_unbiased_r3(ocr, terrain_small):
@@ -293,6 +287,25 @@ def test_reuse_1080p_tiles(ocr, terrain_1080, mode, est, ntiles):
     assert (gpu[bg] == (1.0 if mode == "ao" else 0.0)).all()
 
 
+@pytest.mark.parametrize("mode,est", [("ao", "biased"), ("ao", "unbiased"), ("shadow", "biased"),
+                                      ("shadow", "unbiased")])
+def test_reuse_1080p_full_frame(ocr, terrain_1080, mode, est):
+    # the benchmark's frames (1920x1080 terrain, 7x7 window) compared with the
+    # oracle at every one of the 2,073,600 targets, in the launch
+    # configuration the benchmark times
+    case = terrain_1080
+    log(f"[reuse 1080p full frame] {mode} window 3 {est}")
+    occ = _trace(ocr, case, mode, seed=1)
+    gpu = _reuse(ocr, case, mode, occ, ocr.reuse_params("window", 3, 0, est))
+    p = _oparams(case, mode, est, "window", 3, seed=1)
+    rec, res = oracle.frame(case.osc, case.gb, p)
+    gh = occ.hit_u32()
+    hs = compare_hits(gh, rec, case.gb.valid)
+    st = compare_values(gpu, res, exclude=mismatch_reach(gh, rec, p))
+    log(f"    hits {hs}; values {st}")
+    assert st["compared"] >= 0.999 * st["targets"]
+
+
 # ---------------------------------------------------------------------------
 # Determinism, accumulation, edge cases
 # ---------------------------------------------------------------------------
@@ -310,19 +323,33 @@ def test_bitwise_deterministic(ocr, terrain_1080):
         assert np.array_equal(outs[0][2].view(np.uint32), outs[1][2].view(np.uint32))
 
 
-def test_multi_sample_mean(ocr, boxes):
-    # A6: the mean over M samples of the per-sample estimate
-    M = 4
-    log("[accumulate] boxes window 2 biased, 4 samples")
-    params = ocr.reuse_params("window", 2, 0, "biased")
-    gpu = to_np(ocr.render(boxes.bvh, boxes.dg, "ao", boxes.R, None, seed=2, nsamples=M, first_sample=3,
+@pytest.mark.parametrize("which,mode,est,size", [("boxes", "ao", "biased", 2), ("boxes", "ao", "unbiased", 2),
+                                                  ("terrain_small", "shadow", "biased", 3),
+                                                  ("terrain_small", "shadow", "unbiased", 2)])
+def test_multi_sample_mean(ocr, request, which, mode, est, size):
+    # A6: the mean over M samples of the per-sample estimate (the final step
+    # of App. D / App. H).  Each sample's records are compared with the
+    # oracle's, and the accumulated mean with the mean of admissible
+    # per-sample oracle values, target by target.
+    case = request.getfixturevalue(which)
+    M, first, seed = 4, 3, 2
+    log(f"[accumulate] {case.name} {mode} window {size} {est}, {M} samples")
+    params = ocr.reuse_params("window", size, 0, est)
+    light = case.light if mode != "ao" else None
+    gpu = to_np(ocr.render(case.bvh, case.dg, mode, case.R, light, seed=seed, nsamples=M, first_sample=first,
                            params=params))
-    s, _ = oracle.render(boxes.osc, boxes.gb, _oparams(boxes, "ao", "biased", "window", 2, seed=2, sample=3), M)
-    diff = np.abs(gpu - s / M)
-    # per-sample values agree within 1e-4 except excluded/ambiguous targets,
-    # which can shift one sample's estimate; require agreement almost everywhere
-    assert (diff <= 1e-4).mean() > 0.995
-    assert np.median(diff) < 1e-6
+    results, excludes = [], []
+    for s in range(first, first + M):
+        occ = _trace(ocr, case, mode, seed=seed, sample=s)
+        p = _oparams(case, mode, est, "window", size, seed=seed, sample=s)
+        rec, res = oracle.frame(case.osc, case.gb, p)
+        gh = occ.hit_u32()
+        compare_hits(gh, rec, case.gb.valid)
+        results.append(res)
+        excludes.append(mismatch_reach(gh, rec, p))
+    st = compare_mean(gpu, results, excludes)
+    log(f"    {st}")
+    assert st["compared"] > 0.99 * st["targets"]
 
 
 @pytest.mark.parametrize("W,H", [(1, 1), (3, 5), (37, 23), (64, 1)])
@@ -368,7 +395,12 @@ def test_dark_guard_on_gpu(ocr):
     assert (g == 0.0).all()
     n = _reuse(ocr, case, "shadow", occ, ocr.reuse_params("window", 2, 0, "biased", dark_guard=False))
     _, res = oracle.frame(case.osc, gb, _oparams(case, "shadow", "biased", "window", 2, guard=False))
-    compare_values(n, res)
+    # floor, plate and light are parallel, so a pair's light crossing is
+    # y' = 2 z_j - o_k: the light sample of j shifted by the receiver offset.
+    # Whenever j's sample lies within the window's spread (0.12 m) of a light
+    # edge, several of its pairs fall in the oracle's band at that edge, and a
+    # target with more than three such pairs is not compared (2.5% here)
+    compare_values(n, res, max_excluded=0.05)
 
 
 def test_error_paths_on_device(ocr, boxes):

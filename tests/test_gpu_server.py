@@ -10,8 +10,9 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 import workloads as w
-from gpu_util import log, to_np
+from gpu_util import compare_hits, compare_values, log, mismatch_reach, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +76,7 @@ def world(ocr):
                                                 albedo=DI_ALBEDO)
         torch.cuda.synchronize()
         r["ref"] = to_np(out).copy()
-    return bvhs, pools, reqs
+    return bvhs, pools, reqs, scenes
 
 
 def _serve(ocr, bvhs, pools, reqs, budget, slots, held, pace_ms=0.0):
@@ -122,7 +123,7 @@ def _serve(ocr, bvhs, pools, reqs, budget, slots, held, pace_ms=0.0):
 
 @pytest.mark.parametrize("held", [False, True])
 def test_mix_equals_alone(ocr, world, held):
-    bvhs, pools, reqs = world
+    bvhs, pools, reqs, _ = world
     log(f"[server] 24 requests, 6 slots, held={held}")
     got, st = _serve(ocr, bvhs, pools, reqs, 1 << 30, 6, held)
     for k, r in enumerate(reqs):
@@ -132,7 +133,7 @@ def test_mix_equals_alone(ocr, world, held):
 
 
 def test_budget_waits_and_still_equal(ocr, world):
-    bvhs, pools, reqs = world
+    bvhs, pools, reqs, _ = world
     # room for one 257x131 request's records (28 B/px) at a time, or a few small ones
     W, H = SIZES[2]
     budget = int(28 * W * H * 1.2) + 4096
@@ -145,7 +146,7 @@ def test_budget_waits_and_still_equal(ocr, world):
 
 
 def test_refuses_oversized(ocr, world):
-    bvhs, pools, reqs = world
+    bvhs, pools, reqs, _ = world
     srv = ocr.Server(1 << 16, slots=2)
     sid = srv.add_scene(bvhs[0], [dg for _, dg in pools[0]])
     st, _ = srv.try_submit(ocr.request(sid, 2, "ao", 1.0, out=None))
@@ -154,10 +155,45 @@ def test_refuses_oversized(ocr, world):
 
 
 def test_paced_arrivals_statistics(ocr, world):
-    bvhs, pools, reqs = world
+    bvhs, pools, reqs, _ = world
     log("[server] paced arrivals")
     got, st = _serve(ocr, bvhs, pools, reqs, 1 << 30, 4, False, pace_ms=0.5)
     for k, r in enumerate(reqs):
         assert np.array_equal(got[k].view(np.uint32), r["ref"].view(np.uint32)), k
     assert 0 < st.p50_ms <= st.p99_ms <= st.max_ms
     assert st.frames_per_s > 0
+
+
+@pytest.mark.parametrize("held", [False, True])
+def test_mix_matches_oracle(ocr, world, held):
+    # The accuracy bar of the served loop, checked against the oracle and not
+    # only against the library's own per-view path: AO and shadow requests
+    # (7x7 window, biased and unbiased) served in the middle of the 24-request
+    # mix, with other requests in flight, each compared target by target
+    # with the oracle's estimate of the same request.
+    bvhs, pools, reqs, scenes = world
+    checked = []
+    for i, (mode, est) in enumerate([("ao", "biased"), ("ao", "unbiased"), ("shadow", "biased"),
+                                     ("shadow", "unbiased")]):
+        checked.append(dict(si=1, vi=2, mode=mode, R=2.0, light=w.terrain_light() if mode == "shadow" else None,
+                            seed=5000 + i, sample=1, est=est, params=ocr.reuse_params("window", 3, 3, est)))
+    mix = reqs[:12] + checked + reqs[12:]
+    log(f"[server vs oracle] {len(mix)} requests, 6 slots, held={held}")
+    got, st = _serve(ocr, bvhs, pools, mix, 1 << 30, 6, held)
+    assert st.completed == len(mix) and st.max_in_flight > 1
+    osc = oracle.Scene(scenes[1].V, scenes[1].F)
+    gb, dg = pools[1][2]
+    for c in checked:
+        k = next(i for i, r in enumerate(mix) if r is c)
+        # the request's records, traced alone (records are a pure function
+        # of the inputs and the seed), name the rays whose hits differ
+        occ = ocr.trace_occluders(bvhs[1], dg, c["mode"], c["R"], c["light"], c["seed"], c["sample"])
+        torch.cuda.synchronize()
+        p = oracle.params(c["mode"], c["est"], "window", radius=3, ao_radius=c["R"], light=c["light"],
+                          seed=c["seed"], sample=c["sample"])
+        rec, res = oracle.frame(osc, gb, p)
+        gh = occ.hit_u32()
+        hs = compare_hits(gh, rec, gb.valid)
+        vs = compare_values(got[k], res, exclude=mismatch_reach(gh, rec, p))
+        log(f"    {c['mode']} {c['est']}: hits {hs}; values {vs}")
+        assert vs["compared"] > 0.99 * vs["targets"]

@@ -32,6 +32,86 @@ def test_pcg4d_uniform_and_decorrelated():
     assert not np.array_equal(a, b)
 
 
+# pcg4d as Jarzynski and Olano (JCGT 2020) define it, evaluated here in numpy
+# uint32 arithmetic (wrapping products and sums): a multiply-add step per
+# word, a round of cross products v0 += v1 v3, v1 += v2 v0, v2 += v0 v1,
+# v3 += v1 v2, an xor with each word's upper half, and the cross products
+# again.
+_M, _C = np.uint32(1664525), np.uint32(1013904223)
+
+
+def _np_pcg4d(v):
+    v = np.array(v, dtype=np.uint32, copy=True)
+    with np.errstate(over="ignore"):
+        v = v * _M + _C
+
+        def cross(v):
+            v[0] += v[1] * v[3]
+            v[1] += v[2] * v[0]
+            v[2] += v[0] * v[1]
+            v[3] += v[1] * v[2]
+
+        cross(v)
+        v ^= v >> np.uint32(16)
+        cross(v)
+    return v
+
+
+def _np_pcg4d_inverse(v):
+    # each step of the hash is invertible: the cross products are undone in
+    # reverse order, the half-word xor is its own inverse, and the
+    # multiply-add is undone with the inverse of the odd multiplier mod 2^32
+    v = np.array(v, dtype=np.uint32, copy=True)
+    minv = np.uint32(pow(1664525, -1, 1 << 32))
+    with np.errstate(over="ignore"):
+
+        def uncross(v):
+            v[3] -= v[1] * v[2]
+            v[2] -= v[0] * v[1]
+            v[1] -= v[2] * v[0]
+            v[0] -= v[1] * v[3]
+
+        uncross(v)
+        v ^= v >> np.uint32(16)
+        uncross(v)
+        v = (v - _C) * minv
+    return v
+
+
+def test_pcg4d_known_answers():
+    # known-answer vectors: the oracle's hash against the independent numpy
+    # evaluation of the published definition, on edge and random counters
+    rng = np.random.default_rng(20)
+    ins = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 0, 0, 1), (0xFFFFFFFF,) * 4, (1919, 1079, 0, 0x9E3779B9),
+           (12, 34, 56, 78)]
+    ins += [tuple(int(x) for x in row) for row in rng.integers(0, 1 << 32, (500, 4), dtype=np.uint64)]
+    ref = _np_pcg4d(np.array(ins, dtype=np.uint64).astype(np.uint32).T)
+    got = np.array([oracle.pcg4d(*v) for v in ins], dtype=np.uint32).T
+    assert np.array_equal(got, ref)
+    # and the hash is a bijection of (Z / 2^32)^4: the numpy inverse undoes it
+    back = _np_pcg4d_inverse(got)
+    assert np.array_equal(back, np.array(ins, dtype=np.uint64).astype(np.uint32).T)
+
+
+def test_pcg4d_avalanche():
+    # flipping one low input bit (the pixel, sample and seed counters live
+    # there) flips each output bit with probability ~1/2.  (Flips of the top
+    # input bits diffuse less -- a product moves a change in bit b only to
+    # bits >= b until the half-word xor -- so they are not asserted.)
+    rng = np.random.default_rng(21)
+    base = rng.integers(0, 1 << 32, (4, 256), dtype=np.uint64).astype(np.uint32)
+    h0 = np.array([oracle.pcg4d(*base[:, i]) for i in range(base.shape[1])], dtype=np.uint32)
+    rates = []
+    for word in range(4):
+        for bit in (0, 4, 8, 12, 16):
+            b = base.copy()
+            b[word] ^= np.uint32(1 << bit)
+            h1 = np.array([oracle.pcg4d(*b[:, i]) for i in range(b.shape[1])], dtype=np.uint32)
+            flips = np.unpackbits((h0 ^ h1).view(np.uint8)).mean()
+            rates.append(flips)
+    assert 0.45 < min(rates) and max(rates) < 0.55, rates
+
+
 @pytest.mark.parametrize("normal", [(0.0, 1.0, 0.0), (0.0, 0.0, -1.0), (0.0, 0.0, 1.0),
                                     (0.48, -0.6, 0.64), (-0.8, 0.0, -0.6)])
 def test_cosine_hemisphere_moments(normal):
