@@ -256,7 +256,8 @@ def run_primer():
     cure; the child takes that place.  A failing child ends the bench with
     its status: the GPU is not used again after a failure."""
     cmd = [sys.executable, os.path.abspath(__file__), "--workload", "ao_1080p", "--steps", "2", "--warmup", "0",
-           "--settle-seconds", "1.0", "--cpu-baseline", "off", "--primer", "off"]
+           "--settle-seconds", "1.0", "--cpu-baseline", "off", "--primer", "off", "--extras", "off",
+           "--amortised-reps", "0"]
     t0 = time.perf_counter()
     try:
         p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=300)

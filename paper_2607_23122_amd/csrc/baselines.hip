@@ -68,40 +68,61 @@ __global__ __launch_bounds__(kBBlock2) void filter_kernel(GBufView g, const floa
 }
 
 // out[i] = (1/|S(i)|) sum_j V(x_i, y_j), y_j the light sample of pixel j.
+// Every lane of a wave runs the same loop over the set's extent (lanes whose
+// set is smaller, or that are outside the image, ride along), so that the
+// segments whose per-lane walk overflowed its stack are decided together by
+// a wave-coherent walk.
 __global__ __launch_bounds__(kBBlock2) void light_reuse_kernel(DeviceBVH bvh, GBufView g, LightF L, uint32_t sd,
                                                                uint32_t sample, float *out, int r, int gw, int gh,
                                                                int accumulate) {
     __shared__ uint32_t stack[kStackLds * kBBlock2];
+    __shared__ uint32_t wstack[kBBlock2 / 64][kStackTotal];
     int px, py;
-    if (!pixel_of(g, px, py)) return;
-    const int64_t i = (int64_t)py * g.w + px;
-    const uint32_t prim = g.prim[i];
-    float v = 0.0f;
+    const bool inside = pixel_of(g, px, py);
+    const int64_t i = inside ? (int64_t)py * g.w + px : 0;
+    const uint32_t prim = inside ? g.prim[i] : OCR_HIT_MISS;
+    float x[3] = {0.f, 0.f, 0.f}, n[3] = {0.f, 0.f, 0.f}, o[3] = {0.f, 0.f, 0.f};
+    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
     if (prim != OCR_HIT_MISS) {
-        float x[3], n[3], o[3];
         load3(g.pos, i, x);
         load3(g.nrm, i, n);
         offset_point(x, n, o);
-        int x0, x1, y0, y1;
         set_bounds(px, py, r, gw, gh, g.w, g.h, x0, x1, y0, y1);
-        int vis = 0, m = 0;
-        for (int y = y0; y <= y1; ++y)
-            for (int xx = x0; xx <= x1; ++xx) {
-                if (g.prim[(int64_t)y * g.w + xx] == OCR_HIT_MISS) continue;
+    }
+    const int ex = gw == 0 ? 2 * r + 1 : gw, ey = gw == 0 ? 2 * r + 1 : gh;
+    int vis = 0, m = 0;
+    for (int dy = 0; dy < ey; ++dy)
+        for (int dx = 0; dx < ex; ++dx) {
+            const int y = y0 + dy, xx = x0 + dx;
+            const bool in = y <= y1 && xx <= x1 && g.prim[(int64_t)y * g.w + xx] != OCR_HIT_MISS;
+            bool want = false, overflow = false, blocked = false;
+            TRay ray{};
+            if (in) {
                 ++m;
                 float yl[3], d[3];
                 light_point((uint32_t)xx, (uint32_t)y, sample, sd, L, yl);
                 d[0] = yl[0] - o[0];
                 d[1] = yl[1] - o[1];
                 d[2] = yl[2] - o[2];
-                if (!shadow_traced(n, o, d, L)) continue;
-                TRay ray;
-                make_ray(o, d, prim, OCR_HIT_MISS, 1.0f, ray);
-                const Hit h = traverse<true, false>(bvh, ray, 1.0f, stack + threadIdx.x, kBBlock2);
-                if (h.tri == OCR_HIT_MISS) ++vis;
+                if (shadow_traced(n, o, d, L)) {
+                    want = true;
+                    make_ray(o, d, prim, OCR_HIT_MISS, 1.0f, ray);
+                    const Hit h = traverse<true, false>(bvh, ray, 1.0f, stack + threadIdx.x, kBBlock2, overflow);
+                    blocked = h.tri != OCR_HIT_MISS;
+                }
             }
-        v = (float)vis / (float)m;
-    }
+            if (wave_ballot(overflow) != 0ull) {
+                const TRay rr[1] = {ray};
+                const bool wr[1] = {overflow};
+                bool br[1];
+                WalkStats st;
+                traverse_wave_any<1>(bvh, rr, 1.0f, wr, br, wstack[threadIdx.x >> 6], st);
+                if (overflow) blocked = br[0];
+            }
+            if (want && !blocked) ++vis;
+        }
+    if (!inside) return;
+    const float v = prim != OCR_HIT_MISS ? (float)vis / (float)m : 0.0f;
     out[i] = accumulate ? out[i] + v : v;
 }
 

@@ -81,6 +81,7 @@ __global__ __launch_bounds__(kBBlock, 7) void batch_trace_kernel(const BatchView
                                                               const uint32_t *__restrict__ q_start, uint32_t *ctr,
                                                               int tw, int th, int packing) {
     __shared__ uint32_t stack[kStackLds * kBBlock];
+    __shared__ uint32_t wstack[kBBlock / 64][kStackTotal];
     const int lane = threadIdx.x & 63;
     const int home = blockIdx.x & 7;
     const int passes = (tw * th) >> 6;
@@ -105,14 +106,13 @@ __global__ __launch_bounds__(kBBlock, 7) void batch_trace_kernel(const BatchView
             int lx, ly;
             tile_pixel(packing, tw, th, it, lane, lx, ly);
             const int px = tx * tw + lx, py = ty * th + ly;
-            if (px < w && py < h) {
-                if (V.mode == OCR_AO)
-                    trace_pixel<OCR_AO>(V.bvh, V.g, V.R, V.L, V.sd, V.sample, V.occ, px, py, stack + threadIdx.x,
-                                        kBBlock);
-                else
-                    trace_pixel<OCR_SHADOW>(V.bvh, V.g, V.R, V.L, V.sd, V.sample, V.occ, px, py,
-                                            stack + threadIdx.x, kBBlock);
-            }
+            // every lane calls (the view's mode is the wave's)
+            if (V.mode == OCR_AO)
+                trace_pixel<OCR_AO>(V.bvh, V.g, V.R, V.L, V.sd, V.sample, V.occ, px, py, px < w && py < h,
+                                    stack + threadIdx.x, kBBlock, wstack[threadIdx.x >> 6]);
+            else
+                trace_pixel<OCR_SHADOW>(V.bvh, V.g, V.R, V.L, V.sd, V.sample, V.occ, px, py, px < w && py < h,
+                                        stack + threadIdx.x, kBBlock, wstack[threadIdx.x >> 6]);
         }
     }
 }

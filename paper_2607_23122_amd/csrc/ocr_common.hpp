@@ -29,11 +29,11 @@ static_assert(sizeof(Node4) == 128, "node must be one cache line");
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr int kMaxLeaf = 8;
-// Per-lane traversal stack: 16 entries in LDS per lane plus 48 spill entries
-// in private memory; the builder keeps 3 * depth + 1 <= kStackTotal.  16 LDS
-// entries (16 KB per 256-lane block) let the register limit, not LDS, set
-// the trace kernel's occupancy; measured 17% faster than 32 entries, and
-// the spill entries are rarely reached.
+// Per-lane traversal stack: 16 entries in LDS per lane (16 KB per 256-lane
+// block lets the register limit, not LDS, set the trace kernel's occupancy;
+// measured 17% faster than 32 entries).  A walk that needs more stops and
+// its ray is decided by a wave-coherent walk, whose stack of kStackTotal
+// entries per wave the builder guarantees (3 * depth + 1 <= kStackTotal).
 constexpr int kStackLds = 16;
 constexpr int kStackTotal = 64;
 constexpr int kMaxDepth = (kStackTotal - 1) / 3;

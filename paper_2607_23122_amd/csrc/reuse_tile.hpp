@@ -9,13 +9,17 @@
 //
 // P_i(j) depends on both i and j, but only through the pair densities p_k(j)
 // with k - j in [-2R, 2R]^2, each needed by every target whose window holds
-// both.  So each candidate j is handled by one wave that evaluates those
-// (4R+1)^2 densities once, forms every P_i(j) for the (2R+1)^2 targets around
-// j as box sums, and scatters p_i(j)/P_i(j) to the targets.  A block owns a
-// 16x16 target tile and stages the receivers of the tile plus an R-pixel halo
-// in LDS; the scattered terms are summed in LDS as 32.32 fixed-point
-// integers, which makes the sum independent of the order in which waves
-// arrive (bitwise reproducible) at ~2^-33 absolute error per term.
+// both.  So each candidate j's (4R+1)^2 densities are evaluated once, every
+// P_i(j) for the (2R+1)^2 targets around j is formed as box sums (row sums,
+// then column sums), and p_i(j)/P_i(j) is scattered to the targets.  A block
+// owns a 16x16 target tile and stages the receivers of the tile plus an
+// R-pixel halo in LDS; the scattered terms are summed in LDS as 32.32
+// fixed-point integers, which makes the sum independent of the order in which
+// waves arrive (bitwise reproducible) at ~2^-33 absolute error per term.
+// For R = 1..3 a lane takes one receiver row of one candidate (its densities
+// in registers, its row sums to LDS) and then one (candidate, target) pair;
+// other radii take one wave per candidate.  Both sum in the same order, so
+// they give the same bits.
 #pragma once
 #include "density.hpp"
 #include "lights.hpp"
@@ -81,6 +85,10 @@ __device__ inline float noreuse_value(const GBufView &g, const OccView &occ, con
     }
 }
 
+// Radii the row-task body handles (compiled per radius); others take the
+// per-candidate body.
+__host__ __device__ constexpr bool row_body_radius(int R) { return R >= 1 && R <= 3; }
+
 // LDS layout of the window kernel for radius R (dynamic shared memory).
 struct WinLayout {
     int RWX, RWY, cells, side, dens, hsum, words;
@@ -111,7 +119,10 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     l.valid_off = lds_take(off, l.cells);
     l.miss_off = lds_take(off, l.cells);
     l.list_off = lds_take(off, 4 * sizeof(int) + sizeof(uint16_t) * l.cells);
-    l.wave_off = lds_take(off, sizeof(float) * (kRBlock / 64) * (l.dens + l.hsum));
+    // per-wave scratch: the per-candidate body's densities and box sums, or
+    // the row-task body's row sums and centre densities (64 rows of 2R + 1)
+    const int per_wave = row_body_radius(R) ? 2 * 64 * (2 * R + 1) : l.dens + l.hsum;
+    l.wave_off = lds_take(off, sizeof(float) * (kRBlock / 64) * per_wave);
     l.total = off;
     return l;
 }
@@ -141,6 +152,177 @@ __device__ inline float weighted_term(float ratio, const float *s_o, const float
         gf *= inv_bilinear_q(w, recv_load(v, L), L);
     }
     return fminf(ratio * gf, 0x1p31f);
+}
+
+// Inclusive prefix sum over the wave's 64 lanes.
+__device__ inline int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(v, d);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// The targets of tile cells [R, R + kWTX) x [R, R + kWTY) (staged
+// coordinates) that candidate cell (cx, cy) reaches, [tx0, tx0 + ntx) x
+// [ty0, ty0 + nty), and the receivers they need, [tx0 - R, tx0 + ntx + R) x
+// [ty0 - R, ty0 + nty + R).
+struct CandRect {
+    int tx0, ty0, ntx, nty;
+};
+__device__ inline CandRect cand_rect(int cx, int cy, int R) {
+    CandRect q;
+    q.tx0 = max(cx - R, R);
+    q.ty0 = max(cy - R, R);
+    q.ntx = min(cx + R, R + kWTX - 1) - q.tx0 + 1;
+    q.nty = min(cy + R, R + kWTY - 1) - q.ty0 + 1;
+    return q;
+}
+
+// Candidates of a staged tile with the row-task body (window radius R = 1..3,
+// a template parameter so that a receiver row's 4R + 1 densities stay in
+// registers).  Each wave takes a contiguous quarter of the tile's candidate
+// list in batches whose receiver rows fit in its 64 lanes.  A lane takes one
+// receiver row of one candidate j: the densities p_k(j) of the row's
+// receivers (in registers), then the row's box sums over each window of
+// 2R + 1 of them, H[t] = sum_e p(t + e) in e order, and the row's densities
+// at the target columns, both to LDS.  Then a lane takes one (candidate,
+// target) pair: P_i(j) = sum over the window's rows of H, in row order, and
+// scatters p_i(j) / P_i(j) as the per-candidate body does.  The sums run in
+// the same order as that body's, so the estimates are the same bits.
+template <int MODE, bool UNB, class LT, int R>
+__device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *smem, const GBufView &g,
+                                           const OccView &occ, float R2, const LT &L,
+                                           const uint32_t *__restrict__ bits, int words, int tx, int ty) {
+    constexpr int TW = 2 * R + 1, SIDE = 4 * R + 1, D = 2 * R;
+    const int TX = kWTX, TY = kWTY, RW = lay.RWX, CELLS = lay.cells;
+    const float inv_rw = 1.0f / (float)RW;
+    unsigned long long *s_B = reinterpret_cast<unsigned long long *>(smem + lay.B_off);
+    const float *s_o = reinterpret_cast<const float *>(smem + lay.o_off);
+    const float *s_n = reinterpret_cast<const float *>(smem + lay.n_off);
+    const float *s_sh = reinterpret_cast<const float *>(smem + lay.sh_off);
+    const int *s_count = reinterpret_cast<const int *>(smem + lay.list_off);
+    const uint16_t *s_list = reinterpret_cast<const uint16_t *>(smem + lay.list_off + 4 * sizeof(int));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float *w_H = reinterpret_cast<float *>(smem + lay.wave_off) + wave * (2 * 64 * TW);
+    float *w_C = w_H + 64 * TW;
+    const int x0 = tx * TX - R, y0 = ty * TY - R;
+    const int ncand = *s_count;
+    const int per = (ncand + kRBlock / 64 - 1) / (kRBlock / 64);
+    int cur = min(wave * per, ncand);
+    const int end = min(cur + per, ncand);
+    while (cur < end) {
+        // candidate lanes: lane k holds candidate cur + k, its receiver rows
+        // and its targets; the batch is the leading candidates whose rows fit
+        const int ci = cur + lane;
+        int c = 0, hd = 0, nt = 0;
+        if (ci < end) {
+            c = s_list[ci];
+            const int cy = small_div(c, inv_rw), cx = c - __mul24(cy, RW);
+            const CandRect q = cand_rect(cx, cy, R);
+            hd = q.nty + 2 * R;
+            nt = __mul24(q.ntx, q.nty);
+        }
+        const int rows_inc = wave_incl_scan(hd), tg_inc = wave_incl_scan(nt);
+        const int nb = __popcll(wave_ballot(ci < end && rows_inc <= 64));
+        const int rows_total = __builtin_amdgcn_readlane(rows_inc, nb - 1);
+        const int tg_total = __builtin_amdgcn_readlane(tg_inc, nb - 1);
+        const int rows_exc = rows_inc - hd, tg_exc = tg_inc - nt;
+
+        // (1) one receiver row per lane
+        {
+            int k = 0;
+            for (int m = 0; m < nb; ++m) k += lane >= __builtin_amdgcn_readlane(rows_inc, m) ? 1 : 0;
+            k = min(k, nb - 1);
+            const int cl = __shfl(c, k), rs = __shfl(rows_exc, k);
+            if (lane < rows_total) {
+                const int cy = small_div(cl, inv_rw), cx = cl - __mul24(cy, RW);
+                const CandRect q = cand_rect(cx, cy, R);
+                const int WD = q.ntx + 2 * R;
+                const int kx0 = q.tx0 - R, ky = q.ty0 - R + (lane - rs);
+                const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
+                const float oj[3] = {s_o[cl], s_o[CELLS + cl], s_o[2 * CELLS + cl]};
+                float dzj[3], nzj[3];
+                ld3(occ.dz, gj, dzj);
+                ld3(occ.nz, gj, nzj);
+                // unbiased: the row's validation bits, bit e for receiver kx0 + e
+                uint32_t rowbits = 0xFFFFFFFFu;
+                if (UNB) {
+                    const int qb = __mul24(ky - cy + D, SIDE) + (kx0 - cx + D);
+                    const int w0 = qb >> 5;
+                    const uint32_t lo = bits[gj * words + w0];
+                    const uint32_t hi = w0 + 1 < words ? bits[gj * words + w0 + 1] : 0u;
+                    rowbits = (uint32_t)((((unsigned long long)hi << 32) | lo) >> (qb & 31));
+                }
+                const int kcb = __mul24(ky, RW) + kx0;
+                float p[SIDE];
+#pragma unroll
+                for (int e = 0; e < SIDE; ++e) {
+                    p[e] = 0.0f;
+                    if (e < WD && ((rowbits >> e) & 1u)) {
+                        const int kc = kcb + e;
+                        const float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
+                        const float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
+                        float w[3];
+                        rel_vec(oj, ok, dzj, w);
+                        if constexpr (MODE == OCR_AO) {
+                            p[e] = dens_ao(w, nk, nzj, R2);
+                        } else {
+                            float v[kRecvFloats<LT>];
+                            for (int a = 0; a < kRecvFloats<LT>; ++a) v[a] = s_sh[a * CELLS + kc];
+                            p[e] = dens_light(w, nk, recv_load(v, L), nzj, L);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < TW; ++t) {
+                    float h = 0.0f;
+#pragma unroll
+                    for (int e = 0; e < TW; ++e) h += p[t + e];
+                    w_H[__mul24(lane, TW) + t] = h;
+                    w_C[__mul24(lane, TW) + t] = p[t + R];
+                }
+            }
+        }
+        wave_sync();
+        // (2) one (candidate, target) pair per lane
+        for (int q0 = 0; q0 < tg_total; q0 += 64) {
+            const int qq = q0 + lane;
+            int k = 0;
+            for (int m = 0; m < nb; ++m) k += qq >= __builtin_amdgcn_readlane(tg_inc, m) ? 1 : 0;
+            k = min(k, nb - 1);
+            const int cl = __shfl(c, k), rs = __shfl(rows_exc, k), ts = __shfl(tg_exc, k);
+            if (qq < tg_total) {
+                const int cy = small_div(cl, inv_rw), cx = cl - __mul24(cy, RW);
+                const CandRect q = cand_rect(cx, cy, R);
+                const int idx = qq - ts;
+                const int r2 = small_div(idx, __builtin_amdgcn_rcpf((float)q.ntx)), t2 = idx - __mul24(r2, q.ntx);
+                const float *ph = w_H + __mul24(rs + r2, TW) + t2;
+                float P = 0.0f;
+#pragma unroll
+                for (int e = 0; e < TW; ++e) P += ph[e * TW];
+                const float pij = w_C[__mul24(rs + r2 + R, TW) + t2];
+                if (pij > 0.0f && P > 0.0f) {
+                    float term = pij * __builtin_amdgcn_rcpf(P);
+                    if constexpr (MODE >= kShadowSA || kBilinear<LT>) {
+                        const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
+                        const float oj[3] = {s_o[cl], s_o[CELLS + cl], s_o[2 * CELLS + cl]};
+                        float dzj[3];
+                        ld3(occ.dz, gj, dzj);
+                        term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS,
+                                                   __mul24(q.ty0 + r2, RW) + (q.tx0 + t2), oj, dzj, L);
+                    }
+                    atomicAdd(&s_B[(q.ty0 + r2 - R) * TX + (q.tx0 + t2 - R)],
+                              (unsigned long long)rintf(term * 4294967296.0f));
+                }
+            }
+        }
+        wave_sync();  // the row sums are read before the next batch writes them
+        cur += nb;
+    }
+    (void)TY;
 }
 
 // One kWTX x kWTY target tile (tx, ty) of the sliding-window estimator; every
@@ -204,158 +386,166 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
     }
     __syncthreads();
 
-    // One wave per candidate j.
-    const int ncand = *s_count;
-    for (int li = wave; li < ncand; li += kRBlock / 64) {
-        const int c = __builtin_amdgcn_readfirstlane((int)s_list[li]);
-        const int cy = small_div(c, inv_rw), cx = c - __mul24(cy, RW);
-        const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
-        float oj[3] = {s_o[c], s_o[CELLS + c], s_o[2 * CELLS + c]};
-        float dzj[3], nzj[3];
-        ld3(occ.dz, gj, dzj);
-        ld3(occ.nz, gj, nzj);
-        // The targets of this tile that j reaches are the cells [tx0, tx1] x
-        // [ty0, ty1] (staged coordinates; the tile is [R, R + TX) x [R, R + TY));
-        // they need the receivers [tx0 - R, tx1 + R] x [ty0 - R, ty1 + R], a
-        // WD x HD rectangle inside the staged region (13 x 13 at R = 3 for a
-        // candidate whose targets are all in the tile, less in the halo).
-        const int tx0 = max(cx - R, R), tx1 = min(cx + R, R + TX - 1);
-        const int ty0 = max(cy - R, R), ty1 = min(cy + R, R + TY - 1);
-        const int ntx = tx1 - tx0 + 1, nty = ty1 - ty0 + 1;
-        const int WD = ntx + 2 * R, HD = nty + 2 * R;
-        const int kx0 = tx0 - R, ky0 = ty0 - R;
-        // (hardware reciprocals: small_div stays exact with a 1-ulp inverse
-        // for the quotients below, all < 2^12)
-        const float inv_wd = __builtin_amdgcn_rcpf((float)WD), inv_ntx = __builtin_amdgcn_rcpf((float)ntx);
-        const int nq = WD * HD;
-        // (1) densities p_k(j) over the rectangle, row stride SIDE; every lane
-        // runs every pass so that the count of positive densities is uniform.
-        // Shadow candidates have a few positive densities at most (the light
-        // subtends a narrow cone); AO candidates most often have dozens.
-        constexpr bool kSparsePath = MODE != OCR_AO;
-        int npos = 0;
-        int *e_code = reinterpret_cast<int *>(w_h);  // positive entries, q order
-        float *e_p = w_h + kSparse;
-        for (int q0 = 0; q0 < nq; q0 += 64) {
-            const int q = q0 + lane;
-            float p = 0.0f;
-            int qy = 0, qx = 0;
-            if (q < nq) {
-                // (index products by 24-bit multiplies: full rate, all operands < 2^23)
-                qy = small_div(q, inv_wd);
-                qx = q - __mul24(qy, WD);
-                const int kx = kx0 + qx, ky = ky0 + qy;
-                const int kc = __mul24(ky, RW) + kx;
-                // unbiased: candidate j's validation bit for the receiver at
-                // offset k - j first.  It is set only where the validation
-                // found the same density positive (and the segment free), so
-                // a pair without it contributes 0 whatever its density, and a
-                // round with no bit set skips the densities altogether
-                // (shadow candidates have a few positive pairs, clustered).
-                bool need = true;
-                if (UNB) {
-                    const int qb = __mul24(ky - cy + D, SIDE) + (kx - cx + D);
-                    const uint32_t wv = bits[gj * words + (qb >> 5)];
-                    need = (wv >> (qb & 31)) & 1u;
+    if (R == 1) {
+        tile_row_candidates<MODE, UNB, LT, 1>(lay, smem, g, occ, R2, L, bits, words, tx, ty);
+    } else if (R == 2) {
+        tile_row_candidates<MODE, UNB, LT, 2>(lay, smem, g, occ, R2, L, bits, words, tx, ty);
+    } else if (R == 3) {
+        tile_row_candidates<MODE, UNB, LT, 3>(lay, smem, g, occ, R2, L, bits, words, tx, ty);
+    } else {
+        // Other radii: one wave per candidate j.
+        const int ncand = *s_count;
+        for (int li = wave; li < ncand; li += kRBlock / 64) {
+            const int c = __builtin_amdgcn_readfirstlane((int)s_list[li]);
+            const int cy = small_div(c, inv_rw), cx = c - __mul24(cy, RW);
+            const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
+            float oj[3] = {s_o[c], s_o[CELLS + c], s_o[2 * CELLS + c]};
+            float dzj[3], nzj[3];
+            ld3(occ.dz, gj, dzj);
+            ld3(occ.nz, gj, nzj);
+            // The targets of this tile that j reaches are the cells [tx0, tx1] x
+            // [ty0, ty1] (staged coordinates; the tile is [R, R + TX) x [R, R + TY));
+            // they need the receivers [tx0 - R, tx1 + R] x [ty0 - R, ty1 + R], a
+            // WD x HD rectangle inside the staged region (13 x 13 at R = 3 for a
+            // candidate whose targets are all in the tile, less in the halo).
+            const int tx0 = max(cx - R, R), tx1 = min(cx + R, R + TX - 1);
+            const int ty0 = max(cy - R, R), ty1 = min(cy + R, R + TY - 1);
+            const int ntx = tx1 - tx0 + 1, nty = ty1 - ty0 + 1;
+            const int WD = ntx + 2 * R, HD = nty + 2 * R;
+            const int kx0 = tx0 - R, ky0 = ty0 - R;
+            // (hardware reciprocals: small_div stays exact with a 1-ulp inverse
+            // for the quotients below, all < 2^12)
+            const float inv_wd = __builtin_amdgcn_rcpf((float)WD), inv_ntx = __builtin_amdgcn_rcpf((float)ntx);
+            const int nq = WD * HD;
+            // (1) densities p_k(j) over the rectangle, row stride SIDE; every lane
+            // runs every pass so that the count of positive densities is uniform.
+            // Shadow candidates have a few positive densities at most (the light
+            // subtends a narrow cone); AO candidates most often have dozens.
+            constexpr bool kSparsePath = MODE != OCR_AO;
+            int npos = 0;
+            int *e_code = reinterpret_cast<int *>(w_h);  // positive entries, q order
+            float *e_p = w_h + kSparse;
+            for (int q0 = 0; q0 < nq; q0 += 64) {
+                const int q = q0 + lane;
+                float p = 0.0f;
+                int qy = 0, qx = 0;
+                if (q < nq) {
+                    // (index products by 24-bit multiplies: full rate, all operands < 2^23)
+                    qy = small_div(q, inv_wd);
+                    qx = q - __mul24(qy, WD);
+                    const int kx = kx0 + qx, ky = ky0 + qy;
+                    const int kc = __mul24(ky, RW) + kx;
+                    // unbiased: candidate j's validation bit for the receiver at
+                    // offset k - j first.  It is set only where the validation
+                    // found the same density positive (and the segment free), so
+                    // a pair without it contributes 0 whatever its density, and a
+                    // round with no bit set skips the densities altogether
+                    // (shadow candidates have a few positive pairs, clustered).
+                    bool need = true;
+                    if (UNB) {
+                        const int qb = __mul24(ky - cy + D, SIDE) + (kx - cx + D);
+                        const uint32_t wv = bits[gj * words + (qb >> 5)];
+                        need = (wv >> (qb & 31)) & 1u;
+                    }
+                    if (need) {
+                        float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
+                        float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
+                        float w[3];
+                        rel_vec(oj, ok, dzj, w);
+                        if (MODE == OCR_AO) {
+                            p = dens_ao(w, nk, nzj, R2);
+                        } else {
+                            float v[kRecvFloats<LT>];
+                            for (int a = 0; a < kRecvFloats<LT>; ++a) v[a] = s_sh[a * CELLS + kc];
+                            p = dens_light(w, nk, recv_load(v, L), nzj, L);
+                        }
+                    }
+                    w_dens[__mul24(qy, SIDE) + qx] = p;
                 }
-                if (need) {
-                    float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
-                    float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
-                    float w[3];
-                    rel_vec(oj, ok, dzj, w);
-                    if (MODE == OCR_AO) {
-                        p = dens_ao(w, nk, nzj, R2);
-                    } else {
-                        float v[kRecvFloats<LT>];
-                        for (int a = 0; a < kRecvFloats<LT>; ++a) v[a] = s_sh[a * CELLS + kc];
-                        p = dens_light(w, nk, recv_load(v, L), nzj, L);
+                if (!kSparsePath) continue;
+                const unsigned long long pm = __ballot(p > 0.0f);
+                if (npos < kSparse) {
+                    // keep the first kSparse positive entries for the sparse path
+                    const int at = npos + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(pm >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
+                    if (p > 0.0f && at < kSparse) {
+                        e_code[at] = (qy << 8) | qx;
+                        e_p[at] = p;
                     }
                 }
-                w_dens[__mul24(qy, SIDE) + qx] = p;
-            }
-            if (!kSparsePath) continue;
-            const unsigned long long pm = __ballot(p > 0.0f);
-            if (npos < kSparse) {
-                // keep the first kSparse positive entries for the sparse path
-                const int at = npos + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(pm >> 32),
-                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)pm, 0u));
-                if (p > 0.0f && at < kSparse) {
-                    e_code[at] = (qy << 8) | qx;
-                    e_p[at] = p;
-                }
-            }
-            npos += (int)__popcll(pm);
-        }
-        wave_sync();
-        if (kSparsePath && npos <= kSparse) {
-            // (2') Few positive densities (most shadow candidates): P_i(j) from
-            // the positive entries alone.  Lane e takes entry e; the sums run
-            // over the rows in order and within a row over the columns in
-            // order, the grouping of the box sums below, which only add zeros
-            // besides (exact), so both paths give the same bits.
-            int my_code = 0;
-            float my_p = 0.0f;
-            if (lane < npos) {
-                my_code = e_code[lane];
-                my_p = e_p[lane];
-            }
-            const int my_y = my_code >> 8, my_x = my_code & 255;
-            const bool tgt = lane < npos && my_x >= R && my_x < R + ntx && my_y >= R && my_y < R + nty;
-            if (__ballot(tgt) != 0ull) {
-                float P = 0.0f, h = 0.0f;
-                int row = -1;
-                for (int m = 0; m < npos; ++m) {
-                    const int cm = __builtin_amdgcn_readlane(my_code, m);
-                    const float pv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_p), m));
-                    const int ym = cm >> 8, xm = cm & 255;
-                    if (ym != row) {
-                        P += h;
-                        h = 0.0f;
-                        row = ym;
-                    }
-                    if (abs(ym - my_y) <= R && abs(xm - my_x) <= R) h += pv;
-                }
-                P += h;
-                if (tgt) {
-                    float term = my_p * __builtin_amdgcn_rcpf(P);
-                    if constexpr (MODE >= kShadowSA || kBilinear<LT>)
-                        term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ky0 + my_y, RW) + (kx0 + my_x),
-                                                   oj, dzj, L);
-                    atomicAdd(&s_B[(ky0 + my_y - R) * TX + (kx0 + my_x - R)],
-                              (unsigned long long)rintf(term * 4294967296.0f));
-                }
-            }
-        } else {
-            // (2) row box sums H[row][t] = sum_{e < 2R+1} p(row, t + e), t < ntx
-            for (int q = lane; q < HD * ntx; q += 64) {
-                const int row = small_div(q, inv_ntx), t2 = q - __mul24(row, ntx);
-                const float *pr = w_dens + __mul24(row, SIDE) + t2;
-                float h = 0.0f;
-                // unrolled so the LDS reads issue together; the additions keep their order
-#pragma unroll 4
-                for (int e = 0; e < TW; ++e) h += pr[e];
-                w_h[__mul24(row, TW) + t2] = h;
+                npos += (int)__popcll(pm);
             }
             wave_sync();
-            // (3) target i = (tx0 + t2, ty0 + r2): P_i(j) is the column box sum of H
-            for (int q = lane; q < nty * ntx; q += 64) {
-                const int r2 = small_div(q, inv_ntx), t2 = q - __mul24(r2, ntx);
-                const float *ph = w_h + __mul24(r2, TW) + t2;
-                float P = 0.0f;
-#pragma unroll 4
-                for (int e = 0; e < TW; ++e) P += ph[__mul24(e, TW)];
-                const float pij = w_dens[__mul24(r2 + R, SIDE) + (t2 + R)];
-                if (pij > 0.0f && P > 0.0f) {
-                    float term = pij * __builtin_amdgcn_rcpf(P);
-                    if constexpr (MODE >= kShadowSA || kBilinear<LT>)
-                        term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ty0 + r2, RW) + (tx0 + t2), oj,
-                                                   dzj, L);
-                    atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],
-                              (unsigned long long)rintf(term * 4294967296.0f));
+            if (kSparsePath && npos <= kSparse) {
+                // (2') Few positive densities (most shadow candidates): P_i(j) from
+                // the positive entries alone.  Lane e takes entry e; the sums run
+                // over the rows in order and within a row over the columns in
+                // order, the grouping of the box sums below, which only add zeros
+                // besides (exact), so both paths give the same bits.
+                int my_code = 0;
+                float my_p = 0.0f;
+                if (lane < npos) {
+                    my_code = e_code[lane];
+                    my_p = e_p[lane];
+                }
+                const int my_y = my_code >> 8, my_x = my_code & 255;
+                const bool tgt = lane < npos && my_x >= R && my_x < R + ntx && my_y >= R && my_y < R + nty;
+                if (__ballot(tgt) != 0ull) {
+                    float P = 0.0f, h = 0.0f;
+                    int row = -1;
+                    for (int m = 0; m < npos; ++m) {
+                        const int cm = __builtin_amdgcn_readlane(my_code, m);
+                        const float pv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_p), m));
+                        const int ym = cm >> 8, xm = cm & 255;
+                        if (ym != row) {
+                            P += h;
+                            h = 0.0f;
+                            row = ym;
+                        }
+                        if (abs(ym - my_y) <= R && abs(xm - my_x) <= R) h += pv;
+                    }
+                    P += h;
+                    if (tgt) {
+                        float term = my_p * __builtin_amdgcn_rcpf(P);
+                        if constexpr (MODE >= kShadowSA || kBilinear<LT>)
+                            term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ky0 + my_y, RW) + (kx0 + my_x),
+                                                       oj, dzj, L);
+                        atomicAdd(&s_B[(ky0 + my_y - R) * TX + (kx0 + my_x - R)],
+                                  (unsigned long long)rintf(term * 4294967296.0f));
+                    }
+                }
+            } else {
+                // (2) row box sums H[row][t] = sum_{e < 2R+1} p(row, t + e), t < ntx
+                for (int q = lane; q < HD * ntx; q += 64) {
+                    const int row = small_div(q, inv_ntx), t2 = q - __mul24(row, ntx);
+                    const float *pr = w_dens + __mul24(row, SIDE) + t2;
+                    float h = 0.0f;
+                    // unrolled so the LDS reads issue together; the additions keep their order
+    #pragma unroll 4
+                    for (int e = 0; e < TW; ++e) h += pr[e];
+                    w_h[__mul24(row, TW) + t2] = h;
+                }
+                wave_sync();
+                // (3) target i = (tx0 + t2, ty0 + r2): P_i(j) is the column box sum of H
+                for (int q = lane; q < nty * ntx; q += 64) {
+                    const int r2 = small_div(q, inv_ntx), t2 = q - __mul24(r2, ntx);
+                    const float *ph = w_h + __mul24(r2, TW) + t2;
+                    float P = 0.0f;
+    #pragma unroll 4
+                    for (int e = 0; e < TW; ++e) P += ph[__mul24(e, TW)];
+                    const float pij = w_dens[__mul24(r2 + R, SIDE) + (t2 + R)];
+                    if (pij > 0.0f && P > 0.0f) {
+                        float term = pij * __builtin_amdgcn_rcpf(P);
+                        if constexpr (MODE >= kShadowSA || kBilinear<LT>)
+                            term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS, __mul24(ty0 + r2, RW) + (tx0 + t2), oj,
+                                                       dzj, L);
+                        atomicAdd(&s_B[(ty0 + r2 - R) * TX + (tx0 + t2 - R)],
+                                  (unsigned long long)rintf(term * 4294967296.0f));
+                    }
                 }
             }
+            wave_sync();
         }
-        wave_sync();
     }
     __syncthreads();
 

@@ -33,13 +33,14 @@ template <int MODE, class LT = LightF>
 __global__ __launch_bounds__(kBlock) void trace_kernel(DeviceBVH bvh, GBufView g, float R, LT L, uint32_t sd,
                                                        uint32_t sample, OccView out, int tiles_x, int ntiles) {
     __shared__ uint32_t stack[kStackLds * kBlock];
+    __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
     int tx, ty;
     tile_of_block(tiles_x, ntiles, tx, ty);
-    if (ty * tiles_x + tx >= ntiles) return;
+    if (ty * tiles_x + tx >= ntiles) return;  // the whole block
     int px, py;
     pixel_of_thread(tx, ty, px, py);
-    if (px >= g.w || py >= g.h) return;
-    trace_pixel<MODE, false, LT>(bvh, g, R, L, sd, sample, out, px, py, stack + threadIdx.x, kBlock);
+    trace_pixel<MODE, false, LT>(bvh, g, R, L, sd, sample, out, px, py, px < g.w && py < g.h, stack + threadIdx.x,
+                                 kBlock, wstack[threadIdx.x >> 6]);
 }
 
 // Shadow records of several lights with wave-coherent walks: the wave walks
@@ -103,14 +104,15 @@ __global__ __launch_bounds__(kBlock) void trace_count_kernel(DeviceBVH bvh, GBuf
                                                              uint32_t sd, uint32_t sample, OccView out, int tiles_x,
                                                              int ntiles, uint64_t *stats) {
     __shared__ uint32_t stack[kStackLds * kBlock];
+    __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
     int tx, ty;
     tile_of_block(tiles_x, ntiles, tx, ty);
-    if (ty * tiles_x + tx >= ntiles) return;
+    if (ty * tiles_x + tx >= ntiles) return;  // the whole block
     int px, py;
     pixel_of_thread(tx, ty, px, py);
     WalkStats ws;
-    if (px < g.w && py < g.h)
-        trace_pixel<MODE, true>(bvh, g, R, L, sd, sample, out, px, py, stack + threadIdx.x, kBlock, &ws);
+    trace_pixel<MODE, true>(bvh, g, R, L, sd, sample, out, px, py, px < g.w && py < g.h, stack + threadIdx.x, kBlock,
+                            wstack[threadIdx.x >> 6], &ws);
     uint64_t v[5] = {ws.walks, ws.nodes, ws.box_tests, ws.tri_tests, ws.walks};
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -378,10 +380,11 @@ __global__ __launch_bounds__(kBlock) void validate_group_kernel(DeviceBVH bvh, G
                                                                 LT L, int N, int gw, int gh, int D, int words,
                                                                 uint32_t *bits, int tiles_x, int ntiles) {
     __shared__ uint32_t stack[kStackLds * kBlock];
+    __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
     __shared__ uint32_t s_words[kBlock * 2];
     int tx, ty;
     tile_of_block(tiles_x, ntiles, tx, ty);
-    if (ty * tiles_x + tx >= ntiles) return;
+    if (ty * tiles_x + tx >= ntiles) return;  // the whole block
     const int tid = threadIdx.x;
     s_words[2 * tid] = 0u;
     s_words[2 * tid + 1] = 0u;
@@ -389,19 +392,23 @@ __global__ __launch_bounds__(kBlock) void validate_group_kernel(DeviceBVH bvh, G
     const int side = 2 * D + 1;
     const int ngroups = (32 / gw) * (8 / gh);
     const int npairs = ngroups * N * N;
-    for (int P = tid; P < npairs; P += kBlock) {
+    // rounds of one pair per lane (every lane runs every round, so that a
+    // wave can decide the segments whose per-lane walk overflowed together)
+    for (int base = 0; base < npairs; base += kBlock) {
+        const int P = base + tid;
         const int grp = P / (N * N), pr = P % (N * N), m = pr / N, kk = pr % N;
         const int gx0 = (grp % (32 / gw)) * gw, gy0 = (grp / (32 / gw)) * gh;
         const int mlx = gx0 + m % gw, mly = gy0 + m / gw, klx = gx0 + kk % gw, kly = gy0 + kk / gw;
         const int mx = tx * 32 + mlx, my = ty * 8 + mly, kx = tx * 32 + klx, ky = ty * 8 + kly;
-        if (mx >= g.w || my >= g.h || kx >= g.w || ky >= g.h) continue;
-        const int64_t j = (int64_t)my * g.w + mx, k = (int64_t)ky * g.w + kx;
-        const uint32_t hj = occ.hit[j], primk = g.prim[k];
-        if (hj >= OCR_HIT_SELF || primk == OCR_HIT_MISS) continue;
-        bool bit = false;
-        if (j == k) {
+        bool pair = P < npairs && mx < g.w && my < g.h && kx < g.w && ky < g.h;
+        const int64_t j = pair ? (int64_t)my * g.w + mx : 0, k = pair ? (int64_t)ky * g.w + kx : 0;
+        const uint32_t hj = pair ? occ.hit[j] : OCR_HIT_MISS, primk = pair ? g.prim[k] : OCR_HIT_MISS;
+        pair = pair && hj < OCR_HIT_SELF && primk != OCR_HIT_MISS;
+        bool bit = false, overflow = false;
+        TRay r{};
+        if (pair && j == k) {
             bit = true;
-        } else {
+        } else if (pair) {
             float xj[3], nj[3], oj[3], dzj[3], nzj[3], xk[3], nk[3], ok[3], w[3];
             load3(g.pos, j, xj);
             load3(g.nrm, j, nj);
@@ -419,11 +426,18 @@ __global__ __launch_bounds__(kBlock) void validate_group_kernel(DeviceBVH bvh, G
                 p = dens_light(w, nk, recv_of(ok, L), nzj, L);
             }
             if (p > 0.0f) {
-                TRay r;
                 make_ray(ok, w, hj, primk, 1.0f - 1e-4f, r);
-                Hit h = traverse<true, false>(bvh, r, 1.0f - 1e-4f, stack + threadIdx.x, kBlock);
+                Hit h = traverse<true, false>(bvh, r, 1.0f - 1e-4f, stack + threadIdx.x, kBlock, overflow);
                 bit = h.tri == OCR_HIT_MISS;
             }
+        }
+        if (wave_ballot(overflow) != 0ull) {
+            const TRay rr[1] = {r};
+            const bool wr[1] = {overflow};
+            bool br[1];
+            WalkStats st;
+            traverse_wave_any<1>(bvh, rr, 1.0f - 1e-4f, wr, br, wstack[tid >> 6], st);
+            if (overflow) bit = !br[0];
         }
         if (bit) {
             const int bidx = (kly - mly + D) * side + (klx - mlx + D);

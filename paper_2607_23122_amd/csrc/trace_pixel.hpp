@@ -14,43 +14,58 @@ __device__ inline void load3(const float *p, int64_t i, float v[3]) {
 }
 
 // Sample pixel (px, py), trace its ray and write its occluder record.
-// `stack` is this lane's LDS stack, `stride` apart between entries.  With
-// COUNT the walk's work is added to *ws.  LT: one light (LightF) or several
-// (LightSetF, shadows).
+// Every lane of the wave calls it (`inside` false: the lane rides along).
+// `stack` is this lane's LDS stack, `stride` apart between entries; `wstack`
+// the wave's stack of kStackTotal entries for the rays whose per-lane walk
+// overflowed its stack (decided again by a wave-coherent walk: the same
+// closest hit).  With COUNT the per-lane walks' work is added to *ws.  LT:
+// one light (LightF) or several (LightSetF, shadows).
 template <int MODE, bool COUNT = false, class LT = LightF>
 __device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, float R, const LT &L, uint32_t sd,
-                                   uint32_t sample, const OccView &out, int px, int py, uint32_t *stack,
-                                   int stride, WalkStats *ws = nullptr) {
-    int64_t i = (int64_t)py * g.w + px;
-    uint32_t prim = g.prim[i];
-    if (prim == OCR_HIT_MISS) {
-        out.hit[i] = OCR_HIT_MISS;
+                                   uint32_t sample, const OccView &out, int px, int py, bool inside,
+                                   uint32_t *stack, int stride, uint32_t *wstack, WalkStats *ws = nullptr) {
+    const int64_t i = inside ? (int64_t)py * g.w + px : 0;
+    const uint32_t prim = inside ? g.prim[i] : OCR_HIT_MISS;
+    uint32_t code = OCR_HIT_MISS;  // background, or a shadow sample that is not traced
+    float d[3] = {0.f, 0.f, 0.f};
+    const float tmax = MODE == OCR_AO ? R : 1.0f;
+    bool want = false;
+    TRay r{};
+    if (prim != OCR_HIT_MISS) {
+        float x[3], n[3], o[3];
+        load3(g.pos, i, x);
+        load3(g.nrm, i, n);
+        offset_point(x, n, o);
+        if (MODE == OCR_AO) {
+            ao_direction((uint32_t)px, (uint32_t)py, sample, sd, n, d);
+            want = true;
+        } else {
+            float y[3];
+            LightF Lc;  // the light the sample lies on
+            pick_light((uint32_t)px, (uint32_t)py, sample, sd, L, o, y, Lc);
+            d[0] = y[0] - o[0];
+            d[1] = y[1] - o[1];
+            d[2] = y[2] - o[2];
+            want = shadow_traced(n, o, d, Lc);
+            if (!want) code = OCR_HIT_SELF;
+        }
+        if (want) make_ray(o, d, prim, OCR_HIT_MISS, tmax, r);
+    }
+    Hit h;
+    h.t = tmax;
+    h.tri = OCR_HIT_MISS;
+    h.leaf_tri = 0;
+    bool overflow = false;
+    if (want) h = traverse<false, MODE == OCR_AO, COUNT>(bvh, r, tmax, stack, stride, overflow, ws);
+    if (wave_ballot(overflow) != 0ull) {
+        const Hit hw = traverse_wave_closest<MODE == OCR_AO>(bvh, r, tmax, overflow, wstack);
+        if (overflow) h = hw;
+    }
+    if (!inside) return;
+    if (!want) {
+        out.hit[i] = code;
         return;
     }
-    float x[3], n[3], o[3], d[3];
-    load3(g.pos, i, x);
-    load3(g.nrm, i, n);
-    offset_point(x, n, o);
-    float tmax;
-    if (MODE == OCR_AO) {
-        ao_direction((uint32_t)px, (uint32_t)py, sample, sd, n, d);
-        tmax = R;
-    } else {
-        float y[3];
-        LightF Lc;  // the light the sample lies on
-        pick_light((uint32_t)px, (uint32_t)py, sample, sd, L, o, y, Lc);
-        d[0] = y[0] - o[0];
-        d[1] = y[1] - o[1];
-        d[2] = y[2] - o[2];
-        if (!shadow_traced(n, o, d, Lc)) {
-            out.hit[i] = OCR_HIT_SELF;
-            return;
-        }
-        tmax = 1.0f;
-    }
-    TRay r;
-    make_ray(o, d, prim, OCR_HIT_MISS, tmax, r);
-    Hit h = traverse<false, MODE == OCR_AO, COUNT>(bvh, r, tmax, stack, stride, ws);
     out.hit[i] = h.tri;
     if (h.tri == OCR_HIT_MISS) return;
     float nz[3];

@@ -2,7 +2,10 @@
 //
 // One lane per ray.  The traversal stack lives in LDS, one column per lane
 // (entry k of lane t at [k * blockDim + t], so lanes at equal depth hit
-// distinct banks), with a private spill area for the rare deep paths.
+// distinct banks), kStackLds entries deep and nothing in private memory: a
+// walk that would push past it stops and reports the overflow, and the
+// caller decides that ray with the wave-coherent walk below (its stack, one
+// per wave, holds the 3 depth + 1 entries any walk of the tree can need).
 // Child boxes are tested with a conservative slab test (one FMA per plane,
 // offsets and far distances widened so no box that the ray touches is
 // skipped; see TRay), and
@@ -122,16 +125,17 @@ struct Hit {
 // Closest hit over t in (0, tmax] (INCLUSIVE) or (0, tmax); with ANY, the
 // first hit found over (0, tmax) ends the query.  Equal distances resolve
 // to the smaller scene triangle index.  With COUNT the walk's work is added
-// to *ws (a separate instantiation; the result is the same).
+// to *ws (a separate instantiation; the result is the same).  If a push would
+// take the stack past kStackLds entries the walk stops, sets `overflow` and
+// its result is not to be used.
 template <bool ANY, bool INCLUSIVE, bool COUNT = false>
 __device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, uint32_t *lds_stack, int stride,
-                               WalkStats *ws = nullptr) {
+                               bool &overflow, WalkStats *ws = nullptr) {
     if (COUNT) ws->walks += 1;
     Hit h;
     h.t = tmax;
     h.tri = OCR_HIT_MISS;
     h.leaf_tri = 0;
-    uint32_t spill[kStackTotal - kStackLds];
     int sp = 0;
     uint32_t node = 0;  // root
     const float grow = 1.0f + 0x1p-20f;
@@ -180,8 +184,11 @@ __device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, 
 #pragma unroll
                 for (int k = 3; k >= 1; --k) {
                     if (tn[k] < INFINITY) {
-                        if (sp < kStackLds) lds_stack[sp * stride] = cand[k];
-                        else spill[sp - kStackLds] = cand[k];
+                        if (sp == kStackLds) {
+                            overflow = true;
+                            return h;
+                        }
+                        lds_stack[sp * stride] = cand[k];
                         ++sp;
                     }
                 }
@@ -219,7 +226,7 @@ __device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, 
         }
         if (sp == 0) break;
         --sp;
-        node = sp < kStackLds ? lds_stack[sp * stride] : spill[sp - kStackLds];
+        node = lds_stack[sp * stride];
     }
     return h;
 }
