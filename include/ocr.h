@@ -273,6 +273,23 @@ ocr_status ocr_reuse_ao(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_o
                         const ocr_reuse_params *params, void *workspace, size_t workspace_bytes, float *out,
                         void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ocr_reuse_ao without the workspace argument.  The unbiased estimator's
+ * validation bits and candidate lists live in a device array of the library
+ * (64 MiB per device, held from the library's first use on that device until
+ * the process ends); the call allocates nothing, and its results are those of
+ * ocr_reuse_ao (the same kernels).
+ *   Arguments, output and errors as ocr_reuse_ao, and OCR_ERR_INVALID_ARG
+ *   when the frame needs more than 64 MiB of workspace (ocr_workspace_bytes;
+ *   a 1920x1080 window of radius 3 needs 58 MB) or when params->validated is
+ *   set (the validation runs within the call).
+ * Every call on a device shares that device's array and leaves its contents
+ * there: calls that overlap on one device (on different streams, or from
+ * different threads) race; the caller orders them. */
+ocr_status ocr_reuse_ao_noalloc(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                float ao_radius, const ocr_reuse_params *params, float *out, void *stream);
+
 /* Shadow reuse (Sec. 4.4): out[i] = F_i - B_i with B_i as above for p_Sh of
  * Eq. shadow-pdf (Jacobian of Eq. shadow-jacobian at the light
  * re-intersection y'(x,z); support: y' on the rectangle beyond z, on the

@@ -117,7 +117,7 @@ class ServerStats(ctypes.Structure):
 EXPORTS = ["ocr_build_bvh", "ocr_build_bvh_host", "ocr_bvh_free", "ocr_bvh_get_info", "ocr_trace_occluders",
            "ocr_trace_occluders_counted", "ocr_sample_rays",
            "ocr_workspace_bytes", "ocr_validate_pairs",
-           "ocr_reuse_ao", "ocr_reuse_shadow", "ocr_reuse_shadow_solid_angle", "ocr_reuse_direct_illumination",
+           "ocr_reuse_ao", "ocr_reuse_ao_noalloc", "ocr_reuse_shadow", "ocr_reuse_shadow_solid_angle", "ocr_reuse_direct_illumination",
            "ocr_trace_occluders_lights", "ocr_reuse_shadow_lights", "ocr_validate_pairs_lights",
            "ocr_filter_values",
            "ocr_light_reuse_shadow", "ocr_scale", "ocr_last_error",
@@ -166,6 +166,9 @@ def lib():
     L.ocr_reuse_ao.restype = i32
     L.ocr_reuse_ao.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), ctypes.c_float,
                                ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
+    L.ocr_reuse_ao_noalloc.restype = i32
+    L.ocr_reuse_ao_noalloc.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), ctypes.c_float,
+                                       ctypes.POINTER(ReuseParams), vp, vp]
     L.ocr_reuse_shadow.restype = i32
     L.ocr_reuse_shadow.argtypes = [vp, ctypes.POINTER(_GBuffer), ctypes.POINTER(_Occ), ctypes.POINTER(_Light),
                                    ctypes.POINTER(ReuseParams), vp, ctypes.c_size_t, vp, vp]
@@ -477,6 +480,16 @@ def reuse_ao(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluders, ao_radius: fl
     _check(lib().ocr_reuse_ao(bvh.h if bvh is not None else None, ctypes.byref(g), ctypes.byref(o), float(ao_radius),
                               ctypes.byref(params), _dptr(ws) if ws is not None else None, nbytes, _dptr(out),
                               _stream(stream)))
+    return out
+
+
+def reuse_ao_noalloc(bvh: BVH | None, gbuf: DeviceGBuffer, occ: Occluders, ao_radius: float, params: ReuseParams,
+                     out, stream=None):
+    """ocr_reuse_ao_noalloc: reuse_ao with the library's device scratch in
+    place of a workspace (the call allocates nothing; `out` is the caller's)."""
+    g, o = gbuf.c(), occ.c()
+    _check(lib().ocr_reuse_ao_noalloc(bvh.h if bvh is not None else None, ctypes.byref(g), ctypes.byref(o),
+                                      float(ao_radius), ctypes.byref(params), _dptr(out), _stream(stream)))
     return out
 
 

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libocr.so")
 SOURCES = ["api.cpp", "bvh_build.cpp", "trace.hip", "reuse.hip", "baselines.hip", "batch.hip", "plan.cpp",
-           "server.cpp"]
+           "server.cpp", "scratch.hip"]
 ARCH = "gfx950"
 
 

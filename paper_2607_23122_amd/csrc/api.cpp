@@ -394,6 +394,30 @@ ocr_status ocr_reuse_ao(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_o
     return reuse_common(bvh, gbuf, occ, OCR_AO, ao_radius, L, params, workspace, workspace_bytes, out, stream);
 }
 
+ocr_status ocr_reuse_ao_noalloc(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
+                                float ao_radius, const ocr_reuse_params *params, float *out, void *stream) {
+    if (!(std::isfinite(ao_radius) && ao_radius > 0.0f))
+        return fail(OCR_ERR_INVALID_ARG, "AO radius %g must be finite and > 0", (double)ao_radius);
+    ocr_status st = check_gbuf(gbuf);
+    if (st) return st;
+    if ((st = check_params(params))) return st;
+    if (params->estimator == OCR_UNBIASED && params->validated)
+        return fail(OCR_ERR_INVALID_ARG, "the no-allocation entry point validates within the call (validated = 0)");
+    const size_t need = ocr_workspace_bytes(gbuf->width, gbuf->height, params);
+    if (need > kScratchBytes)
+        return fail(OCR_ERR_INVALID_ARG, "a %dx%d frame needs %zu bytes of scratch; this entry point holds %zu",
+                    gbuf->width, gbuf->height, need, kScratchBytes);
+    void *ws = nullptr;
+    if (need > 0) {
+        hipError_t e = scratch_address(&ws);
+        if (e != hipSuccess) return hip_fail(e, "scratch address");
+    }
+    LightF L;
+    std::memset(&L, 0, sizeof L);
+    return reuse_common(bvh, gbuf, occ, OCR_AO, ao_radius, L, params, ws, need > 0 ? kScratchBytes : 0, out,
+                        stream);
+}
+
 ocr_status ocr_reuse_shadow(const ocr_bvh *bvh, const ocr_gbuffer *gbuf, const ocr_occluders *occ,
                             const ocr_rect_light *light, const ocr_reuse_params *params, void *workspace,
                             size_t workspace_bytes, float *out, void *stream) {

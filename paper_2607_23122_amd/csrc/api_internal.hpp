@@ -55,6 +55,13 @@ hipError_t launch_reuse_bilinear(const GBufView &g, const OccView &occ, int mode
                                  const ocr_reuse_params &p, const uint32_t *bits, float *out, hipStream_t st,
                                  float scale);
 
+// Scratch of the no-allocation entry point (scratch.hip): a static device
+// array of kScratchBytes per device; scratch_address gives its address on
+// the current device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxScratchDevices = 64;
+hipError_t scratch_address(void **ptr);
+
 // The simple reuse baselines (baselines.hip).
 hipError_t launch_filter(const GBufView &g, const ocr_reuse_params &p, const float *in, float *out, hipStream_t st);
 hipError_t launch_light_reuse(const DeviceBVH &bvh, const GBufView &g, const LightF &L, uint32_t seed32,

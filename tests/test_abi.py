@@ -80,3 +80,16 @@ def test_argument_validation_without_device():
                                 8, None) == -1
     assert b"zero length" in lib.ocr_last_error()
     assert lib.ocr_scale(None, 4, 1.0, None) == -1
+
+
+def test_noalloc_size_limit_without_device():
+    # a frame whose unbiased workspace exceeds the library's 64 MiB scratch is
+    # refused before any device call (the pointers are never dereferenced)
+    import paper_2607_23122_amd as ocr
+    lib = ocr.lib()
+    g = ocr._GBuffer(8, 8, 8, 4096, 4096)
+    o = ocr._Occ(8, 8, 8)
+    p = ocr.reuse_params("window", 3, 0, "unbiased")
+    assert ocr.workspace_bytes(4096, 4096, p) > 64 << 20
+    assert lib.ocr_reuse_ao_noalloc(None, ctypes.byref(g), ctypes.byref(o), 1.0, ctypes.byref(p), 8, None) == -1
+    assert b"scratch" in lib.ocr_last_error()
