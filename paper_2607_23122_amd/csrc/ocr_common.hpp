@@ -169,6 +169,17 @@ __device__ inline int small_div(int q, float inv_d) { return (int)(((float)q + 0
 // in a vector register and compares it again.
 __device__ inline unsigned long long wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Inclusive prefix sum over the wave's 64 lanes.
+__device__ inline int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(v, d);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
 // Make this wave's LDS writes visible to its other lanes before they read.
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");

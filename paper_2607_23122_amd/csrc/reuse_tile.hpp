@@ -154,17 +154,6 @@ __device__ inline float weighted_term(float ratio, const float *s_o, const float
     return fminf(ratio * gf, 0x1p31f);
 }
 
-// Inclusive prefix sum over the wave's 64 lanes.
-__device__ inline int wave_incl_scan(int v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_up(v, d);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
-
 // The targets of tile cells [R, R + kWTX) x [R, R + kWTY) (staged
 // coordinates) that candidate cell (cx, cy) reaches, [tx0, tx0 + ntx) x
 // [ty0, ty0 + nty), and the receivers they need, [tx0 - R, tx0 + ntx + R) x
