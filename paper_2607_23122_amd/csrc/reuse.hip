@@ -40,7 +40,12 @@ __global__ __launch_bounds__(kRBlock) void reuse_window_kernel(GBufView g, OccVi
 }
 
 // Fixed groups.  Block = 32 x 8 pixels; the group shapes (1x1, 2x1, 2x2,
-// 4x2) tile it exactly.
+// 4x2) tile it exactly.  One lane per pixel, in three roles: as receiver k it
+// evaluates the densities p_k(j) of its group's candidates; as candidate j it
+// sums its denominator P(j) over the group's receivers once (every target of
+// a group shares it); as target i it adds p_i(j) / P(j) over the candidates.
+// The pixel's G-buffer entry, hit id and validation words are read in one
+// round of loads, the hit's record in a second.
 template <int MODE, bool UNB, class LT = LightF>
 __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccView occ, float R2, LT L,
                                                               const uint32_t *__restrict__ bits, int words, int N,
@@ -50,8 +55,9 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     __shared__ float s_o[3][kRBlock], s_n[3][kRBlock], s_dz[3][kRBlock], s_nz[3][kRBlock];
     __shared__ uint32_t s_hit[kRBlock];
     __shared__ uint8_t s_val[kRBlock];
-    __shared__ uint32_t s_bits[kRBlock][2];
-    __shared__ float s_p[kRBlock][8];
+    __shared__ uint32_t s_bits[2][UNB ? kRBlock : 1];
+    __shared__ float s_p[8][kRBlock];  // s_p[m][k]: density of the group's candidate m at receiver k
+    __shared__ float s_P[kRBlock];     // s_P[j]: denominator of candidate j
 
     int tx, ty;
     r_tile_of_block(tiles_x, ntiles, tx, ty);
@@ -61,16 +67,24 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     const int px = tx * 32 + lx, py = ty * 8 + ly;
     const bool inside = px < g.w && py < g.h;
     const int64_t gi = inside ? (int64_t)py * g.w + px : 0;
-    const bool valid = inside && g.prim[gi] != OCR_HIT_MISS;
-    float o[3] = {0.f, 0.f, 0.f}, n[3] = {0.f, 0.f, 0.f};
-    uint32_t hit = OCR_HIT_MISS;
-    if (valid) {
-        float x[3];
+    // first round: every load of the pixel issued together
+    const uint32_t prim = inside ? g.prim[gi] : OCR_HIT_MISS;
+    const uint32_t hit0 = inside ? occ.hit[gi] : OCR_HIT_MISS;
+    float x[3] = {0.f, 0.f, 0.f}, n[3] = {0.f, 0.f, 0.f};
+    uint32_t b0 = 0u, b1 = 0u;
+    if (inside) {
         ld3(g.pos, gi, x);
         ld3(g.nrm, gi, n);
-        offset_point(x, n, o);
-        hit = occ.hit[gi];
+        if (UNB) {
+            b0 = bits[gi * words];
+            b1 = words > 1 ? bits[gi * words + 1] : 0u;
+        }
     }
+    const bool valid = prim != OCR_HIT_MISS;
+    const uint32_t hit = valid ? hit0 : OCR_HIT_MISS;
+    float o[3] = {0.f, 0.f, 0.f};
+    if (valid) offset_point(x, n, o);
+    else n[0] = n[1] = n[2] = 0.0f;
     for (int a = 0; a < 3; ++a) {
         s_o[a][tid] = o[a];
         s_n[a][tid] = n[a];
@@ -86,11 +100,11 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     }
     // this lane's light terms as a receiver (its point, for several lights)
     const auto rk = recv_of(o, L);
-    s_hit[tid] = valid ? hit : OCR_HIT_MISS;
+    s_hit[tid] = hit;
     s_val[tid] = valid;
     if (UNB) {
-        s_bits[tid][0] = valid ? bits[gi * words] : 0u;
-        s_bits[tid][1] = (valid && words > 1) ? bits[gi * words + 1] : 0u;
+        s_bits[0][tid] = valid ? b0 : 0u;
+        s_bits[1][tid] = valid ? b1 : 0u;
     }
     __syncthreads();
 
@@ -110,10 +124,19 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
             p = MODE == OCR_AO ? dens_ao(w, n, nzj, R2) : dens_light(w, n, rk, nzj, L);
             if (UNB && p > 0.0f) {
                 const int bidx = (ly - my + D) * SIDE + (lx - mx + D);
-                if (!((s_bits[jt][bidx >> 5] >> (bidx & 31)) & 1u)) p = 0.0f;
+                if (!((s_bits[bidx >> 5][jt] >> (bidx & 31)) & 1u)) p = 0.0f;
             }
         }
-        s_p[tid][m] = p;
+        s_p[m][tid] = p;
+    }
+    __syncthreads();
+
+    // this lane as candidate j: P(j) over the group's receivers, in receiver order
+    if (hit < OCR_HIT_SELF) {
+        const int mj = (ly - gy0) * gw + (lx - gx0);
+        float P = 0.0f;
+        for (int k = 0; k < N; ++k) P += s_p[mj][(gy0 + k / gw) * 32 + gx0 + k % gw];
+        s_P[tid] = P;
     }
     __syncthreads();
 
@@ -124,14 +147,11 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     for (int m = 0; m < N; ++m) {
         const int mx = gx0 + m % gw, my = gy0 + m / gw;
         const int jt = my * 32 + mx;
-        if (s_val[jt] && s_hit[jt] == OCR_HIT_MISS) ++misses;
-        if (s_hit[jt] >= OCR_HIT_SELF) continue;
-        float P = 0.0f;
-        for (int k = 0; k < N; ++k) {
-            const int kt = (gy0 + k / gw) * 32 + gx0 + k % gw;
-            P += s_p[kt][m];
-        }
-        const float pij = s_p[tid][m];
+        const uint32_t hj = s_hit[jt];
+        if (s_val[jt] && hj == OCR_HIT_MISS) ++misses;
+        if (hj >= OCR_HIT_SELF) continue;
+        const float P = s_P[jt];
+        const float pij = s_p[m][tid];
         if (pij > 0.0f && P > 0.0f) {
             float term = pij * __builtin_amdgcn_rcpf(P);
             if constexpr (MODE >= kShadowSA || kBilinear<LT>) {

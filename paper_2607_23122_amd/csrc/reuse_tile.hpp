@@ -54,11 +54,13 @@ __device__ inline float finish(int mode, bool valid, float B, float F, bool dark
 // is 1).
 template <int MODE, class LT>
 __device__ inline float noreuse_value(const GBufView &g, const OccView &occ, const LT &L, int64_t gi, float scale) {
-    const bool valid = g.prim[gi] != OCR_HIT_MISS;
+    // (both ids read together; a background pixel's hit id is never used)
+    const uint32_t prim = g.prim[gi], hit0 = occ.hit[gi];
+    const bool valid = prim != OCR_HIT_MISS;
     if constexpr (MODE == OCR_AO) {
-        return (!valid || occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
+        return (!valid || hit0 == OCR_HIT_MISS) ? 1.0f : 0.0f;
     } else if constexpr (MODE == OCR_SHADOW && !kBilinear<LT>) {
-        return (valid && occ.hit[gi] == OCR_HIT_MISS) ? 1.0f : 0.0f;
+        return (valid && hit0 == OCR_HIT_MISS) ? 1.0f : 0.0f;
     } else {
         if (!valid) return 0.0f;
         float x[3], n[3], o[3];
@@ -66,7 +68,7 @@ __device__ inline float noreuse_value(const GBufView &g, const OccView &occ, con
         ld3(g.nrm, gi, n);
         offset_point(x, n, o);
         float Bg = 0.0f;
-        const uint32_t hit = occ.hit[gi];
+        const uint32_t hit = hit0;
         if (hit < OCR_HIT_SELF) {
             float dz[3], nz[3];
             ld3(occ.dz, gi, dz);
