@@ -479,6 +479,7 @@ typedef struct {
     int32_t candidates;       /* knob settings the autotuner timed */
     double tune_ms;           /* autotuner wall time */
     double best_trace_ms;     /* autotuner's time for the chosen trace knobs */
+    int32_t from_cache;       /* 1 when an earlier plan of the same shape gave the knobs */
 } ocr_plan_info;
 
 /* Create a plan over `nviews` views (1..4096).  The plan allocates, once, the
@@ -486,6 +487,12 @@ typedef struct {
  * views and its work tables.  tuning: NULL = autotune (time every tile and
  * packing setting on these views with `stream` and keep the fastest; only
  * the plan's own records are written meanwhile), else use the given knobs.
+ * An autotuned choice is kept for the process, keyed by the device
+ * architecture and the view set's shape (each view's size, effect, reuse
+ * parameters and scene size); a later plan of the same shape takes it
+ * without timing (info.from_cache).  With the environment variable
+ * OCR_TUNE_CACHE naming a file, choices are also read from and appended to
+ * it, so they outlive the process.
  * Synchronous.  Errors: OCR_ERR_INVALID_ARG (any view argument that the
  * per-view calls would refuse, accumulate or validated set, bad knobs),
  * OCR_ERR_OOM, OCR_ERR_HIP. */

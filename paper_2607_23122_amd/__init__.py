@@ -84,7 +84,7 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("nviews", ctypes.c_int32), ("pixels", ctypes.c_int64), ("trace_items", ctypes.c_int64),
                 ("reuse_items", ctypes.c_int64), ("device_bytes", ctypes.c_int64), ("tuning", PlanTuning),
                 ("tuned", ctypes.c_int32), ("candidates", ctypes.c_int32), ("tune_ms", ctypes.c_double),
-                ("best_trace_ms", ctypes.c_double)]
+                ("best_trace_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
 
 
 class ServerOptions(ctypes.Structure):

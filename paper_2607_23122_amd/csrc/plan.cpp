@@ -7,9 +7,16 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cinttypes>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
+#include <utility>
 #include <vector>
 
 #include "api_internal.hpp"
@@ -33,7 +40,7 @@ struct ocr_plan {
     size_t reuse_lds = 0;
     int cus = 256, trace_bpc = 1, reuse_bpc = 1;
     ocr_plan_tuning tun{};
-    int tuned = 0, candidates = 0;
+    int tuned = 0, candidates = 0, from_cache = 0;
     double tune_ms = 0.0, best_trace_ms = 0.0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -187,6 +194,83 @@ ocr_status autotune(ocr_plan *p, hipStream_t st) {
     p->best_trace_ms = best;
     p->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return OCR_OK;
+}
+
+// Autotuner choices, kept per (device architecture, view-set shape) for the
+// life of the process and, when the environment names a file in
+// OCR_TUNE_CACHE, across processes (one line per choice: architecture,
+// shape hash, tile width and height, packing).  The shape is what the
+// trace's speed depends on: every view's size, effect, reuse parameters and
+// scene (its triangle and node counts and depth).
+std::mutex g_tune_mu;
+std::map<std::pair<std::string, uint64_t>, ocr_plan_tuning> g_tune;
+bool g_tune_loaded = false;
+
+uint64_t fnv(uint64_t h, int64_t v) {
+    for (int b = 0; b < 8; ++b) {
+        h ^= (uint64_t)(v >> (8 * b)) & 0xFFu;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+uint64_t shape_hash(const ocr_view_desc *views, int n) {
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, n);
+    for (int v = 0; v < n; ++v) {
+        const ocr_view_desc &d = views[v];
+        for (int64_t x : {(int64_t)d.gbuf.width, (int64_t)d.gbuf.height, (int64_t)d.mode,
+                          (int64_t)d.params.pattern, (int64_t)d.params.radius, (int64_t)d.params.group_n,
+                          (int64_t)d.params.estimator, d.bvh->info.ntris, d.bvh->info.nnodes,
+                          (int64_t)d.bvh->info.depth})
+            h = fnv(h, x);
+    }
+    return h;
+}
+
+std::string device_arch(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    return a.empty() ? "unknown" : a.substr(0, a.find(':'));
+}
+
+// (with g_tune_mu held)
+void load_tune_file() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("OCR_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[64];
+    uint64_t shape = 0;
+    int tw = 0, th = 0, pack = 0;
+    while (std::fscanf(f, "%63s %" SCNx64 " %d %d %d", arch, &shape, &tw, &th, &pack) == 5)
+        if (valid_tile(tw, th) && pack >= OCR_PACK_ROW && pack <= OCR_PACK_MORTON)
+            g_tune[{arch, shape}] = ocr_plan_tuning{tw, th, pack, 1};
+    std::fclose(f);
+}
+
+bool cached_tuning(const std::string &arch, uint64_t shape, ocr_plan_tuning &t) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    load_tune_file();
+    auto it = g_tune.find({arch, shape});
+    if (it == g_tune.end()) return false;
+    t = it->second;
+    return true;
+}
+
+void store_tuning(const std::string &arch, uint64_t shape, const ocr_plan_tuning &t) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    load_tune_file();
+    g_tune[{arch, shape}] = t;
+    const char *path = std::getenv("OCR_TUNE_CACHE");
+    if (!path || !*path) return;
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fprintf(f, "%s %" PRIx64 " %d %d %d\n", arch.c_str(), shape, t.tile_w, t.tile_h, t.packing);
+        std::fclose(f);
+    }
 }
 
 void free_plan(ocr_plan *p) {
@@ -350,10 +434,27 @@ ocr_status ocr_plan_create(const ocr_view_desc *views, int32_t nviews, const ocr
         return hip_fail(e, "plan upload");
     }
     if (!tuning) {
-        ocr_status s2 = autotune(p, st);
-        if (s2) {
-            free_plan(p);
-            return s2;
+        // a view set of this shape tuned before on this architecture takes
+        // its choice; otherwise time every setting and keep the fastest
+        const std::string arch = device_arch(p->device);
+        const uint64_t shape = shape_hash(views, nviews);
+        ocr_plan_tuning t;
+        if (cached_tuning(arch, shape, t)) {
+            p->tun = t;
+            p->tuned = 1;
+            p->from_cache = 1;
+            e = upload_trace_tables(p, t.tile_w, t.tile_h);
+            if (e != hipSuccess) {
+                free_plan(p);
+                return hip_fail(e, "plan upload");
+            }
+        } else {
+            ocr_status s2 = autotune(p, st);
+            if (s2) {
+                free_plan(p);
+                return s2;
+            }
+            store_tuning(arch, shape, p->tun);
         }
     }
     if (p->tun.use_graph) {
@@ -407,6 +508,7 @@ ocr_status ocr_plan_get_info(const ocr_plan *p, ocr_plan_info *info) {
     info->candidates = p->candidates;
     info->tune_ms = p->tune_ms;
     info->best_trace_ms = p->best_trace_ms;
+    info->from_cache = p->from_cache;
     return OCR_OK;
 }
 

@@ -143,6 +143,30 @@ def test_plan_autotune(ocr, mixed):
     plan.free()
 
 
+def test_plan_autotune_choice_is_kept(ocr, mixed):
+    # a second autotuned plan over views of the same shape takes the first
+    # plan's choice without timing, and computes the same bits
+    _, bvhs, views = mixed
+    log("[plan] autotune twice")
+    descs, outs = _descs(ocr, bvhs, views)
+    p1 = ocr.Plan(descs)
+    i1 = p1.info()
+    p1.launch()
+    torch.cuda.synchronize()
+    out1 = [to_np(o).copy() for o in outs]
+    p1.free()
+    p2 = ocr.Plan(descs)
+    i2 = p2.info()
+    assert i2.tuned == 1 and i2.from_cache == 1 and i2.candidates == 0
+    assert (i2.tuning.tile_w, i2.tuning.tile_h, i2.tuning.packing) == (i1.tuning.tile_w, i1.tuning.tile_h,
+                                                                      i1.tuning.packing)
+    p2.launch()
+    _check_plan(ocr, p2, views, outs, "cached tuning")
+    for o, o1 in zip(outs, out1):
+        assert np.array_equal(to_np(o).view(np.uint32), o1.view(np.uint32))
+    p2.free()
+
+
 def test_plan_graph_replays(ocr, mixed):
     # replay several times with the program's own eager work and
     # synchronisations between replays; every replay must reproduce the result
