@@ -1238,6 +1238,7 @@ typedef struct {
     int m;
     double *P;      /* m x m: P[a*m + b] = density of candidate S[b] at receiver S[a] */
     double *Ppass;
+    double *Pv;     /* a variant of P (parity support) */
     int *amb;
     idlist cand;    /* tracer scratch (light-sample reuse) */
 } target_buf;
@@ -1308,32 +1309,41 @@ static void eval_light_reuse(const reuse_ctx *c, target_buf *t, int ix, int iy, 
     *nvar = (uint8_t)nv;
 }
 
-static double combine(const reuse_ctx *c, const target_buf *t, int ia, const int *amb_idx, int namb,
-                      unsigned mask, int use_fp64, const double *cfac) {
-    /* B_i = sum_j [p_i(j) > 0 and P_i(j) > 0] p_i(j) / P_i(j),
-     * P_i(j) = sum_{k in S(i)} p_k(j)   (App. D / App. H, step 3);
-     * under the solid-angle definition each term carries the factor
-     * C_Omega(x_i, z_j) (cfac[j's index], Eq. reapp-shadow-solid-angle-estimator). */
+/* The estimate's sum (App. D / App. H, step 3):
+ *   B_i = sum_j [p_i(j) > 0 and P_i(j) > 0] C_ij p_i(j) / P_i(j),
+ *   P_i(j) = sum_{k in S(i)} p_k(j),
+ * over the set's densities Pm[a * m + b] = p_{S[a]}(z_{S[b]}) (receiver a,
+ * candidate b), i = S[ia]; C_ij = cfac[b] (the solid-angle, direct-lighting
+ * or emitter-density factor of the estimator), 1 when cfac is NULL. */
+static double mis_sum(const reuse_ctx *c, const target_buf *t, const double *Pm, int ia, const double *cfac) {
     int m = t->m;
     double B = 0.0;
     for (int b = 0; b < m; ++b) {
-        int64_t j = t->S[b];
-        if (c->hit[j] >= ORC_SELF) continue;
-        double pij = 0.0, Pj = 0.0;
-        for (int a = 0; a < m; ++a) {
-            int e = a * m + b;
-            double v = t->P[e];
-            if (!use_fp64 && t->amb[e]) {
-                v = 0.0;
-                for (int q = 0; q < namb; ++q)
-                    if (amb_idx[q] == e && ((mask >> q) & 1u)) v = t->Ppass[e];
-            }
-            Pj += v;
-            if (a == ia) pij = v;
-        }
+        if (c->hit[t->S[b]] >= ORC_SELF) continue;
+        double Pj = 0.0;
+        for (int a = 0; a < m; ++a) Pj += Pm[a * m + b];
+        double pij = Pm[ia * m + b];
         if (pij > 0.0 && Pj > 0.0) B += (cfac ? cfac[b] : 1.0) * (pij / Pj);
     }
     return B;
+}
+
+/* Parity support, not part of the estimator: the densities whose support
+ * decision lies within FP32 rounding of its threshold (t->amb) may be
+ * decided either way by an FP32 implementation.  Variant `mask` of the
+ * matrix takes, for the q-th such density, its in-support value when bit q
+ * is set and 0 otherwise. */
+static void variant_matrix(const target_buf *t, const int *amb_idx, int namb, unsigned mask, double *Pv) {
+    int m = t->m;
+    for (int e = 0; e < m * m; ++e) {
+        double v = t->P[e];
+        if (t->amb[e]) {
+            v = 0.0;
+            for (int q = 0; q < namb; ++q)
+                if (amb_idx[q] == e && ((mask >> q) & 1u)) v = t->Ppass[e];
+        }
+        Pv[e] = v;
+    }
 }
 
 static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, double *value, uint8_t *nvar,
@@ -1463,12 +1473,14 @@ static void eval_target(const reuse_ctx *c, target_buf *t, int ix, int iy, doubl
         for (int a = 0; a < m; ++a)
             if (c->hit[t->S[a]] == ORC_MISS) dark = 0;
     }
-    double B = combine(c, t, ia, amb_idx, namb, 0u, 1, cf);
+    double B = mis_sum(c, t, t->P, ia, cf);
     *value = dark ? 0.0 : (p->mode == 0 ? 1.0 - B : F - B);
+    /* admissible values of an FP32 implementation (parity support) */
     if (excluded || namb > MAX_AMBIG) return;
     int nv = 1 << namb;
     for (int v = 0; v < nv; ++v) {
-        double Bv = combine(c, t, ia, amb_idx, namb, (unsigned)v, 0, cf);
+        variant_matrix(t, amb_idx, namb, (unsigned)v, t->Pv);
+        double Bv = mis_sum(c, t, t->Pv, ia, cf);
         var[v] = dark ? 0.0 : (p->mode == 0 ? 1.0 - Bv : F - Bv);
     }
     *nvar = (uint8_t)nv;
@@ -1515,6 +1527,7 @@ void orc_reuse(const orc_scene *s, int32_t W, int32_t H, const float *pos, const
         target_buf t;
         t.P = (double *)malloc(sizeof(double) * MAXSET * MAXSET);
         t.Ppass = (double *)malloc(sizeof(double) * MAXSET * MAXSET);
+        t.Pv = (double *)malloc(sizeof(double) * MAXSET * MAXSET);
         t.amb = (int *)malloc(sizeof(int) * MAXSET * MAXSET);
         t.cand.ids = NULL;
         t.cand.n = 0;
@@ -1527,6 +1540,7 @@ void orc_reuse(const orc_scene *s, int32_t W, int32_t H, const float *pos, const
         }
         free(t.P);
         free(t.Ppass);
+        free(t.Pv);
         free(t.amb);
         free(t.cand.ids);
     }
