@@ -128,6 +128,8 @@ WORKLOADS = {
     "shadow_sa_bilinear_1080p": dict(mode="shadow_sa", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2,
                                      sample_seed=1, light_pdf=1),
     "batched_16": dict(radius=2.0, window_r=3, sample_seed=1),
+    # GROUP N = 8 reuse alone on the 1080p frame (the HBM-bound reuse variant)
+    "group8_1080p": dict(mode="ao", width=1920, height=1080, radius=2.0, window_r=3, scene_seed=2, sample_seed=1),
     "served": dict(radius=2.0, window_r=3, rate=400.0, budget_gib=4.0, slots=8),
 }
 # served scenes: the batched generator's sizes twice, seeds 100..107
@@ -239,6 +241,19 @@ def main():
         result = run_batched(args)
     elif args.workload == "served":
         result = run_served(args)
+    elif args.workload == "group8_1080p":
+        g8 = run_group8(args, {})
+        result = {"metric": "GROUP 8 reuse GB/s of algorithmic bytes at 1080p (AO and shadows)",
+                  "value": g8["ao"]["biased_gbs"], "unit": "GB/s", "n_gpus": 1, "steps": 30, "warmup": 5,
+                  "ms_per_step": g8["ao"]["biased_ms"], "higher_is_better": True, "scaling": "weak",
+                  "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                  "config": {"workload": "group8_1080p: the 1080p terrain frame, GROUP N = 8 (4x2 groups), biased "
+                                         "and unbiased, and no reuse", "global_batch": 1, "seq_len": 1920 * 1080,
+                             "parallelism": "single-gpu"},
+                  "group8_reuse": g8,
+                  "roofline": {"bound": "hbm", "achieved": g8["ao"]["biased_gbs"], "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": g8["ao"]["biased_hbm_frac"], "traffic": None,
+                               "kernel": "ocr::reuse_group_kernel<0, false, ocr::LightF>"}}
     elif args.workload == "ao_1080p" and args.extras == "on":
         result = run_all(args)
     else:
