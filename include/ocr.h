@@ -235,8 +235,8 @@ ocr_status ocr_sample_rays(const ocr_gbuffer *gbuf, int32_t mode, const ocr_rect
 
 /* Device workspace (bytes) ocr_reuse_ao / ocr_reuse_shadow need for a
  * w x h frame: the first-hit validation bits of the unbiased estimator
- * (one bit per receiver/candidate pair of a reuse set) and, for the window
- * pattern, lists of the candidate pixels (about 4 bytes per pixel); 0 for the
+ * (one bit per receiver/candidate pair of a reuse set) and lists of the
+ * candidate pixels (about 4 bytes per pixel); 0 for the
  * other estimators.  Returns 0 for invalid parameters. */
 size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params *params);
 

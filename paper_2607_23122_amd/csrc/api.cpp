@@ -347,12 +347,10 @@ size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params
         return 0;
     if (params->pattern != OCR_WINDOW && params->pattern != OCR_GROUP) return 0;
     size_t bytes = (size_t)width * (size_t)height * (size_t)pair_words(*params) * sizeof(uint32_t);
-    // window validation also keeps per-XCD candidate lists: 8 counters of one
+    // the validation also keeps per-XCD candidate lists: 8 counters of one
     // 128-byte line each, then room for every pixel of every 16x16 tile
-    if (params->pattern == OCR_WINDOW) {
-        size_t tiles = (size_t)((width + 15) / 16) * (size_t)((height + 15) / 16);
-        bytes += (8 * 32 + ((tiles + 7) / 8) * 8 * 256) * sizeof(uint32_t);
-    }
+    size_t tiles = (size_t)((width + 15) / 16) * (size_t)((height + 15) / 16);
+    bytes += (8 * 32 + ((tiles + 7) / 8) * 8 * 256) * sizeof(uint32_t);
     return bytes;
 }
 

@@ -121,9 +121,9 @@ __host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int w
     l.valid_off = lds_take(off, l.cells);
     l.miss_off = lds_take(off, l.cells);
     l.list_off = lds_take(off, 4 * sizeof(int) + sizeof(uint16_t) * l.cells);
-    // per-wave scratch: the per-candidate body's densities and box sums, or
-    // the row-task body's row sums and centre densities (64 rows of 2R + 1)
-    const int per_wave = row_body_radius(R) ? 2 * 64 * (2 * R + 1) : l.dens + l.hsum;
+    // per-wave scratch: the per-candidate body's densities and box sums (the
+    // row-task body keeps its sums in registers)
+    const int per_wave = row_body_radius(R) ? 0 : l.dens + l.hsum;
     l.wave_off = lds_take(off, sizeof(float) * (kRBlock / 64) * per_wave);
     l.total = off;
     return l;
@@ -172,17 +172,29 @@ __device__ inline CandRect cand_rect(int cx, int cy, int R) {
     return q;
 }
 
+// DPP control of the whole-wave shift that gives each lane the value of the
+// next lane (wave_shl:1).
+constexpr int kDppNextLane = 0x130;
+
+// v of lane + 1 (whole-wave DPP shift; lane 63 gets 0).
+__device__ inline float from_next_lane(float v) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kDppNextLane, 0xF, 0xF, false));
+}
+
 // Candidates of a staged tile with the row-task body (window radius R = 1..3,
 // a template parameter so that a receiver row's 4R + 1 densities stay in
 // registers).  Each wave takes a contiguous quarter of the tile's candidate
-// list in batches whose receiver rows fit in its 64 lanes.  A lane takes one
-// receiver row of one candidate j: the densities p_k(j) of the row's
-// receivers (in registers), then the row's box sums over each window of
-// 2R + 1 of them, H[t] = sum_e p(t + e) in e order, and the row's densities
-// at the target columns, both to LDS.  Then a lane takes one (candidate,
-// target) pair: P_i(j) = sum over the window's rows of H, in row order, and
-// scatters p_i(j) / P_i(j) as the per-candidate body does.  The sums run in
-// the same order as that body's, so the estimates are the same bits.
+// list in batches whose receiver rows fit in its 64 lanes, the rows of a
+// candidate on consecutive lanes.  A lane takes one receiver row of one
+// candidate j: the densities p_k(j) of the row's receivers, then the row's
+// box sums over each window of 2R + 1 of them, H[t] = sum_e p(t + e) in e
+// order, all in registers.  The lane of target row r then forms, for each
+// target column t, P_i(j) = sum over the window's rows of H, in row order,
+// from the next 2R lanes (cross-lane moves, no memory), takes p_i(j) from
+// lane r + R, and scatters p_i(j) / P_i(j) as the per-candidate body does.
+// The sums run in the same order as that body's, so the estimates are the
+// same bits.
 template <int MODE, bool UNB, class LT, int R>
 __device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *smem, const GBufView &g,
                                            const OccView &occ, float R2, const LT &L,
@@ -197,120 +209,105 @@ __device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *
     const int *s_count = reinterpret_cast<const int *>(smem + lay.list_off);
     const uint16_t *s_list = reinterpret_cast<const uint16_t *>(smem + lay.list_off + 4 * sizeof(int));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float *w_H = reinterpret_cast<float *>(smem + lay.wave_off) + wave * (2 * 64 * TW);
-    float *w_C = w_H + 64 * TW;
     const int x0 = tx * TX - R, y0 = ty * TY - R;
     const int ncand = *s_count;
     const int per = (ncand + kRBlock / 64 - 1) / (kRBlock / 64);
     int cur = min(wave * per, ncand);
     const int end = min(cur + per, ncand);
     while (cur < end) {
-        // candidate lanes: lane k holds candidate cur + k, its receiver rows
-        // and its targets; the batch is the leading candidates whose rows fit
+        // candidate lanes: lane k holds candidate cur + k and its receiver
+        // rows; the batch is the leading candidates whose rows fit
         const int ci = cur + lane;
-        int c = 0, hd = 0, nt = 0;
+        int c = 0, hd = 0;
         if (ci < end) {
             c = s_list[ci];
             const int cy = small_div(c, inv_rw), cx = c - __mul24(cy, RW);
-            const CandRect q = cand_rect(cx, cy, R);
-            hd = q.nty + 2 * R;
-            nt = __mul24(q.ntx, q.nty);
+            hd = cand_rect(cx, cy, R).nty + 2 * R;
         }
-        const int rows_inc = wave_incl_scan(hd), tg_inc = wave_incl_scan(nt);
+        const int rows_inc = wave_incl_scan(hd);
         const int nb = __popcll(wave_ballot(ci < end && rows_inc <= 64));
         const int rows_total = __builtin_amdgcn_readlane(rows_inc, nb - 1);
-        const int tg_total = __builtin_amdgcn_readlane(tg_inc, nb - 1);
-        const int rows_exc = rows_inc - hd, tg_exc = tg_inc - nt;
+        const int rows_exc = rows_inc - hd;
 
-        // (1) one receiver row per lane
-        {
-            int k = 0;
-            for (int m = 0; m < nb; ++m) k += lane >= __builtin_amdgcn_readlane(rows_inc, m) ? 1 : 0;
-            k = min(k, nb - 1);
-            const int cl = __shfl(c, k), rs = __shfl(rows_exc, k);
-            if (lane < rows_total) {
-                const int cy = small_div(cl, inv_rw), cx = cl - __mul24(cy, RW);
-                const CandRect q = cand_rect(cx, cy, R);
-                const int WD = q.ntx + 2 * R;
-                const int kx0 = q.tx0 - R, ky = q.ty0 - R + (lane - rs);
-                const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
-                const float oj[3] = {s_o[cl], s_o[CELLS + cl], s_o[2 * CELLS + cl]};
-                float dzj[3], nzj[3];
-                ld3(occ.dz, gj, dzj);
-                ld3(occ.nz, gj, nzj);
-                // unbiased: the row's validation bits, bit e for receiver kx0 + e
-                uint32_t rowbits = 0xFFFFFFFFu;
-                if (UNB) {
-                    const int qb = __mul24(ky - cy + D, SIDE) + (kx0 - cx + D);
-                    const int w0 = qb >> 5;
-                    const uint32_t lo = bits[gj * words + w0];
-                    const uint32_t hi = w0 + 1 < words ? bits[gj * words + w0 + 1] : 0u;
-                    rowbits = (uint32_t)((((unsigned long long)hi << 32) | lo) >> (qb & 31));
-                }
-                const int kcb = __mul24(ky, RW) + kx0;
-                float p[SIDE];
+        // this lane's candidate and receiver row
+        int k = 0;
+        for (int m = 0; m < nb; ++m) k += lane >= __builtin_amdgcn_readlane(rows_inc, m) ? 1 : 0;
+        k = min(k, nb - 1);
+        const int cl = __shfl(c, k), rs = __shfl(rows_exc, k);
+        const int cy = small_div(cl, inv_rw), cx = cl - __mul24(cy, RW);
+        const CandRect q = cand_rect(cx, cy, R);
+        const int row = lane - rs;
+        const bool has_row = lane < rows_total;
+        const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
+        const float oj[3] = {s_o[cl], s_o[CELLS + cl], s_o[2 * CELLS + cl]};
+        float dzj[3] = {0.f, 0.f, 0.f};
+        float p[SIDE];
 #pragma unroll
-                for (int e = 0; e < SIDE; ++e) {
-                    p[e] = 0.0f;
-                    if (e < WD && ((rowbits >> e) & 1u)) {
-                        const int kc = kcb + e;
-                        const float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
-                        const float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
-                        float w[3];
-                        rel_vec(oj, ok, dzj, w);
-                        if constexpr (MODE == OCR_AO) {
-                            p[e] = dens_ao(w, nk, nzj, R2);
-                        } else {
-                            float v[kRecvFloats<LT>];
-                            for (int a = 0; a < kRecvFloats<LT>; ++a) v[a] = s_sh[a * CELLS + kc];
-                            p[e] = dens_light(w, nk, recv_load(v, L), nzj, L);
-                        }
+        for (int e = 0; e < SIDE; ++e) p[e] = 0.0f;
+        if (has_row) {
+            const int WD = q.ntx + 2 * R;
+            const int kx0 = q.tx0 - R, ky = q.ty0 - R + row;
+            float nzj[3];
+            ld3(occ.dz, gj, dzj);
+            ld3(occ.nz, gj, nzj);
+            // unbiased: the row's validation bits, bit e for receiver kx0 + e
+            uint32_t rowbits = 0xFFFFFFFFu;
+            if (UNB) {
+                const int qb = __mul24(ky - cy + D, SIDE) + (kx0 - cx + D);
+                const int w0 = qb >> 5;
+                const uint32_t lo = bits[gj * words + w0];
+                const uint32_t hi = w0 + 1 < words ? bits[gj * words + w0 + 1] : 0u;
+                rowbits = (uint32_t)((((unsigned long long)hi << 32) | lo) >> (qb & 31));
+            }
+            const int kcb = __mul24(ky, RW) + kx0;
+#pragma unroll
+            for (int e = 0; e < SIDE; ++e) {
+                if (e < WD && ((rowbits >> e) & 1u)) {
+                    const int kc = kcb + e;
+                    const float ok[3] = {s_o[kc], s_o[CELLS + kc], s_o[2 * CELLS + kc]};
+                    const float nk[3] = {s_n[kc], s_n[CELLS + kc], s_n[2 * CELLS + kc]};
+                    float w[3];
+                    rel_vec(oj, ok, dzj, w);
+                    if constexpr (MODE == OCR_AO) {
+                        p[e] = dens_ao(w, nk, nzj, R2);
+                    } else {
+                        float v[kRecvFloats<LT>];
+                        for (int a = 0; a < kRecvFloats<LT>; ++a) v[a] = s_sh[a * CELLS + kc];
+                        p[e] = dens_light(w, nk, recv_load(v, L), nzj, L);
                     }
-                }
-#pragma unroll
-                for (int t = 0; t < TW; ++t) {
-                    float h = 0.0f;
-#pragma unroll
-                    for (int e = 0; e < TW; ++e) h += p[t + e];
-                    w_H[__mul24(lane, TW) + t] = h;
-                    w_C[__mul24(lane, TW) + t] = p[t + R];
                 }
             }
         }
-        wave_sync();
-        // (2) one (candidate, target) pair per lane
-        for (int q0 = 0; q0 < tg_total; q0 += 64) {
-            const int qq = q0 + lane;
-            int k = 0;
-            for (int m = 0; m < nb; ++m) k += qq >= __builtin_amdgcn_readlane(tg_inc, m) ? 1 : 0;
-            k = min(k, nb - 1);
-            const int cl = __shfl(c, k), rs = __shfl(rows_exc, k), ts = __shfl(tg_exc, k);
-            if (qq < tg_total) {
-                const int cy = small_div(cl, inv_rw), cx = cl - __mul24(cy, RW);
-                const CandRect q = cand_rect(cx, cy, R);
-                const int idx = qq - ts;
-                const int r2 = small_div(idx, __builtin_amdgcn_rcpf((float)q.ntx)), t2 = idx - __mul24(r2, q.ntx);
-                const float *ph = w_H + __mul24(rs + r2, TW) + t2;
-                float P = 0.0f;
+        // P_i(j) for target row `row`, column t: the box sums of rows row ..
+        // row + 2R (lanes lane .. lane + 2R, all of this candidate when row is
+        // a target row), summed in row order; p_i(j) from row + R.  Every lane
+        // takes part in the moves; the lanes of target rows scatter.
+        const bool target_row = has_row && row < q.nty;
 #pragma unroll
-                for (int e = 0; e < TW; ++e) P += ph[e * TW];
-                const float pij = w_C[__mul24(rs + r2 + R, TW) + t2];
-                if (pij > 0.0f && P > 0.0f) {
-                    float term = pij * __builtin_amdgcn_rcpf(P);
-                    if constexpr (MODE >= kShadowSA || kBilinear<LT>) {
-                        const int64_t gj = (int64_t)(y0 + cy) * g.w + (x0 + cx);
-                        const float oj[3] = {s_o[cl], s_o[CELLS + cl], s_o[2 * CELLS + cl]};
-                        float dzj[3];
-                        ld3(occ.dz, gj, dzj);
-                        term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS,
-                                                   __mul24(q.ty0 + r2, RW) + (q.tx0 + t2), oj, dzj, L);
-                    }
-                    atomicAdd(&s_B[(q.ty0 + r2 - R) * TX + (q.tx0 + t2 - R)],
-                              (unsigned long long)rintf(term * 4294967296.0f));
+        for (int t = 0; t < TW; ++t) {
+            float h = 0.0f;
+#pragma unroll
+            for (int e = 0; e < TW; ++e) h += p[t + e];
+            float P = 0.0f;
+            P += h;
+#pragma unroll
+            for (int e = 1; e < TW; ++e) {
+                h = from_next_lane(h);
+                P += h;
+            }
+            float pij = p[t + R];
+#pragma unroll
+            for (int e = 0; e < R; ++e) pij = from_next_lane(pij);
+            if (target_row && t < q.ntx && pij > 0.0f && P > 0.0f) {
+                float term = pij * __builtin_amdgcn_rcpf(P);
+                if constexpr (MODE >= kShadowSA || kBilinear<LT>) {
+                    term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS,
+                                               __mul24(q.ty0 + row, RW) + (q.tx0 + t), oj, dzj, L);
                 }
+                atomicAdd(&s_B[(q.ty0 + row - R) * TX + (q.tx0 + t - R)],
+                          (unsigned long long)rintf(term * 4294967296.0f));
             }
         }
-        wave_sync();  // the row sums are read before the next batch writes them
         cur += nb;
     }
     (void)TY;

@@ -206,9 +206,11 @@ __device__ inline bool pair_receiver(const GBufView &g, int jx, int jy, int side
 // work at block granularity.  (Measured faster than giving each XCD a
 // contiguous range, than a resident-sized grid, and than taking candidates
 // from atomic counters; run lengths 6 for the light effects and 4 for AO were
-// the fastest measured.)
+// the fastest measured, and for fixed groups 16 and 8 of the tried 6-24.)
 constexpr int kLightRun = 6;                   // candidates per run, light effects
 constexpr int kAoRun = 4;                      // candidates per run, AO
+constexpr int kGroupAoRun = 8;                 // candidates per run, fixed groups, AO
+constexpr int kGroupLightRun = 16;             // candidates per run, fixed groups, light effects
 constexpr int kRunWords = 128;                 // validation words of a run in LDS
 static_assert(kRunWords >= kMaxWords, "a run holds at least one candidate's words");
 
@@ -224,12 +226,18 @@ struct RunCand {
 // which adds the segments' useful work to stats[0..4].  Bounded to 7 waves
 // per SIMD (72 registers, some spilled): at its natural register count (5
 // waves) the walk ran 12% slower.
-template <int MODE, bool COUNT, class LT = LightF>
+//
+// GROUP: the fixed groups of N pixels (2^lgw x 2^lgh, aligned to the image
+// origin; D = the group extent).  The receivers of j are the other members of
+// its group, so an offset q is listed only when it stays in j's group; the
+// bit of pair (j, k) is the same offset bit.  A group candidate has at most
+// N - 1 segments, so runs are longer.
+template <int MODE, bool COUNT, class LT = LightF, bool GROUP = false>
 __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
                                                                  LT L, int D, int words, uint32_t *bits,
                                                                  const uint32_t *lists, uint32_t per_xcd,
-                                                                 uint64_t *stats) {
-    constexpr int kRun = MODE == OCR_AO ? kAoRun : kLightRun;
+                                                                 uint64_t *stats, int lgw, int lgh) {
+    constexpr int kRun = GROUP ? (MODE == OCR_AO ? kGroupAoRun : kGroupLightRun) : (MODE == OCR_AO ? kAoRun : kLightRun);
     __shared__ uint32_t wnode[kBlock / 64][kStackTotal];
     __shared__ unsigned long long wmask[kBlock / 64][COUNT ? kStackTotal : 1];
     // listed pairs: (place in the run << 11) | q
@@ -345,7 +353,15 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
                 int64_t k;
                 uint32_t primk;
                 float ok[3], nk[3];
-                if (q < npairs && pair_receiver(g, jx, jy, side, inv_side, D, q, k, primk, ok, nk) && k != j) {
+                bool member = q < npairs;
+                if (GROUP && member) {
+                    // k = j + (q % side - D, q / side - D) in j's group (a negative
+                    // coordinate shifts to a negative group index: never j's)
+                    const int qy = small_div(q, inv_side);
+                    const int kx = jx + (q - qy * side) - D, ky = jy + qy - D;
+                    member = (kx >> lgw) == (jx >> lgw) && (ky >> lgh) == (jy >> lgh);
+                }
+                if (member && pair_receiver(g, jx, jy, side, inv_side, D, q, k, primk, ok, nk) && k != j) {
                     float w[3];
                     rel_vec(oj, ok, dzj, w);
                     float p;
@@ -369,86 +385,6 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
         atomicAdd((unsigned long long *)&stats[2], (unsigned long long)ws.box_tests);
         atomicAdd((unsigned long long *)&stats[3], (unsigned long long)ws.tri_tests);
         atomicAdd((unsigned long long *)&stats[4], (unsigned long long)ws.segments);
-    }
-}
-
-// First-hit validation for fixed groups: one lane per (candidate m, receiver
-// k) pair of a group; block = 32 x 8 pixels, which the group shapes tile.
-// Bit (ky - my + D)(2D+1) + (kx - mx + D) of m's words, D = the group extent.
-template <int MODE, class LT = LightF>
-__global__ __launch_bounds__(kBlock) void validate_group_kernel(DeviceBVH bvh, GBufView g, OccView occ, float R2,
-                                                                LT L, int N, int gw, int gh, int D, int words,
-                                                                uint32_t *bits, int tiles_x, int ntiles) {
-    __shared__ uint32_t stack[kStackLds * kBlock];
-    __shared__ uint32_t wstack[kBlock / 64][kStackTotal];
-    __shared__ uint32_t s_words[kBlock * 2];
-    int tx, ty;
-    tile_of_block(tiles_x, ntiles, tx, ty);
-    if (ty * tiles_x + tx >= ntiles) return;  // the whole block
-    const int tid = threadIdx.x;
-    s_words[2 * tid] = 0u;
-    s_words[2 * tid + 1] = 0u;
-    __syncthreads();
-    const int side = 2 * D + 1;
-    const int ngroups = (32 / gw) * (8 / gh);
-    const int npairs = ngroups * N * N;
-    // rounds of one pair per lane (every lane runs every round, so that a
-    // wave can decide the segments whose per-lane walk overflowed together)
-    for (int base = 0; base < npairs; base += kBlock) {
-        const int P = base + tid;
-        const int grp = P / (N * N), pr = P % (N * N), m = pr / N, kk = pr % N;
-        const int gx0 = (grp % (32 / gw)) * gw, gy0 = (grp / (32 / gw)) * gh;
-        const int mlx = gx0 + m % gw, mly = gy0 + m / gw, klx = gx0 + kk % gw, kly = gy0 + kk / gw;
-        const int mx = tx * 32 + mlx, my = ty * 8 + mly, kx = tx * 32 + klx, ky = ty * 8 + kly;
-        bool pair = P < npairs && mx < g.w && my < g.h && kx < g.w && ky < g.h;
-        const int64_t j = pair ? (int64_t)my * g.w + mx : 0, k = pair ? (int64_t)ky * g.w + kx : 0;
-        const uint32_t hj = pair ? occ.hit[j] : OCR_HIT_MISS, primk = pair ? g.prim[k] : OCR_HIT_MISS;
-        pair = pair && hj < OCR_HIT_SELF && primk != OCR_HIT_MISS;
-        bool bit = false, overflow = false;
-        TRay r{};
-        if (pair && j == k) {
-            bit = true;
-        } else if (pair) {
-            float xj[3], nj[3], oj[3], dzj[3], nzj[3], xk[3], nk[3], ok[3], w[3];
-            load3(g.pos, j, xj);
-            load3(g.nrm, j, nj);
-            offset_point(xj, nj, oj);
-            load3(occ.dz, j, dzj);
-            load3(occ.nz, j, nzj);
-            load3(g.pos, k, xk);
-            load3(g.nrm, k, nk);
-            offset_point(xk, nk, ok);
-            rel_vec(oj, ok, dzj, w);
-            float p;
-            if (MODE == OCR_AO) {
-                p = dens_ao(w, nk, nzj, R2);
-            } else {
-                p = dens_light(w, nk, recv_of(ok, L), nzj, L);
-            }
-            if (p > 0.0f) {
-                make_ray(ok, w, hj, primk, 1.0f - 1e-4f, r);
-                Hit h = traverse<true, false>(bvh, r, 1.0f - 1e-4f, stack + threadIdx.x, kBlock, overflow);
-                bit = h.tri == OCR_HIT_MISS;
-            }
-        }
-        if (wave_ballot(overflow) != 0ull) {
-            const TRay rr[1] = {r};
-            const bool wr[1] = {overflow};
-            bool br[1];
-            WalkStats st;
-            traverse_wave_any<1>(bvh, rr, 1.0f - 1e-4f, wr, br, wstack[tid >> 6], st);
-            if (overflow) bit = !br[0];
-        }
-        if (bit) {
-            const int bidx = (kly - mly + D) * side + (klx - mlx + D);
-            atomicOr(&s_words[2 * (mly * 32 + mlx) + (bidx >> 5)], 1u << (bidx & 31));
-        }
-    }
-    __syncthreads();
-    const int px = tx * 32 + (tid & 31), py = ty * 8 + (tid >> 5);
-    if (px < g.w && py < g.h) {
-        const int64_t i = (int64_t)py * g.w + px;
-        for (int q = 0; q < words; ++q) bits[i * words + q] = s_words[2 * tid + q];
     }
 }
 
@@ -535,41 +471,36 @@ static hipError_t launch_validate_t(const DeviceBVH &bvh, const GBufView &g, con
                                     const LT &L, const ocr_reuse_params &p, uint32_t *bits, uint64_t *stats,
                                     hipStream_t st) {
     const int D = pair_extent(p), words = pair_words(p);
+    int tiles_x;
+    int nt = ntiles_for(g, tiles_x);
+    // the candidate lists live after the bits in the workspace; XCD x holds at most
+    // per_xcd = ceil(ntiles / 8) tiles of 256 pixels
+    uint32_t *lists = bits + (size_t)g.w * g.h * words;
+    const uint32_t per_xcd = (uint32_t)((nt + 7) / 8) * (uint32_t)kBlock;
+    hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(kBlock), 0, st, lists);
+    hipLaunchKernelGGL(compact_kernel, dim3(grid_for(nt)), dim3(kBlock), 0, st, g, occ, lists, per_xcd, tiles_x, nt);
+    // persistent grid: a multiple of 8 blocks (one share per XCD), ~32 per CU
+    dim3 grid(8192), block(kBlock);
+    int gw = 0, gh = 0;
+    if (p.pattern == OCR_GROUP) group_dims(p.group_n, gw, gh);
+    const int lgw = gw == 4 ? 2 : (gw == 2 ? 1 : 0), lgh = gh == 2 ? 1 : 0;
+#define OCR_VAL(M, C, G)                                                                                        \
+    hipLaunchKernelGGL((validate_window_kernel<M, C, LT, G>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, \
+                       bits, lists, per_xcd, stats, lgw, lgh)
+#define OCR_VAL_M(M, G)               \
+    do {                              \
+        if (stats) OCR_VAL(M, true, G); \
+        else OCR_VAL(M, false, G);      \
+    } while (0)
     if (p.pattern == OCR_WINDOW) {
-        int tiles_x;
-        int nt = ntiles_for(g, tiles_x);
-        // the candidate lists live after the bits in the workspace; XCD x holds at most
-        // per_xcd = ceil(ntiles / 8) tiles of 256 pixels
-        uint32_t *lists = bits + (size_t)g.w * g.h * words;
-        const uint32_t per_xcd = (uint32_t)((nt + 7) / 8) * (uint32_t)kBlock;
-        hipLaunchKernelGGL(clear_count_kernel, dim3(1), dim3(kBlock), 0, st, lists);
-        hipLaunchKernelGGL(compact_kernel, dim3(grid_for(nt)), dim3(kBlock), 0, st, g, occ, lists, per_xcd, tiles_x,
-                           nt);
-        // persistent grid: a multiple of 8 blocks (one share per XCD), ~32 per CU
-        dim3 grid(8192), block(kBlock);
-#define OCR_VAL(M, C)                                                                                        \
-    hipLaunchKernelGGL((validate_window_kernel<M, C, LT>), grid, block, 0, st, bvh, g, occ, R * R, L, D, words, \
-                       bits, lists, per_xcd, stats)
-        if (mode == OCR_AO) {
-            if (stats) OCR_VAL(OCR_AO, true);
-            else OCR_VAL(OCR_AO, false);
-        } else {
-            if (stats) OCR_VAL(OCR_SHADOW, true);
-            else OCR_VAL(OCR_SHADOW, false);
-        }
-#undef OCR_VAL
+        if (mode == OCR_AO) OCR_VAL_M(OCR_AO, false);
+        else OCR_VAL_M(OCR_SHADOW, false);
     } else {
-        int gw, gh;
-        group_dims(p.group_n, gw, gh);
-        int tiles_x = (g.w + 31) / 32, tiles_y = (g.h + 7) / 8, nt = tiles_x * tiles_y;
-        dim3 grid(grid_for(nt)), block(kBlock);
-        if (mode == OCR_AO)
-            hipLaunchKernelGGL((validate_group_kernel<OCR_AO, LT>), grid, block, 0, st, bvh, g, occ, R * R, L,
-                               p.group_n, gw, gh, D, words, bits, tiles_x, nt);
-        else
-            hipLaunchKernelGGL((validate_group_kernel<OCR_SHADOW, LT>), grid, block, 0, st, bvh, g, occ, R * R, L,
-                               p.group_n, gw, gh, D, words, bits, tiles_x, nt);
+        if (mode == OCR_AO) OCR_VAL_M(OCR_AO, true);
+        else OCR_VAL_M(OCR_SHADOW, true);
     }
+#undef OCR_VAL_M
+#undef OCR_VAL
     return hipGetLastError();
 }
 

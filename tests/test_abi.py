@@ -35,8 +35,10 @@ def test_workspace_bytes():
     tiles = 120 * 68
     assert ocr.workspace_bytes(1920, 1080, ocr.reuse_params("window", 3, 0, "unbiased")) == \
         1920 * 1080 * 6 * 4 + (8 * 32 + ((tiles + 7) // 8) * 8 * 256) * 4
-    # 4 x 2 groups: offsets in [-3, 3]^2 -> 49 bits -> 2 words
-    assert ocr.workspace_bytes(100, 10, ocr.reuse_params("group", 0, 8, "unbiased")) == 100 * 10 * 2 * 4
+    # 4 x 2 groups: offsets in [-3, 3]^2 -> 49 bits -> 2 words, and the same lists
+    t2 = 7 * 1
+    assert ocr.workspace_bytes(100, 10, ocr.reuse_params("group", 0, 8, "unbiased")) == \
+        100 * 10 * 2 * 4 + (8 * 32 + ((t2 + 7) // 8) * 8 * 256) * 4
     assert ocr.workspace_bytes(100, 10, ocr.reuse_params("window", 9, 0, "unbiased")) == 0
     assert ocr.workspace_bytes(0, 10, ocr.reuse_params("window", 3, 0, "unbiased")) == 0
 
