@@ -15,11 +15,13 @@ __device__ inline void load3(const float *p, int64_t i, float v[3]) {
 
 // Sample pixel (px, py), trace its ray and write its occluder record.
 // Every lane of the wave calls it (`inside` false: the lane rides along).
-// `stack` is this lane's LDS stack, `stride` apart between entries; `wstack`
-// the wave's stack of kStackTotal entries for the rays whose per-lane walk
-// overflowed its stack (decided again by a wave-coherent walk: the same
-// closest hit).  With COUNT the per-lane walks' work is added to *ws.  LT:
-// one light (LightF) or several (LightSetF, shadows).
+// AO rays take per-lane walks from the wave's entry node (wave_entry_node);
+// `stack` is this lane's LDS stack, `stride` apart between entries, and
+// `wstack` the wave's stack of kStackTotal entries for the rays whose
+// per-lane walk overflowed its stack (decided again by a wave-coherent walk:
+// the same closest hit).  Shadow rays take one wave-coherent walk.  With
+// COUNT every ray takes the per-lane walk from the root, whose work is added
+// to *ws.  LT: one light (LightF) or several (LightSetF, shadows).
 template <int MODE, bool COUNT = false, class LT = LightF>
 __device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, float R, const LT &L, uint32_t sd,
                                    uint32_t sample, const OccView &out, int px, int py, bool inside,
@@ -31,6 +33,8 @@ __device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, floa
     const float tmax = MODE == OCR_AO ? R : 1.0f;
     bool want = false;
     TRay r{};
+    // the segment's box, for the AO walks' common entry node
+    float slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
     if (prim != OCR_HIT_MISS) {
         float x[3], n[3], o[3];
         load3(g.pos, i, x);
@@ -49,14 +53,30 @@ __device__ inline void trace_pixel(const DeviceBVH &bvh, const GBufView &g, floa
             want = shadow_traced(n, o, d, Lc);
             if (!want) code = OCR_HIT_SELF;
         }
-        if (want) make_ray(o, d, prim, OCR_HIT_MISS, tmax, r);
+        if (want) {
+            make_ray(o, d, prim, OCR_HIT_MISS, tmax, r);
+            for (int c = 0; c < 3; ++c) {
+                const float e = __fmaf_rn(d[c], tmax, o[c]);
+                slo[c] = fminf(o[c], e);
+                shi[c] = fmaxf(o[c], e);
+            }
+        }
     }
     Hit h;
     h.t = tmax;
     h.tri = OCR_HIT_MISS;
     h.leaf_tri = 0;
     bool overflow = false;
-    if (want) h = traverse<false, MODE == OCR_AO, COUNT>(bvh, r, tmax, stack, stride, overflow, ws);
+    if (MODE != OCR_AO && !COUNT) {
+        // shadow segments of a wave's 8x8 pixels head for the same light and
+        // share most of their path: one wave-coherent walk (same closest hit)
+        h = traverse_wave_closest<false>(bvh, r, tmax, want, wstack);
+    } else {
+        // AO segments are short: the wave's walks start below the levels where
+        // their common box meets one child only
+        const uint32_t entry = MODE == OCR_AO && !COUNT ? wave_entry_node(bvh, slo, shi) : 0u;
+        if (want) h = traverse<false, MODE == OCR_AO, COUNT>(bvh, r, tmax, stack, stride, overflow, ws, entry);
+    }
     if (wave_ballot(overflow) != 0ull) {
         const Hit hw = traverse_wave_closest<MODE == OCR_AO>(bvh, r, tmax, overflow, wstack);
         if (overflow) h = hw;

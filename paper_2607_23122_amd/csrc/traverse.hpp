@@ -127,17 +127,18 @@ struct Hit {
 // to the smaller scene triangle index.  With COUNT the walk's work is added
 // to *ws (a separate instantiation; the result is the same).  If a push would
 // take the stack past kStackLds entries the walk stops, sets `overflow` and
-// its result is not to be used.
+// its result is not to be used.  The walk starts at `start` (the root, or a
+// node below which every triangle the ray can meet lies: wave_entry_node).
 template <bool ANY, bool INCLUSIVE, bool COUNT = false>
 __device__ inline Hit traverse(const DeviceBVH &bvh, const TRay &r, float tmax, uint32_t *lds_stack, int stride,
-                               bool &overflow, WalkStats *ws = nullptr) {
+                               bool &overflow, WalkStats *ws = nullptr, uint32_t start = 0) {
     if (COUNT) ws->walks += 1;
     Hit h;
     h.t = tmax;
     h.tri = OCR_HIT_MISS;
     h.leaf_tri = 0;
     int sp = 0;
-    uint32_t node = 0;  // root
+    uint32_t node = start;
     const float grow = 1.0f + 0x1p-20f;
     for (;;) {
         if (!(node & kLeafBit)) {
@@ -255,6 +256,56 @@ namespace ocr {
 // wave-uniform index, node and triangle fetches become scalar loads.
 typedef __attribute__((address_space(4))) const float cfloat;
 typedef __attribute__((address_space(4))) const uint32_t cuint;
+
+__device__ inline float wave_fmin(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fminf(v, __shfl_xor(v, d));
+    return v;
+}
+__device__ inline float wave_fmax(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d));
+    return v;
+}
+
+// Where a wave's walks of short segments may start (wave-uniform; every lane
+// calls it).  slo/shi: the lane's segment box (empty, +inf / -inf, for a lane
+// without a segment).  Their union, padded, is the box U; from the root the
+// descent goes on while exactly one child box of the node overlaps U and that
+// child is not a leaf.  A triangle that meets a segment holds a point of U,
+// so each of its ancestors' boxes overlaps U: at every node of the descent
+// the triangle's ancestor is the one overlapping child, and the triangle lies
+// below the node returned.  The padding (1e-4 of the coordinates and of U's
+// extent) is far above the rounding of the segment ends and of the triangle
+// test's distance.
+__device__ inline uint32_t wave_entry_node(const DeviceBVH &bvh, const float slo[3], const float shi[3]) {
+    float lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float l = wave_fmin(slo[a]), h = wave_fmax(shi[a]);
+        const float pad = 1e-4f * (fmaxf(fabsf(l), fabsf(h)) + (h - l)) + 1e-6f;
+        lo[a] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, l - pad)));
+        hi[a] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, h + pad)));
+    }
+    uint32_t node = 0;
+    if (!(lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2])) return node;  // no segment
+    for (int lev = 0; lev < kMaxDepth; ++lev) {
+        const cfloat *f = (const cfloat *)(bvh.nodes + node);
+        const cuint *c = (const cuint *)(bvh.nodes + node);
+        int n = 0;
+        uint32_t only = kEmpty;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const bool ov = c[24 + i] != kEmpty && f[i] <= hi[0] && f[4 + i] >= lo[0] && f[8 + i] <= hi[1] &&
+                            f[12 + i] >= lo[1] && f[16 + i] <= hi[2] && f[20 + i] >= lo[2];
+            n += ov ? 1 : 0;
+            only = ov ? c[24 + i] : only;
+        }
+        if (n != 1 || (only & kLeafBit)) break;
+        node = only;
+    }
+    return node;
+}
 
 // Wave-coherent any-hit traversal of up to NR segments per lane.  Every lane
 // of the wave must call it (wave-uniform control flow); slots with
