@@ -218,9 +218,10 @@ def main():
     ap.add_argument("--extras", default="on", choices=["on", "off"],
                     help="with the default workload, also measure the shadow frame, GROUP 8 reuse, the batched "
                          "plan and the served loop, each as an object of the same JSON line")
-    ap.add_argument("--primer", default="on", choices=["on", "off"],
-                    help="first run a short AO frame step in a child process (absorbs the slow first GPU "
-                         "process of a freshly started machine)")
+    ap.add_argument("--primer", default="off", choices=["on", "off"],
+                    help="first run a short AO frame step in a child process (a slow first GPU process was "
+                         "once seen on freshly started machines; not seen since the trace kernel lost its "
+                         "private stack)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (a frame would shard by image "
@@ -265,11 +266,11 @@ def main():
 def run_primer():
     """Runs a short AO frame step (two steps after a second of settle steps)
     in a child process before this process touches the GPU, and returns the
-    child's trace time.  On freshly started machines the first process that
-    used the GPU was seen to run the trace kernel about 13x slower for its
-    whole life (later processes ran normally), which the settle steps do not
-    cure; the child takes that place.  A failing child ends the bench with
-    its status: the GPU is not used again after a failure."""
+    child's trace time (--primer on).  On freshly started machines the first
+    process that used the GPU was once seen to run the trace kernel about 13x
+    slower for its whole life, while the trace kernel used private memory;
+    the child takes that place.  A failing child ends the bench with its
+    status: the GPU is not used again after a failure."""
     cmd = [sys.executable, os.path.abspath(__file__), "--workload", "ao_1080p", "--steps", "2", "--warmup", "0",
            "--settle-seconds", "1.0", "--cpu-baseline", "off", "--primer", "off", "--extras", "off",
            "--amortised-reps", "0"]
