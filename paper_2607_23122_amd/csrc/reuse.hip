@@ -45,18 +45,20 @@ __global__ __launch_bounds__(kRBlock) void reuse_window_kernel(GBufView g, OccVi
 // sums its denominator P(j) over the group's receivers once (every target of
 // a group shares it); as target i it adds p_i(j) / P(j) over the candidates.
 // The pixel's G-buffer entry, hit id and validation words are read in one
-// round of loads, the hit's record in a second.
-template <int MODE, bool UNB, class LT = LightF>
+// round of loads, the hit's record in a second.  The group shape GW x GH is
+// a template parameter: the member loops unroll and their indices are
+// constants.
+template <int MODE, bool UNB, class LT, int GW, int GH>
 __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccView occ, float R2, LT L,
-                                                              const uint32_t *__restrict__ bits, int words, int N,
-                                                              int gw, int gh, int D, int dark_guard,
-                                                              int accumulate, float *out, int tiles_x,
-                                                              int ntiles, float scale) {
-    __shared__ float s_o[3][kRBlock], s_n[3][kRBlock], s_dz[3][kRBlock], s_nz[3][kRBlock];
+                                                              const uint32_t *__restrict__ bits, int words, int D,
+                                                              int dark_guard, int accumulate, float *out,
+                                                              int tiles_x, int ntiles, float scale) {
+    constexpr int N = GW * GH, gw = GW, gh = GH;
+    __shared__ float s_o[3][kRBlock], s_dz[3][kRBlock], s_nz[3][kRBlock];
     __shared__ uint32_t s_hit[kRBlock];
     __shared__ uint8_t s_val[kRBlock];
     __shared__ uint32_t s_bits[2][UNB ? kRBlock : 1];
-    __shared__ float s_p[8][kRBlock];  // s_p[m][k]: density of the group's candidate m at receiver k
+    __shared__ float s_p[N][kRBlock];  // s_p[m][k]: density of the group's candidate m at receiver k
     __shared__ float s_P[kRBlock];     // s_P[j]: denominator of candidate j
 
     int tx, ty;
@@ -87,7 +89,6 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     else n[0] = n[1] = n[2] = 0.0f;
     for (int a = 0; a < 3; ++a) {
         s_o[a][tid] = o[a];
-        s_n[a][tid] = n[a];
     }
     if (hit < OCR_HIT_SELF) {
         float dz[3], nz[3];
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     // this lane as receiver k: densities of the group's candidates
     const int gx0 = (lx / gw) * gw, gy0 = (ly / gh) * gh;
     const int SIDE = 2 * D + 1;
+#pragma unroll
     for (int m = 0; m < N; ++m) {
         const int mx = gx0 + m % gw, my = gy0 + m / gw;
         const int jt = my * 32 + mx;
@@ -135,6 +137,7 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     if (hit < OCR_HIT_SELF) {
         const int mj = (ly - gy0) * gw + (lx - gx0);
         float P = 0.0f;
+#pragma unroll
         for (int k = 0; k < N; ++k) P += s_p[mj][(gy0 + k / gw) * 32 + gx0 + k % gw];
         s_P[tid] = P;
     }
@@ -144,6 +147,7 @@ __global__ __launch_bounds__(kRBlock) void reuse_group_kernel(GBufView g, OccVie
     if (!inside) return;
     float B = 0.0f;
     int misses = 0;
+#pragma unroll
     for (int m = 0; m < N; ++m) {
         const int mx = gx0 + m % gw, my = gy0 + m / gw;
         const int jt = my * 32 + mx;
@@ -229,13 +233,19 @@ static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, co
 template <int MODE, bool UNB, class LT>
 static void launch_grp(const GBufView &g, const OccView &occ, float R2, const LT &L, const uint32_t *bits,
                        int words, const ocr_reuse_params &p, float *out, float scale, hipStream_t st) {
-    int gw, gh;
-    group_dims(p.group_n, gw, gh);
     int tiles_x = (g.w + 31) / 32, tiles_y = (g.h + 7) / 8;
     int nt = tiles_x * tiles_y;
     dim3 grid(((nt + 7) / 8) * 8), block(kRBlock);
-    hipLaunchKernelGGL((reuse_group_kernel<MODE, UNB, LT>), grid, block, 0, st, g, occ, R2, L, bits, words, p.group_n,
-                       gw, gh, pair_extent(p), p.dark_guard, p.accumulate, out, tiles_x, nt, scale);
+#define OCR_GRP(GW, GH)                                                                                        \
+    hipLaunchKernelGGL((reuse_group_kernel<MODE, UNB, LT, GW, GH>), grid, block, 0, st, g, occ, R2, L, bits, words, \
+                       pair_extent(p), p.dark_guard, p.accumulate, out, tiles_x, nt, scale)
+    switch (p.group_n) {
+        case 8: OCR_GRP(4, 2); break;
+        case 4: OCR_GRP(2, 2); break;
+        case 2: OCR_GRP(2, 1); break;
+        default: OCR_GRP(1, 1); break;
+    }
+#undef OCR_GRP
 }
 
 template <int MODE, class LT = LightF>
