@@ -311,6 +311,10 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
             wave_sync();  // the list is read before it is refilled
         };
         for (int b = 0; b < nrun; ++b) {
+            // room for this candidate's pairs in the list (walked first,
+            // before this candidate's data is loaded, so that nothing of it
+            // lives across the walk)
+            if (count + npairs - 1 > kMaxPairs) flush(b);
             // list x and the position in it of candidate c0 + b (scalar)
             uint32_t off = c0 + (uint32_t)b, base = 8 * kCountStride;
 #pragma unroll
@@ -332,8 +336,6 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
             offset_point(xj, nj, oj);
             load3(occ.dz, j, dzj);
             load3(occ.nz, j, nzj);
-            // room for this candidate's pairs in the list
-            if (count + npairs - 1 > kMaxPairs) flush(b);
             if (lane == 0) {
                 RunCand &c = wcand[wave][b];
                 for (int a = 0; a < 3; ++a) {
