@@ -465,7 +465,7 @@ def run_frame(args, workload=None, ctx=None, cpu_seconds=None, amortised_reps=0)
         # traversal and densities are VALU-bound: price the useful operations
         # one validation per light type (single-light kernels carry LightF)
         lt = "ocr::LightSetF" if mode == "shadow2" else "ocr::LightF"
-        kname = f"ocr::validate_window_kernel<{0 if mode == 'ao' else 1}, false, {lt}>"
+        kname = f"ocr::validate_window_kernel<{0 if mode == 'ao' else 1}, false, {lt}, false>"
         traffic = measured_traffic(kname) if workload == "ao_1080p" else None
         roof = alu_roof(val_tops, traffic=traffic, kernel=kname)
     elif dominant in ("reuse_biased", "reuse_unbiased"):
