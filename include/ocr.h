@@ -247,7 +247,7 @@ size_t ocr_workspace_bytes(int32_t width, int32_t height, const ocr_reuse_params
  * from x_k.  Writes one bit per pair into workspace (layout internal; size
  * from ocr_workspace_bytes with estimator OCR_UNBIASED).  mode, ao_radius and
  * light as for the trace.  stats: NULL, or device uint64[5] to which the
- * window validation adds its useful work -- wave walks, node visits, the
+ * validation (window or groups) adds its useful work -- wave walks, node visits, the
  * box and triangle tests each segment needs on its own (a segment tests the
  * children of the nodes whose box it touches, and the triangles of the
  * leaves it reaches), and the segments traced.  With stats the validation runs a slower

@@ -287,17 +287,19 @@ def test_reuse_1080p_tiles(ocr, terrain_1080, mode, est, ntiles):
     assert (gpu[bg] == (1.0 if mode == "ao" else 0.0)).all()
 
 
-@pytest.mark.parametrize("mode,est", [("ao", "biased"), ("ao", "unbiased"), ("shadow", "biased"),
-                                      ("shadow", "unbiased")])
-def test_reuse_1080p_full_frame(ocr, terrain_1080, mode, est):
-    # the benchmark's frames (1920x1080 terrain, 7x7 window) compared with the
-    # oracle at every one of the 2,073,600 targets, in the launch
-    # configuration the benchmark times
+@pytest.mark.parametrize("mode,est,pattern,size", [("ao", "biased", "window", 3), ("ao", "unbiased", "window", 3),
+                                                   ("shadow", "biased", "window", 3),
+                                                   ("shadow", "unbiased", "window", 3),
+                                                   ("ao", "unbiased", "group", 8), ("shadow", "unbiased", "group", 8)])
+def test_reuse_1080p_full_frame(ocr, terrain_1080, mode, est, pattern, size):
+    # the benchmark's frames (1920x1080 terrain, 7x7 window, and the paper's
+    # own 8-pixel groups) compared with the oracle at every one of the
+    # 2,073,600 targets, in the launch configuration the benchmark times
     case = terrain_1080
-    log(f"[reuse 1080p full frame] {mode} window 3 {est}")
+    log(f"[reuse 1080p full frame] {mode} {pattern} {size} {est}")
     occ = _trace(ocr, case, mode, seed=1)
-    gpu = _reuse(ocr, case, mode, occ, ocr.reuse_params("window", 3, 0, est))
-    p = _oparams(case, mode, est, "window", 3, seed=1)
+    gpu = _reuse(ocr, case, mode, occ, ocr.reuse_params(pattern, size, size, est))
+    p = _oparams(case, mode, est, pattern, size, seed=1)
     rec, res = oracle.frame(case.osc, case.gb, p)
     gh = occ.hit_u32()
     hs = compare_hits(gh, rec, case.gb.valid)
@@ -439,23 +441,24 @@ def test_counted_trace_same_records(ocr, terrain_small):
         assert nodes <= boxes <= 4 * nodes and nodes >= walks and tris > 0
 
 
-def test_counted_validation_same_bits(ocr, terrain_small):
+@pytest.mark.parametrize("pattern,size,words,maxseg", [("window", 3, 6, 168), ("group", 8, 2, 7)])
+def test_counted_validation_same_bits(ocr, terrain_small, pattern, size, words, maxseg):
     # the work-accounting validation (lane-masked walk) decides every pair as the timed one does
     case = terrain_small
     for mode in ("ao", "shadow"):
-        log(f"[counted validation] {case.name} {mode}")
+        log(f"[counted validation] {case.name} {mode} {pattern} {size}")
         occ = _trace(ocr, case, mode, seed=8)
-        p = ocr.reuse_params("window", 3, 0, "unbiased")
+        p = ocr.reuse_params(pattern, size, size, "unbiased")
         lt = case.light if mode == "shadow" else None
         ws1 = ocr.validate_pairs(case.bvh, case.dg, occ, mode, case.R, lt, p)
         stats = torch.zeros(5, dtype=torch.int64, device="cuda")
         ws2 = ocr.validate_pairs(case.bvh, case.dg, occ, mode, case.R, lt, p, stats=stats)
         torch.cuda.synchronize()
-        H, W, words = case.gb.height, case.gb.width, 6
+        H, W = case.gb.height, case.gb.width
         cand = (occ.hit_u32() < oracle.SELF).ravel()
         b1 = to_np(ws1)[:H * W * words * 4].view(np.uint32).reshape(H * W, words)[cand]
         b2 = to_np(ws2)[:H * W * words * 4].view(np.uint32).reshape(H * W, words)[cand]
         assert np.array_equal(b1, b2)
         walks, nodes, boxes, tris, segs = [int(v) for v in stats.cpu().tolist()]
-        assert 0 < walks <= segs <= 168 * int(cand.sum())
+        assert 0 < walks <= segs <= maxseg * int(cand.sum())
         assert 0 < boxes <= 4 * 64 * nodes and tris > 0
