@@ -243,6 +243,10 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
                                                                  const uint32_t *lists, uint32_t per_xcd,
                                                                  uint64_t *stats, int lgw, int lgh) {
     constexpr int kRun = GROUP ? (MODE == OCR_AO ? kGroupAoRun : kGroupLightRun) : (MODE == OCR_AO ? kAoRun : kLightRun);
+    // AO window runs (about 120 segments per candidate) start their walks at
+    // the run's entry node; shadow candidates have a segment or two, and
+    // groups at most N - 1, too few to pay for the per-candidate reductions
+    constexpr bool kEntry = MODE == OCR_AO && !GROUP && !COUNT;
     __shared__ uint32_t wnode[kBlock / 64][kStackTotal];
     __shared__ unsigned long long wmask[kBlock / 64][COUNT ? kStackTotal : 1];
     // listed pairs: (place in the run << 11) | q
@@ -280,10 +284,20 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
         for (int w = lane; w < nrun * words; w += 64) wbits[wave][w] = 0u;
         wave_sync();
         int count = 0, done = 0;  // listed pairs; candidates whose words are written
+        // the box of the listed segments (wave-uniform), for the walks'
+        // common entry node
+        float slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
         // Walk the listed pairs (each lane its own segment), then write the
         // words of the candidates gathered so far.
         auto flush = [&](int upto) {
             wave_sync();
+            // the listed segments of a run lie close together: their walks
+            // start below the levels where their box meets one child only
+            const uint32_t entry = kEntry ? entry_node(bvh, slo, shi) : 0u;
+            for (int a = 0; a < 3; ++a) {
+                slo[a] = INFINITY;
+                shi[a] = -INFINITY;
+            }
             for (int e0 = 0; e0 < count; e0 += 64) {
                 TRay r;
                 r.ign0 = r.ign1 = OCR_HIT_MISS;
@@ -309,7 +323,7 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
                     TRay rr[1] = {r};
                     const bool wr[1] = {want};
                     bool br[1];
-                    traverse_wave_any<1>(bvh, rr, 1.0f - 1e-4f, wr, br, wnode[wave], ws);
+                    traverse_wave_any<1>(bvh, rr, 1.0f - 1e-4f, wr, br, wnode[wave], ws, entry);
                     blocked = br[0];
                 }
                 if (want && !blocked) atomicOr(&wbits[wave][b * words + (q >> 5)], 1u << (q & 31));
@@ -350,6 +364,9 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
             offset_point(xj, nj, oj);
             load3(occ.dz, j, dzj);
             load3(occ.nz, j, nzj);
+            // this candidate's segments: z_j = o_j + dz_j and this lane's receivers
+            float clo[3], chi[3];
+            for (int a = 0; a < 3; ++a) clo[a] = chi[a] = oj[a] + dzj[a];
             if (lane == 0) {
                 RunCand &c = wcand[wave][b];
                 for (int a = 0; a < 3; ++a) {
@@ -387,10 +404,23 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
                         p = dens_light(w, nk, recv_of(ok, L), nzj, L);
                     }
                     want = p > 0.0f;
+                    if (want && kEntry) {
+                        for (int a = 0; a < 3; ++a) {
+                            clo[a] = fminf(clo[a], ok[a]);
+                            chi[a] = fmaxf(chi[a], ok[a]);
+                        }
+                    }
                 }
                 const unsigned long long m = __ballot(want);
                 if (want) wq[wave][count + __popcll(m & below)] = (uint16_t)((b << 11) | q);
                 count += __popcll(m);
+            }
+            if (kEntry) {
+                // into the run's box (wave-uniform: scalar registers)
+                for (int a = 0; a < 3; ++a) {
+                    slo[a] = uniform_f(fminf(slo[a], wave_fmin(clo[a])));
+                    shi[a] = uniform_f(fmaxf(shi[a], wave_fmax(chi[a])));
+                }
             }
         }
         flush(nrun);

@@ -268,24 +268,27 @@ __device__ inline float wave_fmax(float v) {
     return v;
 }
 
-// Where a wave's walks of short segments may start (wave-uniform; every lane
-// calls it).  slo/shi: the lane's segment box (empty, +inf / -inf, for a lane
-// without a segment).  Their union, padded, is the box U; from the root the
-// descent goes on while exactly one child box of the node overlaps U and that
-// child is not a leaf.  A triangle that meets a segment holds a point of U,
-// so each of its ancestors' boxes overlaps U: at every node of the descent
-// the triangle's ancestor is the one overlapping child, and the triangle lies
-// below the node returned.  The padding (1e-4 of the coordinates and of U's
-// extent) is far above the rounding of the segment ends and of the triangle
-// test's distance.
-__device__ inline uint32_t wave_entry_node(const DeviceBVH &bvh, const float slo[3], const float shi[3]) {
+// A value the wave holds in every lane, as a scalar.
+__device__ inline float uniform_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+// Where walks of segments inside the wave-uniform box [ulo, uhi] may start.
+// The box, padded, is U; from the root the descent goes on while exactly one
+// child box of the node overlaps U and that child is not a leaf.  A triangle
+// that meets a segment holds a point of U, so each of its ancestors' boxes
+// overlaps U: at every node of the descent the triangle's ancestor is the one
+// overlapping child, and the triangle lies below the node returned.  The
+// padding (1e-4 of the coordinates and of U's extent) is far above the
+// rounding of the segment ends and of the triangle test's distance.
+__device__ inline uint32_t entry_node(const DeviceBVH &bvh, const float ulo[3], const float uhi[3]) {
     float lo[3], hi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float l = wave_fmin(slo[a]), h = wave_fmax(shi[a]);
+        const float l = ulo[a], h = uhi[a];
         const float pad = 1e-4f * (fmaxf(fabsf(l), fabsf(h)) + (h - l)) + 1e-6f;
-        lo[a] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, l - pad)));
-        hi[a] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, h + pad)));
+        lo[a] = uniform_f(l - pad);
+        hi[a] = uniform_f(h + pad);
     }
     uint32_t node = 0;
     if (!(lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2])) return node;  // no segment
@@ -307,6 +310,18 @@ __device__ inline uint32_t wave_entry_node(const DeviceBVH &bvh, const float slo
     return node;
 }
 
+// The same for the union of the lanes' segment boxes slo/shi (empty, +inf /
+// -inf, for a lane without a segment); every lane calls it.
+__device__ inline uint32_t wave_entry_node(const DeviceBVH &bvh, const float slo[3], const float shi[3]) {
+    float lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = uniform_f(wave_fmin(slo[a]));
+        hi[a] = uniform_f(wave_fmax(shi[a]));
+    }
+    return entry_node(bvh, lo, hi);
+}
+
 // Wave-coherent any-hit traversal of up to NR segments per lane.  Every lane
 // of the wave must call it (wave-uniform control flow); slots with
 // want[q] == false only ride along.  The wave walks one node order -- the
@@ -321,7 +336,7 @@ __device__ inline uint32_t wave_entry_node(const DeviceBVH &bvh, const float slo
 template <int NR>
 __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[NR], float tmax,
                                          const bool (&want)[NR], bool (&blocked)[NR], uint32_t *wstack,
-                                         WalkStats &st) {
+                                         WalkStats &st, uint32_t start = 0) {
     bool active[NR];
     // the active lanes of each segment set as a wave-uniform mask, kept in
     // step with active[] (box-test ballots are masked with it)
@@ -338,7 +353,7 @@ __device__ inline void traverse_wave_any(const DeviceBVH &bvh, const TRay (&r)[N
     st.walks += 1;
     const float grow = 1.0f + 0x1p-20f;
     int sp = 0;
-    uint32_t node = 0;
+    uint32_t node = start;  // the root, or a wave_entry_node of the segments
     for (;;) {
         if (!(node & kLeafBit)) {
             {
