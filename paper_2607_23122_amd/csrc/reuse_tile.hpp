@@ -97,15 +97,15 @@ struct WinLayout {
     size_t o_off, n_off, sh_off, valid_off, miss_off, list_off, B_off, wave_off, total;
 };
 
-__host__ __device__ inline size_t lds_take(size_t &off, size_t bytes) {
+__host__ __device__ constexpr size_t lds_take(size_t &off, size_t bytes) {
     size_t at = off;
     off += (bytes + 15) & ~(size_t)15;
     return at;
 }
 
 // nrecv: floats of a receiver's light terms (kRecvFloats of the light type).
-__host__ __device__ inline WinLayout win_layout(int R, int mode, bool unb, int words, int nrecv = 3) {
-    WinLayout l;
+__host__ __device__ constexpr WinLayout win_layout(int R, int mode, bool unb, int words, int nrecv = 3) {
+    WinLayout l{};
     l.RWX = kWTX + 2 * R;
     l.RWY = kWTY + 2 * R;
     l.cells = l.RWX * l.RWY;
@@ -176,10 +176,10 @@ __device__ inline CandRect cand_rect(int cx, int cy, int R) {
 // next lane (wave_shl:1).
 constexpr int kDppNextLane = 0x130;
 
-// v of lane + 1 (whole-wave DPP shift; lane 63 gets 0).
+// v of lane + 1 (whole-wave DPP shift; lane 63, which has no source lane,
+// gets 0 through bound_ctrl, so no zeroed destination is needed).
 __device__ inline float from_next_lane(float v) {
-    return __builtin_bit_cast(float,
-                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kDppNextLane, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kDppNextLane, 0xF, 0xF, true));
 }
 
 // Candidates of a staged tile with the row-task body (window radius R = 1..3,
@@ -200,12 +200,19 @@ __device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *
                                            const OccView &occ, float R2, const LT &L,
                                            const uint32_t *__restrict__ bits, int words, int tx, int ty) {
     constexpr int TW = 2 * R + 1, SIDE = 4 * R + 1, D = 2 * R;
-    const int TX = kWTX, TY = kWTY, RW = lay.RWX, CELLS = lay.cells;
+    constexpr int TX = kWTX, TY = kWTY, RW = kWTX + 2 * R, CELLS = RW * (kWTY + 2 * R);
+    // The staged normals and light terms follow the positions directly
+    // (3 * CELLS floats each, a multiple of 16 bytes), so all the receiver
+    // values a density reads sit at constant offsets from one LDS address.
+    constexpr WinLayout kLay = win_layout(R, MODE, UNB, 1, kRecvFloats<LT>);
+    static_assert(kLay.cells == CELLS && kLay.n_off == kLay.o_off + 3 * CELLS * sizeof(float) &&
+                      (MODE == OCR_AO || kLay.sh_off == kLay.n_off + 3 * CELLS * sizeof(float)),
+                  "receiver arrays are contiguous");
     const float inv_rw = 1.0f / (float)RW;
     unsigned long long *s_B = reinterpret_cast<unsigned long long *>(smem + lay.B_off);
     const float *s_o = reinterpret_cast<const float *>(smem + lay.o_off);
-    const float *s_n = reinterpret_cast<const float *>(smem + lay.n_off);
-    const float *s_sh = reinterpret_cast<const float *>(smem + lay.sh_off);
+    const float *s_n = s_o + 3 * CELLS;
+    const float *s_sh = s_n + 3 * CELLS;
     const int *s_count = reinterpret_cast<const int *>(smem + lay.list_off);
     const uint16_t *s_list = reinterpret_cast<const uint16_t *>(smem + lay.list_off + 4 * sizeof(int));
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -285,11 +292,12 @@ __device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *
         const bool target_row = has_row && row < q.nty;
 #pragma unroll
         for (int t = 0; t < TW; ++t) {
-            float h = 0.0f;
+            // (the sums start from their first term rather than from 0: the
+            // same values, since no density is -0)
+            float h = p[t];
 #pragma unroll
-            for (int e = 0; e < TW; ++e) h += p[t + e];
-            float P = 0.0f;
-            P += h;
+            for (int e = 1; e < TW; ++e) h += p[t + e];
+            float P = h;
 #pragma unroll
             for (int e = 1; e < TW; ++e) {
                 h = from_next_lane(h);
