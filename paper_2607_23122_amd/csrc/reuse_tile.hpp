@@ -173,13 +173,14 @@ __device__ inline CandRect cand_rect(int cx, int cy, int R) {
 }
 
 // DPP control of the whole-wave shift that gives each lane the value of the
-// next lane (wave_shl:1).
-constexpr int kDppNextLane = 0x130;
+// previous lane (wave_shr:1).
+constexpr int kDppPrevLane = 0x138;
 
-// v of lane + 1 (whole-wave DPP shift; lane 63, which has no source lane,
-// gets 0 through bound_ctrl, so no zeroed destination is needed).
-__device__ inline float from_next_lane(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kDppNextLane, 0xF, 0xF, true));
+// v of lane - 1 (whole-wave DPP shift; lane 0, which has no source lane, gets
+// 0 through bound_ctrl).  With full row and bank masks and bound_ctrl set, the
+// compiler folds the move into the instruction that uses it.
+__device__ inline float from_prev_lane(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kDppPrevLane, 0xF, 0xF, true));
 }
 
 // Candidates of a staged tile with the row-task body (window radius R = 1..3,
@@ -189,10 +190,11 @@ __device__ inline float from_next_lane(float v) {
 // candidate on consecutive lanes.  A lane takes one receiver row of one
 // candidate j: the densities p_k(j) of the row's receivers, then the row's
 // box sums over each window of 2R + 1 of them, H[t] = sum_e p(t + e) in e
-// order, all in registers.  The lane of target row r then forms, for each
-// target column t, P_i(j) = sum over the window's rows of H, in row order,
-// from the next 2R lanes (cross-lane moves, no memory), takes p_i(j) from
-// lane r + R, and scatters p_i(j) / P_i(j) as the per-candidate body does.
+// order, all in registers.  For each target column t, the window sums over
+// rows, P_i(j) = sum of H over the 2R + 1 rows of target row r's window in
+// row order, are folded through the lanes by cross-lane moves (no memory) and
+// end on the lane of the window's last row, r + 2R, which takes p_i(j) from
+// lane r + R and scatters p_i(j) / P_i(j) as the per-candidate body does.
 // The sums run in the same order as that body's, so the estimates are the
 // same bits.
 template <int MODE, bool UNB, class LT, int R>
@@ -285,11 +287,16 @@ __device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *
                 }
             }
         }
-        // P_i(j) for target row `row`, column t: the box sums of rows row ..
-        // row + 2R (lanes lane .. lane + 2R, all of this candidate when row is
-        // a target row), summed in row order; p_i(j) from row + R.  Every lane
-        // takes part in the moves; the lanes of target rows scatter.
-        const bool target_row = has_row && row < q.nty;
+        // P_i(j) for target row tr = row - 2R, column t: the box sums of rows
+        // tr .. row (lanes lane - 2R .. lane, all of this candidate when
+        // row >= 2R), summed in row order.  The fold runs upwards through the
+        // lanes, G_e(lane) = G_(e-1)(lane - 1) + H(lane), so that after 2R
+        // steps the lane of row `row` holds the window that ends at it, and
+        // each step is one add with a shifted operand; p_i(j) comes from row
+        // tr + R.  Every lane takes part in the moves; the lanes of rows
+        // 2R .. 2R + nty - 1 scatter for the candidate's nty target rows.
+        const int tr = row - D;
+        const bool target_row = has_row && tr >= 0;
 #pragma unroll
         for (int t = 0; t < TW; ++t) {
             // (the sums start from their first term rather than from 0: the
@@ -299,20 +306,17 @@ __device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *
             for (int e = 1; e < TW; ++e) h += p[t + e];
             float P = h;
 #pragma unroll
-            for (int e = 1; e < TW; ++e) {
-                h = from_next_lane(h);
-                P += h;
-            }
+            for (int e = 1; e < TW; ++e) P = from_prev_lane(P) + h;
             float pij = p[t + R];
 #pragma unroll
-            for (int e = 0; e < R; ++e) pij = from_next_lane(pij);
+            for (int e = 0; e < R; ++e) pij = from_prev_lane(pij);
             if (target_row && t < q.ntx && pij > 0.0f && P > 0.0f) {
                 float term = pij * __builtin_amdgcn_rcpf(P);
                 if constexpr (MODE >= kShadowSA || kBilinear<LT>) {
                     term = weighted_term<MODE>(term, s_o, s_n, s_sh, CELLS,
-                                               __mul24(q.ty0 + row, RW) + (q.tx0 + t), oj, dzj, L);
+                                               __mul24(q.ty0 + tr, RW) + (q.tx0 + t), oj, dzj, L);
                 }
-                atomicAdd(&s_B[(q.ty0 + row - R) * TX + (q.tx0 + t - R)],
+                atomicAdd(&s_B[(q.ty0 + tr - R) * TX + (q.tx0 + t - R)],
                           (unsigned long long)rintf(term * 4294967296.0f));
             }
         }
