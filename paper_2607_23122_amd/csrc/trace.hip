@@ -228,21 +228,23 @@ __device__ inline bool pair_receiver(const GBufView &g, int jx, int jy, int side
 // BVH; an AO candidate has dozens, and short runs only fill its last, partly
 // empty walk.  The list is walked early when the next candidate might not
 // fit.  An oversubscribed grid (8192 blocks) strides through the concatenated
-// candidate lists (tile order) in blocks of 64 runs dealt to the XCDs in turn:
-// an XCD works on a few small parts of the frame at a time, so its L2 holds
-// the part of the hierarchy their segments meet (1080p AO: 0.55 GB fetched
-// per launch instead of 1.5 GB), while every XCD still samples the whole
-// frame and the dispatcher balances the uneven per-run work at block
+// candidate lists (tile order) in blocks of kRunBlock runs dealt to the XCDs
+// in turn: an XCD works on a few small parts of the frame at a time, so its
+// L2 holds the part of the hierarchy their segments meet (1080p AO: 0.55 GB
+// fetched per launch instead of 1.5 GB), while every XCD still samples the
+// whole frame and the dispatcher balances the uneven per-run work at block
 // granularity.  (Measured faster than one contiguous eighth of the runs per
 // XCD, which fetched 0.25 GB but left XCDs idle at the end, than a
-// resident-sized grid, and than taking runs from atomic counters; run lengths
-// 6 for the light effects and 4 for AO were the fastest measured, and for
-// fixed groups 16 and 8 of the tried 6-24.)
+// resident-sized grid, and than taking runs from atomic counters; blocks of
+// 256 runs were the fastest of 16-1024; run lengths 6 for the light effects
+// and 4 for AO were the fastest measured, and for fixed groups 16 and 8 of
+// the tried 6-24.)
 constexpr int kLightRun = 6;                   // candidates per run, light effects
 constexpr int kAoRun = 4;                      // candidates per run, AO
 constexpr int kGroupAoRun = 8;                 // candidates per run, fixed groups, AO
 constexpr int kGroupLightRun = 16;             // candidates per run, fixed groups, light effects
 constexpr int kRunWords = 128;                 // validation words of a run in LDS
+constexpr uint32_t kRunBlock = 256;            // consecutive runs an XCD takes at a time
 static_assert(kRunWords >= kMaxWords, "a run holds at least one candidate's words");
 
 // A candidate of the current run, as its walks need it.
@@ -294,15 +296,15 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
     uint32_t total = 0;
 #pragma unroll
     for (int x = 0; x < 8; ++x) total += lists[x * kCountStride];
-    // runs in blocks of 64; XCD x (blocks x, x + 8, ...) takes run blocks x,
+    // runs in blocks of kRunBlock; XCD x (blocks x, x + 8, ...) takes run blocks x,
     // x + 8, ...
     const uint32_t nruns = (total + (uint32_t)run - 1) / (uint32_t)run;
     const uint32_t xcd = blockIdx.x & 7;
     const uint32_t stride = (gridDim.x / 8) * (kBlock / 64);
     for (uint32_t u = (blockIdx.x >> 3) * (kBlock / 64) + wave;; u += stride) {
-        const uint32_t ri = (u / 64u) * (8u * 64u) + xcd * 64u + (u % 64u);
+        const uint32_t ri = (u / kRunBlock) * (8u * kRunBlock) + xcd * kRunBlock + (u % kRunBlock);
         if (ri >= nruns) {
-            if ((u / 64u) * (8u * 64u) >= nruns) break;
+            if ((u / kRunBlock) * (8u * kRunBlock) >= nruns) break;
             continue;
         }
         const uint32_t c0 = ri * (uint32_t)run;
