@@ -18,13 +18,27 @@
 
 namespace ocr {
 
+// Blocks are dealt to the 8 XCDs round-robin; XCD x takes runs x, x + 8, ...
+// of kRTileRun consecutive tiles (row-major), so that every XCD samples the
+// whole frame and they finish together.  (One contiguous band of tiles per
+// XCD left XCDs idle at the end: 1080p window-3 reuse AO 0.143 -> 0.133 ms,
+// shadows 0.334 -> 0.281 ms, GROUP 8 AO 24.5 -> 22.4 us with runs of 8, of
+// 8-64 tiles and the plain block order; identical bits.)
+constexpr int kRTileRun = 8;
+
 __device__ inline void r_tile_of_block(int tiles_x, int ntiles, int &tx, int &ty) {
-    int b = blockIdx.x;
-    int per = (ntiles + 7) / 8;
-    int t = (b & 7) * per + (b >> 3);
-    if (t >= ntiles) t = ntiles;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, local = b >> 3;
+    int t = (local / kRTileRun) * (8 * kRTileRun) + xcd * kRTileRun + local % kRTileRun;
+    if (t >= ntiles) t = ntiles;  // out of range -> the block exits
     tx = t % tiles_x;
     ty = t / tiles_x;
+}
+
+// Blocks for r_tile_of_block: every tile has one.
+static inline int r_grid_for(int ntiles) {
+    const int per = (ntiles + 7) / 8;
+    return 8 * ((per + kRTileRun - 1) / kRTileRun) * kRTileRun;
 }
 
 template <int MODE, bool UNB, class LT = LightF>
@@ -224,7 +238,7 @@ static hipError_t launch_win(const GBufView &g, const OccView &occ, float R2, co
         while (cur < lay.total && !attr_bytes.compare_exchange_weak(cur, lay.total)) {
         }
     }
-    dim3 grid(((nt + 7) / 8) * 8), block(kRBlock);
+    dim3 grid(r_grid_for(nt)), block(kRBlock);
     hipLaunchKernelGGL((reuse_window_kernel<MODE, UNB, LT>), grid, block, lay.total, st, g, occ, R2, L, bits, words,
                        p.radius, p.dark_guard, p.accumulate, out, tiles_x, nt, scale);
     return hipSuccess;
@@ -235,7 +249,7 @@ static void launch_grp(const GBufView &g, const OccView &occ, float R2, const LT
                        int words, const ocr_reuse_params &p, float *out, float scale, hipStream_t st) {
     int tiles_x = (g.w + 31) / 32, tiles_y = (g.h + 7) / 8;
     int nt = tiles_x * tiles_y;
-    dim3 grid(((nt + 7) / 8) * 8), block(kRBlock);
+    dim3 grid(r_grid_for(nt)), block(kRBlock);
 #define OCR_GRP(GW, GH)                                                                                        \
     hipLaunchKernelGGL((reuse_group_kernel<MODE, UNB, LT, GW, GH>), grid, block, 0, st, g, occ, R2, L, bits, words, \
                        pair_extent(p), p.dark_guard, p.accumulate, out, tiles_x, nt, scale)

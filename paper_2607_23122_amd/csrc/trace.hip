@@ -10,14 +10,19 @@ namespace ocr {
 constexpr int kBlock = 256;
 constexpr int kTile = 16;  // 16 x 16 pixels per block, one 8 x 8 sub-tile per wave
 
-// Blocks are dealt to the 8 XCDs round-robin; remap so that each XCD walks a
-// contiguous band of tiles, keeping the BVH paths a band touches in that
-// XCD's L2.
+// Blocks are dealt to the 8 XCDs round-robin; remap so that each XCD takes
+// runs of kTileRun consecutive tiles (row-major) in turn: XCD x gets tile
+// runs x, x + 8, ...  A run's rays share much of their BVH paths in that
+// XCD's L2, and every XCD samples the whole frame, so the XCDs finish
+// together.  (One contiguous band of tiles per XCD left XCDs idle at the end:
+// 1080p trace AO 0.385 -> 0.344 ms and shadows 0.43 -> 0.32 ms with runs of 16,
+// the fastest of 8-64 tiles and of the plain block order; identical records.)
+constexpr int kTileRun = 16;
+
 __device__ inline void tile_of_block(int tiles_x, int ntiles, int &tx, int &ty) {
-    int b = blockIdx.x;
-    int per = (ntiles + 7) / 8;
-    int xcd = b & 7, local = b >> 3;
-    int t = xcd * per + local;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, local = b >> 3;
+    int t = (local / kTileRun) * (8 * kTileRun) + xcd * kTileRun + local % kTileRun;
     if (t >= ntiles) t = ntiles;  // out of range -> caller exits
     tx = t % tiles_x;
     ty = t / tiles_x;
@@ -126,8 +131,8 @@ __global__ __launch_bounds__(kBlock) void trace_count_kernel(DeviceBVH bvh, GBuf
 
 // Candidate lists for the window validation: every pixel whose ray found an
 // occluder.  One list per XCD (blocks are dealt to the XCDs round-robin):
-// XCD x compacts the same contiguous band of tiles that tile_of_block gives
-// it, a block kCompactTiles consecutive tiles of the band, appending their
+// XCD x compacts a contiguous band of ceil(ntiles / 8) tiles, a block
+// kCompactTiles consecutive tiles of the band, appending their
 // candidates (tile by tile, in pixel order within a wave) to list x with a
 // single atomic, and the validation blocks of XCD x consume list x, so each
 // XCD's L2 sees one contiguous set of tiles.  (The appends to one counter
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(GBufView g, OccView occ
     unsigned long long m[kCompactTiles];
 #pragma unroll
     for (int i = 0; i < kCompactTiles; ++i) {
-        // this block's i-th tile of XCD xcd's band (the band as in tile_of_block)
+        // this block's i-th tile of XCD xcd's band
         const int t = (int)xcd * per + (int)(blockIdx.x >> 3) * kCompactTiles + i;
         bool cand = false;
         jj[i] = 0;
@@ -511,7 +516,12 @@ static inline int ntiles_for(const GBufView &g, int &tiles_x) {
     return tiles_x * tiles_y;
 }
 
-static inline int grid_for(int ntiles) { return ((ntiles + 7) / 8) * 8; }
+// Blocks for tile_of_block: 8 XCDs x whole runs of kTileRun tiles covering
+// ceil(ntiles / 8) tiles each, so every tile has a block.
+static inline int grid_for(int ntiles) {
+    const int per = (ntiles + 7) / 8;
+    return 8 * ((per + kTileRun - 1) / kTileRun) * kTileRun;
+}
 
 hipError_t launch_trace(const DeviceBVH &bvh, const GBufView &g, int mode, float R, const LightF &L, uint32_t seed32,
                         uint32_t sample, const OccView &out, hipStream_t st) {
