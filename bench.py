@@ -211,8 +211,9 @@ def main():
     ap.add_argument("--served-poses", type=int, default=2, help="camera poses per scene and resolution (served)")
     ap.add_argument("--served-baseline", default="on", choices=["on", "off"],
                     help="also run the one-slot FIFO server on the same arrivals")
-    ap.add_argument("--served-rates", type=lambda v: [float(x) for x in v.split(",") if x], default=[1800.0],
-                    help="further offered loads (requests/s), served and FIFO on the same arrivals")
+    ap.add_argument("--served-rates", type=lambda v: [float(x) for x in v.split(",") if x], default=None,
+                    help="further offered loads (requests/s), served and FIFO on the same arrivals; default: "
+                         "midway between the two servers' measured capacities")
     ap.add_argument("--amortised-reps", type=int, default=3,
                     help="repetitions of 200 accumulated samples for the amortised per-sample times (0: off)")
     ap.add_argument("--extras", default="on", choices=["on", "off"],
@@ -906,7 +907,13 @@ def run_served(args):
     # offered loads above the one-slot FIFO's capacity (and below the 8-slot
     # server's), where completed frames/s can differ between the two
     loads = {}
-    for hi_rate in args.served_rates:
+    rates = args.served_rates
+    if rates is None:
+        # midway between the FIFO's and the slotted server's capacity (rounded
+        # to 100/s), where the completed frames/s of the two can differ
+        rates = ([round(0.5 * (capacity[f"slots_{cfg['slots']}"] + capacity["fifo_one_slot"]), -2)]
+                 if "fifo_one_slot" in capacity else [])
+    for hi_rate in rates:
         arr2, pk2 = trace_of(hi_rate)
         srv8 = serve(cfg["slots"], arr2, pk2)
         fifo = serve(1, arr2, pk2) if args.served_baseline == "on" else None
