@@ -185,9 +185,11 @@ __device__ inline float from_prev_lane(float v) {
 
 // Candidates of a staged tile with the row-task body (window radius R = 1..3,
 // a template parameter so that a receiver row's 4R + 1 densities stay in
-// registers).  Each wave takes a contiguous quarter of the tile's candidate
-// list in batches whose receiver rows fit in its 64 lanes, the rows of a
-// candidate on consecutive lanes.  A lane takes one receiver row of one
+// registers).  The waves of the block claim batches of consecutive entries of
+// the tile's candidate list in turn from one shared cursor (a compare-and-swap
+// in LDS), a batch being the leading candidates whose receiver rows fit in 64
+// lanes, the rows of a candidate on consecutive lanes; so only the tile's last
+// batch is partly empty, not one per wave.  A lane takes one receiver row of one
 // candidate j: the densities p_k(j) of the row's receivers, then the row's
 // box sums over each window of 2R + 1 of them, H[t] = sum_e p(t + e) in e
 // order, all in registers.  For each target column t, the window sums over
@@ -215,15 +217,16 @@ __device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *
     const float *s_o = reinterpret_cast<const float *>(smem + lay.o_off);
     const float *s_n = s_o + 3 * CELLS;
     const float *s_sh = s_n + 3 * CELLS;
-    const int *s_count = reinterpret_cast<const int *>(smem + lay.list_off);
+    int *s_count = reinterpret_cast<int *>(smem + lay.list_off);
     const uint16_t *s_list = reinterpret_cast<const uint16_t *>(smem + lay.list_off + 4 * sizeof(int));
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
     const int x0 = tx * TX - R, y0 = ty * TY - R;
-    const int ncand = *s_count;
-    const int per = (ncand + kRBlock / 64 - 1) / (kRBlock / 64);
-    int cur = min(wave * per, ncand);
-    const int end = min(cur + per, ncand);
-    while (cur < end) {
+    // s_count[0]: candidates listed; s_count[1]: the shared cursor (entries
+    // claimed), zero at the tile's start
+    const int end = s_count[0];
+    for (;;) {
+        const int cur = __builtin_amdgcn_readfirstlane(__atomic_load_n(&s_count[1], __ATOMIC_RELAXED));
+        if (cur >= end) break;
         // candidate lanes: lane k holds candidate cur + k and its receiver
         // rows; the batch is the leading candidates whose rows fit
         const int ci = cur + lane;
@@ -237,6 +240,11 @@ __device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *
         const int nb = __popcll(wave_ballot(ci < end && rows_inc <= 64));
         const int rows_total = __builtin_amdgcn_readlane(rows_inc, nb - 1);
         const int rows_exc = rows_inc - hd;
+        // claim the batch; if another wave moved the cursor first, form the
+        // next batch from where it now stands (some wave succeeds each round)
+        int won = 0;
+        if (lane == 0) won = atomicCAS(&s_count[1], cur, cur + nb) == cur;
+        if (!__builtin_amdgcn_readfirstlane(won)) continue;
 
         // this lane's candidate and receiver row
         int k = 0;
@@ -320,7 +328,6 @@ __device__ inline void tile_row_candidates(const WinLayout &lay, unsigned char *
                           (unsigned long long)rintf(term * 4294967296.0f));
             }
         }
-        cur += nb;
     }
     (void)TY;
 }
@@ -349,7 +356,7 @@ __device__ inline void reuse_window_tile(unsigned char *smem, const GBufView &g,
 
     const int x0 = tx * TX - R, y0 = ty * TY - R;
     const int tid = threadIdx.x;
-    if (tid == 0) *s_count = 0;
+    if (tid == 0) s_count[0] = s_count[1] = 0;
     for (int t = tid; t < TX * TY; t += kRBlock) s_B[t] = 0ull;
     __syncthreads();
 
