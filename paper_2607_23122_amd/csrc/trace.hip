@@ -364,8 +364,24 @@ __global__ __launch_bounds__(kBlock, 7) void validate_window_kernel(DeviceBVH bv
             wave_sync();
             for (int b = done; b < upto; ++b) {
                 const RunCand &c = wcand[wave][b];
-                const int64_t j = (int64_t)c.jy * g.w + c.jx;
-                for (int w = lane; w < words; w += 64) bits[j * words + w] = wbits[wave][b * words + w];
+                if constexpr (kEntry) {
+                    // the candidate's words as a wave-uniform base plus a
+                    // 32-bit lane offset; the empty asm keeps the compiler
+                    // from hoisting a per-lane 64-bit address out of the run
+                    // loop, which this form (the largest) had to spill at the
+                    // register bound: 8 bytes per lane stored once per wave,
+                    // 25 MB of writes per 1080p AO launch.  (The other forms
+                    // keep it in a register; given the same code, shadows
+                    // measured 4% slower.)
+                    const int jx = __builtin_amdgcn_readfirstlane(c.jx), jy = __builtin_amdgcn_readfirstlane(c.jy);
+                    uint32_t *dst = bits + ((int64_t)jy * g.w + jx) * words;
+                    int w0 = lane;
+                    asm volatile("" : "+v"(w0));
+                    for (int w = w0; w < words; w += 64) dst[w] = wbits[wave][b * words + w];
+                } else {
+                    const int64_t j = (int64_t)c.jy * g.w + c.jx;
+                    for (int w = lane; w < words; w += 64) bits[j * words + w] = wbits[wave][b * words + w];
+                }
             }
             done = upto;
             count = 0;
