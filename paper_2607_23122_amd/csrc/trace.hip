@@ -262,7 +262,7 @@ struct RunCand {
 
 // COUNT: the work-accounting instantiation (lane-masked walk, same bits),
 // which adds the segments' useful work to stats[0..4].  Bounded to 7 waves
-// per SIMD (72 registers; a few words spill in the AO and counting forms): at
+// per SIMD (72 registers; a few words spill in the counting forms): at
 // its natural register count (5 waves) the walk ran 12% slower.
 //
 // GROUP: the fixed groups of N pixels (2^lgw x 2^lgh, aligned to the image
