@@ -354,7 +354,10 @@ def test_multi_sample_mean(ocr, request, which, mode, est, size):
     assert st["compared"] > 0.99 * st["targets"]
 
 
-@pytest.mark.parametrize("W,H", [(1, 1), (3, 5), (37, 23), (64, 1)])
+# (333, 197): 21 x 13 tiles, so the runs of tiles dealt to the XCDs, the
+# compaction blocks' tile groups and the validation's run blocks all end in a
+# partial group
+@pytest.mark.parametrize("W,H", [(1, 1), (3, 5), (37, 23), (64, 1), (333, 197)])
 def test_small_and_ragged_frames(ocr, W, H):
     s = w.boxes_scene(1)
     gb = w.render_gbuffer(s, w.boxes_camera(W, H))
